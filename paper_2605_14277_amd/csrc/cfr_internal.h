@@ -1,0 +1,88 @@
+// Internal declarations shared by the host runtime (cfr_api.hip) and the
+// kernel launchers (cfr_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace cfr {
+
+// Per-iteration scalars kept in device memory, so that every kernel reads
+// the iteration index and its derived factors at run time and a captured
+// graph of one iteration can be replayed unchanged.
+struct Scalars {
+    double t;      // iterations completed (incremented first thing each iteration)
+    double w;      // averaging weight of the current iteration
+    double W;      // sum of weights so far
+    double dpos;   // DCFR factor for positive regrets, t^a/(t^a+1)
+    double dneg;   // DCFR factor for negative regrets, t^b/(t^b+1)
+    double pad[3];
+    double out[8]; // scalar results of the evaluation kernels
+};
+
+// Payoff matrix sorted along one player's sequences: CSR of A (player 1
+// rows) or CSR of A^T (player 2 rows), with the row-block partition the
+// product kernel walks.
+struct DevMatrix {
+    int32_t n_rows = 0;
+    int32_t n_cols = 0;
+    int64_t nnz = 0;
+    int32_t n_blk = 0;
+    const int32_t *ptr = nullptr;  // [n_rows+1]
+    const int32_t *idx = nullptr;  // [nnz]
+    const void *val = nullptr;     // [nnz] value type
+    const int32_t *blk = nullptr;  // [n_blk+1] first row of each block
+};
+
+// One player's treeplex in level order (see the runtime for the layout).
+struct DevPlayer {
+    int32_t n_seq = 0;
+    int32_t n_inf = 0;
+    int32_t n_levels = 0;
+    const int32_t *lvl_inf = nullptr;  // host array [n_levels+1]
+    const int32_t *lvl_seq = nullptr;  // host array [n_levels+1]
+    int32_t *inf_first = nullptr;      // [n_inf+1]
+    int32_t *seq_par = nullptr;        // [n_seq] parent sequence of each sequence's decision point
+    int32_t *seq_child = nullptr;      // [n_seq+1] child decision points of each sequence
+    void *r = nullptr;                 // [n_seq] accumulator type
+    void *m = nullptr;                 // [n_seq] accumulator type
+    void *s = nullptr;                 // [n_seq] accumulator type
+    void *b = nullptr;                 // [n_seq] value type
+    void *x = nullptr;                 // [n_seq] value type
+    void *g = nullptr;                 // [n_seq] value type
+    void *xbar = nullptr;              // [n_seq] value type
+    void *vinf = nullptr;              // [n_inf] compute type
+};
+
+// Kernel launchers (cfr_kernels.hip).  All enqueue on `st` and return the
+// launch status.
+hipError_t launch_begin(int prec, Scalars *sc, int variant, int avg_kind, double alpha,
+                        double beta, double gamma, hipStream_t st);
+hipError_t launch_uniform_b(int prec, const DevPlayer &p, hipStream_t st);
+hipError_t launch_spmv(int prec, const DevMatrix &A, const void *xin, void *yout,
+                       int xcd_remap, hipStream_t st);
+hipError_t launch_up_level(int prec, int variant, const DevPlayer &p, int level, double usign,
+                           const void *g, const Scalars *sc, hipStream_t st);
+hipError_t launch_down_level(int prec, const DevPlayer &p, int level, int average,
+                             const Scalars *sc, hipStream_t st);
+hipError_t launch_normalize(int prec, const DevPlayer &p, const Scalars *sc, hipStream_t st);
+hipError_t launch_br_level(int prec, const DevPlayer &p, int level, double usign,
+                           const void *g, hipStream_t st);
+hipError_t launch_root_value(int prec, const DevPlayer &p, double usign, const void *g,
+                             double *out, hipStream_t st);
+hipError_t launch_dot(int prec, int32_t n, const void *a, const void *b, double *partials,
+                      int n_partials, double *out, hipStream_t st);
+
+size_t value_bytes(int prec);
+size_t accum_bytes(int prec);
+size_t compute_bytes(int prec);
+
+constexpr int kSpmvThreads = 256;
+constexpr int kSpmvItems = 8;
+constexpr int kSpmvCap = kSpmvThreads * kSpmvItems;  // nonzeros staged per block
+constexpr int kSpmvRowCap = 2048;                    // rows per block
+constexpr int kDotPartials = 512;
+
+}  // namespace cfr

@@ -1,0 +1,562 @@
+// HIP kernels for one iteration of sequence-form CFR on gfx950.
+//
+// The path is sparse and bandwidth-bound (about 0.25 flop per byte), so
+// nothing here uses MFMA.  Kernels:
+//   k_spmv      payoff product over a row-sorted matrix (A y over the CSR,
+//               A^T x over the CSC): each 256-thread block owns a run of
+//               whole rows holding at most 2048 nonzeros, streams their
+//               index/value pairs with coalesced loads, gathers the input
+//               vector, stages the products in LDS, and sums every row in
+//               ascending column order.  A row longer than one block's
+//               capacity gets a block of its own and a tree reduction.
+//   k_up        one treeplex level of ObserveUtility (Algorithm 2, bottom-up
+//               part and regret update) fused with the variant's post-step
+//               and with regret matching for the next strategy: one thread
+//               per decision point.
+//   k_down      one treeplex level of NextStrategy's top-down pass, fused
+//               with the average-strategy accumulation of the strategy it
+//               overwrites: one thread per sequence.
+//   k_br        one level of the best-response max-sweep.
+//   k_begin / k_normalize / k_root / k_dot   per-iteration scalars, average
+//               normalisation and deterministic scalar reductions.
+// Precision modes select the value type (payoffs, strategies, utilities),
+// the accumulator type (regrets, predictions, averages) and the compute
+// type (in-register arithmetic).  No kernel uses atomics, so every result
+// is run-to-run reproducible.
+#include "cfr_internal.h"
+
+#include <cfloat>
+
+#include "cfr.h"
+
+namespace cfr {
+
+template <int P>
+struct Types;
+template <>
+struct Types<CFR_FP64> {
+    using V = double;
+    using R = double;
+    using C = double;
+};
+template <>
+struct Types<CFR_FP32> {
+    using V = float;
+    using R = float;
+    using C = float;
+};
+template <>
+struct Types<CFR_FP32_ACC64> {
+    using V = float;
+    using R = double;
+    using C = double;
+};
+
+size_t value_bytes(int prec) { return prec == CFR_FP64 ? 8 : 4; }
+size_t accum_bytes(int prec) { return prec == CFR_FP32 ? 4 : 8; }
+size_t compute_bytes(int prec) { return prec == CFR_FP32 ? 4 : 8; }
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kMaxActs = 8;  // decision points up to this size keep their actions in registers
+
+inline unsigned grid_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+
+// ---------------------------------------------------------------------------
+// Per-iteration scalars
+// ---------------------------------------------------------------------------
+
+__global__ void k_begin(Scalars *sc, int variant, int avg_kind, double alpha, double beta,
+                        double gamma)
+{
+    double t = sc->t + 1.0;
+    sc->t = t;
+    int kind = avg_kind;
+    if (kind == CFR_AVG_DEFAULT) {
+        kind = variant == CFR_PLUS        ? CFR_AVG_LINEAR
+               : variant == CFR_DCFR      ? CFR_AVG_POW_GAMMA
+               : variant == CFR_PCFR_PLUS ? CFR_AVG_QUADRATIC
+                                          : CFR_AVG_UNIFORM;
+    }
+    double w = 1.0;
+    if (kind == CFR_AVG_LINEAR) w = t;
+    else if (kind == CFR_AVG_QUADRATIC) w = t * t;
+    else if (kind == CFR_AVG_POW_GAMMA) w = pow(t, gamma);
+    sc->w = w;
+    sc->W = sc->W + w;
+    double ta = pow(t, alpha), tb = pow(t, beta);
+    sc->dpos = ta / (ta + 1.0);
+    sc->dneg = tb / (tb + 1.0);
+}
+
+// ---------------------------------------------------------------------------
+// Payoff product y = M x over a row-sorted matrix
+// ---------------------------------------------------------------------------
+
+template <int P>
+__global__ __launch_bounds__(kSpmvThreads) void k_spmv(
+    int32_t n_blk, const int32_t *__restrict__ blk, const int32_t *__restrict__ ptr,
+    const int32_t *__restrict__ idx, const typename Types<P>::V *__restrict__ val,
+    const typename Types<P>::V *__restrict__ xin, typename Types<P>::V *__restrict__ yout,
+    int xcd_remap)
+{
+    using V = typename Types<P>::V;
+    using C = typename Types<P>::C;
+    __shared__ C prod[kSpmvCap];
+
+    int32_t bid = (int32_t)blockIdx.x;
+    if (xcd_remap) {
+        // Workgroups are dealt round-robin over the 8 XCDs; give each XCD a
+        // contiguous range of row blocks so neighbouring rows (which gather
+        // neighbouring input entries) share one L2.
+        int32_t per = (n_blk + 7) / 8;
+        bid = (int32_t)(blockIdx.x % 8) * per + (int32_t)(blockIdx.x / 8);
+    }
+    if (bid >= n_blk) return;
+    const int tid = threadIdx.x;
+    const int32_t rb = blk[bid], re = blk[bid + 1];
+    const int32_t e0 = ptr[rb], e1 = ptr[re];
+    const int32_t n = e1 - e0;
+
+    if (n > kSpmvCap) {
+        // a single long row: strided partial sums, then a fixed-order tree
+        C acc = 0;
+        for (int32_t i = tid; i < n; i += kSpmvThreads)
+            acc = acc + (C)val[e0 + i] * (C)xin[idx[e0 + i]];
+        prod[tid] = acc;
+        __syncthreads();
+        for (int w = kSpmvThreads / 2; w > 0; w >>= 1) {
+            if (tid < w) prod[tid] = prod[tid] + prod[tid + w];
+            __syncthreads();
+        }
+        if (tid == 0) yout[rb] = (V)prod[0];
+        return;
+    }
+
+    int32_t c[kSpmvItems];
+    V v[kSpmvItems];
+#pragma unroll
+    for (int k = 0; k < kSpmvItems; ++k) {
+        int32_t i = k * kSpmvThreads + tid;
+        bool ok = i < n;
+        c[k] = ok ? __builtin_nontemporal_load(idx + e0 + i) : 0;
+        v[k] = ok ? __builtin_nontemporal_load(val + e0 + i) : (V)0;
+    }
+#pragma unroll
+    for (int k = 0; k < kSpmvItems; ++k) {
+        int32_t i = k * kSpmvThreads + tid;
+        if (i < n) prod[i] = (C)v[k] * (C)xin[c[k]];
+    }
+    __syncthreads();
+    for (int32_t r = rb + tid; r < re; r += kSpmvThreads) {
+        int32_t a = ptr[r] - e0, z = ptr[r + 1] - e0;
+        C acc = 0;
+        for (int32_t i = a; i < z; ++i) acc = acc + prod[i];
+        yout[r] = (V)acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// ObserveUtility for one level, fused with the variant and regret matching
+// ---------------------------------------------------------------------------
+
+template <int P, int VAR>
+__device__ __forceinline__ typename Types<P>::C post_step(typename Types<P>::C r,
+                                                          typename Types<P>::C dpos,
+                                                          typename Types<P>::C dneg)
+{
+    if (VAR == CFR_PLUS || VAR == CFR_PCFR_PLUS) return r > 0 ? r : 0;
+    if (VAR == CFR_DCFR) {
+        if (r > 0) return r * dpos;
+        if (r < 0) return r * dneg;
+    }
+    return r;
+}
+
+template <int P, int VAR>
+__global__ __launch_bounds__(kThreads) void k_up(
+    int32_t j0, int32_t j1, const int32_t *__restrict__ inf_first,
+    const int32_t *__restrict__ seq_child, const typename Types<P>::V *__restrict__ g,
+    typename Types<P>::C usign, typename Types<P>::C *__restrict__ vinf,
+    typename Types<P>::V *__restrict__ b, typename Types<P>::R *__restrict__ r,
+    typename Types<P>::R *__restrict__ m, const Scalars *__restrict__ sc)
+{
+    using V = typename Types<P>::V;
+    using R = typename Types<P>::R;
+    using C = typename Types<P>::C;
+    constexpr bool kPred = VAR == CFR_PCFR_PLUS || VAR == CFR_PCFR;
+    int32_t j = j0 + (int32_t)(blockIdx.x * kThreads + threadIdx.x);
+    if (j >= j1) return;
+    C dpos = 1, dneg = 1;
+    if (VAR == CFR_DCFR) {
+        dpos = (C)sc->dpos;
+        dneg = (C)sc->dneg;
+    }
+    const int32_t a0 = inf_first[j], a1 = inf_first[j + 1];
+    const int32_t n = a1 - a0;
+
+    auto cf_utility = [&](int32_t a) -> C {
+        C acc = usign * (C)g[a];
+        const int32_t c1 = seq_child[a + 1];
+        for (int32_t c = seq_child[a]; c < c1; ++c) acc = acc + vinf[c];
+        return acc;
+    };
+
+    if (n <= kMaxActs) {
+        C q[kMaxActs];
+        C V_ = 0;
+#pragma unroll
+        for (int k = 0; k < kMaxActs; ++k) {
+            if (k < n) {
+                q[k] = cf_utility(a0 + k);
+                V_ = V_ + (C)b[a0 + k] * q[k];
+            }
+        }
+        vinf[j] = V_;
+        C z[kMaxActs];
+        C Z = 0;
+#pragma unroll
+        for (int k = 0; k < kMaxActs; ++k) {
+            if (k < n) {
+                const int32_t a = a0 + k;
+                C inst = q[k] - V_;
+                C rr = post_step<P, VAR>((C)r[a] + inst, dpos, dneg);
+                r[a] = (R)rr;
+                C zz = (C)(R)rr;
+                if (kPred) {
+                    m[a] = (R)inst;
+                    zz = zz + (C)(R)inst;
+                }
+                zz = zz > 0 ? zz : 0;
+                z[k] = zz;
+                Z = Z + zz;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kMaxActs; ++k) {
+            if (k < n) b[a0 + k] = (V)(Z > 0 ? z[k] / Z : (C)1 / (C)n);
+        }
+        return;
+    }
+
+    // large decision points: recompute instead of holding every action
+    C V_ = 0;
+    for (int32_t a = a0; a < a1; ++a) V_ = V_ + (C)b[a] * cf_utility(a);
+    vinf[j] = V_;
+    C Z = 0;
+    for (int32_t a = a0; a < a1; ++a) {
+        C inst = cf_utility(a) - V_;
+        C rr = post_step<P, VAR>((C)r[a] + inst, dpos, dneg);
+        r[a] = (R)rr;
+        C zz = (C)(R)rr;
+        if (kPred) {
+            m[a] = (R)inst;
+            zz = zz + (C)(R)inst;
+        }
+        Z = Z + (zz > 0 ? zz : 0);
+    }
+    for (int32_t a = a0; a < a1; ++a) {
+        C zz = (C)r[a];
+        if (kPred) zz = zz + (C)m[a];
+        zz = zz > 0 ? zz : 0;
+        b[a] = (V)(Z > 0 ? zz / Z : (C)1 / (C)n);
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(kThreads) void k_uniform_b(int32_t n_inf,
+                                                        const int32_t *__restrict__ inf_first,
+                                                        typename Types<P>::V *__restrict__ b)
+{
+    using V = typename Types<P>::V;
+    using C = typename Types<P>::C;
+    int32_t j = (int32_t)(blockIdx.x * kThreads + threadIdx.x);
+    if (j >= n_inf) return;
+    const int32_t a0 = inf_first[j], a1 = inf_first[j + 1];
+    for (int32_t a = a0; a < a1; ++a) b[a] = (V)((C)1 / (C)(a1 - a0));
+}
+
+// ---------------------------------------------------------------------------
+// NextStrategy top-down pass for one level, fused with averaging
+// ---------------------------------------------------------------------------
+
+template <int P>
+__global__ __launch_bounds__(kThreads) void k_down(
+    int32_t s0, int32_t s1, const int32_t *__restrict__ seq_par,
+    const typename Types<P>::V *__restrict__ b, typename Types<P>::V *__restrict__ x,
+    typename Types<P>::R *__restrict__ s, const Scalars *__restrict__ sc, int average)
+{
+    using R = typename Types<P>::R;
+    int32_t i = s0 + (int32_t)(blockIdx.x * kThreads + threadIdx.x);
+    if (i >= s1) return;
+    if (average) {
+        R w = (R)sc->w;
+        s[i] = s[i] + w * (R)x[i];
+    }
+    x[i] = x[seq_par[i]] * b[i];
+}
+
+// ---------------------------------------------------------------------------
+// Evaluation: average normalisation, best-response sweep, reductions
+// ---------------------------------------------------------------------------
+
+template <int P>
+__global__ __launch_bounds__(kThreads) void k_normalize(int32_t n, const typename Types<P>::R *s,
+                                                        const Scalars *__restrict__ sc,
+                                                        typename Types<P>::V *__restrict__ xbar)
+{
+    using V = typename Types<P>::V;
+    int32_t i = (int32_t)(blockIdx.x * kThreads + threadIdx.x);
+    if (i >= n) return;
+    double W = sc->W;
+    xbar[i] = i == 0 ? (V)1 : (V)((double)s[i] / W);
+}
+
+template <int P>
+__global__ __launch_bounds__(kThreads) void k_br(int32_t j0, int32_t j1,
+                                                 const int32_t *__restrict__ inf_first,
+                                                 const int32_t *__restrict__ seq_child,
+                                                 const typename Types<P>::V *__restrict__ g,
+                                                 typename Types<P>::C usign,
+                                                 typename Types<P>::C *__restrict__ vmax)
+{
+    using C = typename Types<P>::C;
+    int32_t j = j0 + (int32_t)(blockIdx.x * kThreads + threadIdx.x);
+    if (j >= j1) return;
+    const int32_t a0 = inf_first[j], a1 = inf_first[j + 1];
+    C best = 0;
+    for (int32_t a = a0; a < a1; ++a) {
+        C acc = usign * (C)g[a];
+        for (int32_t c = seq_child[a]; c < seq_child[a + 1]; ++c) acc = acc + vmax[c];
+        if (a == a0 || acc > best) best = acc;
+    }
+    vmax[j] = best;
+}
+
+// value at the empty sequence: own utility there plus the values of the
+// decision points directly below it, summed in ascending order
+template <int P>
+__global__ void k_root(int32_t n_root, const typename Types<P>::V *__restrict__ g,
+                       typename Types<P>::C usign, const typename Types<P>::C *__restrict__ v,
+                       double *out)
+{
+    using C = typename Types<P>::C;
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double acc = (double)(usign * (C)g[0]);
+    for (int32_t j = 0; j < n_root; ++j) acc = acc + (double)v[j];
+    *out = acc;
+}
+
+// deterministic two-stage dot product in double
+template <int P>
+__global__ __launch_bounds__(kThreads) void k_dot_partial(int32_t n,
+                                                          const typename Types<P>::V *__restrict__ a,
+                                                          const typename Types<P>::V *__restrict__ b,
+                                                          double *partials)
+{
+    __shared__ double red[kThreads];
+    double acc = 0;
+    for (int32_t i = (int32_t)(blockIdx.x * kThreads + threadIdx.x); i < n;
+         i += (int32_t)(gridDim.x * kThreads))
+        acc = acc + (double)a[i] * (double)b[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(kThreads) void k_dot_final(int n_partials, const double *partials,
+                                                        double *out)
+{
+    __shared__ double red[kThreads];
+    double acc = 0;
+    for (int i = threadIdx.x; i < n_partials; i += kThreads) acc = acc + partials[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// Launch helpers
+// ---------------------------------------------------------------------------
+
+template <int P>
+hipError_t spmv_t(const DevMatrix &A, const void *xin, void *yout, int xcd_remap, hipStream_t st)
+{
+    using V = typename Types<P>::V;
+    if (A.n_blk == 0) return hipSuccess;
+    unsigned grid = xcd_remap ? (unsigned)(((A.n_blk + 7) / 8) * 8) : (unsigned)A.n_blk;
+    hipLaunchKernelGGL((k_spmv<P>), dim3(grid), dim3(kSpmvThreads), 0, st, A.n_blk, A.blk, A.ptr,
+                       A.idx, (const V *)A.val, (const V *)xin, (V *)yout, xcd_remap);
+    return hipGetLastError();
+}
+
+template <int P, int VAR>
+hipError_t up_t(const DevPlayer &p, int level, double usign, const void *g, const Scalars *sc,
+                hipStream_t st)
+{
+    using T = Types<P>;
+    int32_t j0 = p.lvl_inf[level], j1 = p.lvl_inf[level + 1];
+    if (j1 <= j0) return hipSuccess;
+    hipLaunchKernelGGL((k_up<P, VAR>), dim3(grid_for(j1 - j0)), dim3(kThreads), 0, st, j0, j1,
+                       p.inf_first, p.seq_child, (const typename T::V *)g,
+                       (typename T::C)usign, (typename T::C *)p.vinf, (typename T::V *)p.b,
+                       (typename T::R *)p.r, (typename T::R *)p.m, sc);
+    return hipGetLastError();
+}
+
+template <int P>
+hipError_t up_dispatch(int variant, const DevPlayer &p, int level, double usign, const void *g,
+                       const Scalars *sc, hipStream_t st)
+{
+    switch (variant) {
+    case CFR_VANILLA: return up_t<P, CFR_VANILLA>(p, level, usign, g, sc, st);
+    case CFR_PLUS: return up_t<P, CFR_PLUS>(p, level, usign, g, sc, st);
+    case CFR_DCFR: return up_t<P, CFR_DCFR>(p, level, usign, g, sc, st);
+    case CFR_PCFR_PLUS: return up_t<P, CFR_PCFR_PLUS>(p, level, usign, g, sc, st);
+    case CFR_PCFR: return up_t<P, CFR_PCFR>(p, level, usign, g, sc, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int P>
+hipError_t down_t(const DevPlayer &p, int level, int average, const Scalars *sc, hipStream_t st)
+{
+    using T = Types<P>;
+    int32_t s0 = p.lvl_seq[level], s1 = p.lvl_seq[level + 1];
+    if (s1 <= s0) return hipSuccess;
+    hipLaunchKernelGGL((k_down<P>), dim3(grid_for(s1 - s0)), dim3(kThreads), 0, st, s0, s1,
+                       p.seq_par, (const typename T::V *)p.b, (typename T::V *)p.x,
+                       (typename T::R *)p.s, sc, average);
+    return hipGetLastError();
+}
+
+template <int P>
+hipError_t uniform_t(const DevPlayer &p, hipStream_t st)
+{
+    using T = Types<P>;
+    if (p.n_inf == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_uniform_b<P>), dim3(grid_for(p.n_inf)), dim3(kThreads), 0, st, p.n_inf,
+                       p.inf_first, (typename T::V *)p.b);
+    return hipGetLastError();
+}
+
+template <int P>
+hipError_t normalize_t(const DevPlayer &p, const Scalars *sc, hipStream_t st)
+{
+    using T = Types<P>;
+    hipLaunchKernelGGL((k_normalize<P>), dim3(grid_for(p.n_seq)), dim3(kThreads), 0, st, p.n_seq,
+                       (const typename T::R *)p.s, sc, (typename T::V *)p.xbar);
+    return hipGetLastError();
+}
+
+template <int P>
+hipError_t br_t(const DevPlayer &p, int level, double usign, const void *g, hipStream_t st)
+{
+    using T = Types<P>;
+    int32_t j0 = p.lvl_inf[level], j1 = p.lvl_inf[level + 1];
+    if (j1 <= j0) return hipSuccess;
+    hipLaunchKernelGGL((k_br<P>), dim3(grid_for(j1 - j0)), dim3(kThreads), 0, st, j0, j1,
+                       p.inf_first, p.seq_child, (const typename T::V *)g, (typename T::C)usign,
+                       (typename T::C *)p.vinf);
+    return hipGetLastError();
+}
+
+template <int P>
+hipError_t root_t(const DevPlayer &p, double usign, const void *g, double *out, hipStream_t st)
+{
+    using T = Types<P>;
+    int32_t n_root = p.n_levels > 0 ? p.lvl_inf[1] - p.lvl_inf[0] : 0;
+    hipLaunchKernelGGL((k_root<P>), dim3(1), dim3(64), 0, st, n_root,
+                       (const typename T::V *)g, (typename T::C)usign,
+                       (const typename T::C *)p.vinf, out);
+    return hipGetLastError();
+}
+
+template <int P>
+hipError_t dot_t(int32_t n, const void *a, const void *b, double *partials, int n_partials,
+                 double *out, hipStream_t st)
+{
+    using T = Types<P>;
+    int blocks = (int)grid_for(n);
+    if (blocks > n_partials) blocks = n_partials;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL((k_dot_partial<P>), dim3(blocks), dim3(kThreads), 0, st, n,
+                       (const typename T::V *)a, (const typename T::V *)b, partials);
+    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(kThreads), 0, st, blocks, partials, out);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+#define CFR_DISPATCH(prec, call)                                   \
+    switch (prec) {                                                \
+    case CFR_FP64: { constexpr int P = CFR_FP64; return call; }    \
+    case CFR_FP32: { constexpr int P = CFR_FP32; return call; }    \
+    case CFR_FP32_ACC64: { constexpr int P = CFR_FP32_ACC64; return call; } \
+    default: return hipErrorInvalidValue;                          \
+    }
+
+hipError_t launch_begin(int prec, Scalars *sc, int variant, int avg_kind, double alpha,
+                        double beta, double gamma, hipStream_t st)
+{
+    (void)prec;
+    hipLaunchKernelGGL(k_begin, dim3(1), dim3(1), 0, st, sc, variant, avg_kind, alpha, beta, gamma);
+    return hipGetLastError();
+}
+
+hipError_t launch_uniform_b(int prec, const DevPlayer &p, hipStream_t st)
+{
+    CFR_DISPATCH(prec, uniform_t<P>(p, st));
+}
+
+hipError_t launch_spmv(int prec, const DevMatrix &A, const void *xin, void *yout, int xcd_remap,
+                       hipStream_t st)
+{
+    CFR_DISPATCH(prec, spmv_t<P>(A, xin, yout, xcd_remap, st));
+}
+
+hipError_t launch_up_level(int prec, int variant, const DevPlayer &p, int level, double usign,
+                           const void *g, const Scalars *sc, hipStream_t st)
+{
+    CFR_DISPATCH(prec, up_dispatch<P>(variant, p, level, usign, g, sc, st));
+}
+
+hipError_t launch_down_level(int prec, const DevPlayer &p, int level, int average,
+                             const Scalars *sc, hipStream_t st)
+{
+    CFR_DISPATCH(prec, down_t<P>(p, level, average, sc, st));
+}
+
+hipError_t launch_normalize(int prec, const DevPlayer &p, const Scalars *sc, hipStream_t st)
+{
+    CFR_DISPATCH(prec, normalize_t<P>(p, sc, st));
+}
+
+hipError_t launch_br_level(int prec, const DevPlayer &p, int level, double usign, const void *g,
+                           hipStream_t st)
+{
+    CFR_DISPATCH(prec, br_t<P>(p, level, usign, g, st));
+}
+
+hipError_t launch_root_value(int prec, const DevPlayer &p, double usign, const void *g,
+                             double *out, hipStream_t st)
+{
+    CFR_DISPATCH(prec, root_t<P>(p, usign, g, out, st));
+}
+
+hipError_t launch_dot(int prec, int32_t n, const void *a, const void *b, double *partials,
+                      int n_partials, double *out, hipStream_t st)
+{
+    CFR_DISPATCH(prec, dot_t<P>(n, a, b, partials, n_partials, out, st));
+}
+
+}  // namespace cfr

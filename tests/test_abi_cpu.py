@@ -1,0 +1,170 @@
+"""The C-ABI library on the CPU: it loads, exports every declared symbol,
+and its host-only entry points (validation, workspace sizing) behave as the
+header states.  No kernel runs here."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import gamegen as gg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cfr.h")
+
+
+@pytest.fixture(scope="module")
+def cfr():
+    import paper_2605_14277_amd as m
+    return m
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cfr_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(cfr):
+    lib = C.CDLL(cfr.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_options_default(cfr):
+    o = cfr.cfr_options_default()
+    assert o.precision == 0 and o.dcfr_alpha == 1.5 and o.dcfr_beta == 0.0
+    assert o.dcfr_gamma == 2.0 and o.use_graph == 1 and not o.workspace
+
+
+@pytest.mark.parametrize("name", ["cfg1", "stops", "perfect"])
+def test_valid_games_validate(cfr, games, name):
+    ga = cfr.GameArrays(games[name])
+    assert cfr.cfr_validate(ga) == cfr.CFR_OK
+    ga2 = cfr.GameArrays(games[name], with_csc=False)
+    assert cfr.cfr_validate(ga2) == cfr.CFR_OK
+
+
+def _corrupt(game, what):
+    import copy
+    g = copy.deepcopy(game)
+    if what == "no_action":
+        f = g.inf_first_seq[0].copy()
+        f[1] = f[0]
+        g.inf_first_seq[0] = f
+    elif what == "parent_after":
+        p = g.inf_parent[0].copy()
+        p[-1] = g.n_seq[0] - 1
+        g.inf_parent[0] = p
+    elif what == "parent_negative":
+        p = g.inf_parent[1].copy()
+        p[0] = -1
+        g.inf_parent[1] = p
+    elif what == "offsets_short":
+        f = g.inf_first_seq[1].copy()
+        f[-1] -= 1
+        g.inf_first_seq[1] = f
+    elif what == "row_ptr_end":
+        r = g.row_ptr.copy()
+        r[-1] += 1
+        g.row_ptr = r
+    elif what == "col_range":
+        c = g.col_idx.copy()
+        c[3] = g.n_seq[1]
+        g.col_idx = c
+    elif what == "col_unsorted":
+        c = g.col_idx.copy()
+        i = int(np.argmax(np.diff(g.row_ptr) >= 2))
+        a = g.row_ptr[i]
+        c[a], c[a + 1] = c[a + 1], c[a]
+        g.col_idx = c
+    elif what == "nan":
+        v = g.val.copy()
+        v[5] = np.nan
+        g.val = v
+    elif what == "csc_mismatch":
+        v = g.val_csc.copy()
+        v[0] += 1e-12
+        g.val_csc = v
+    elif what == "row_ptr_decreasing":
+        r = g.row_ptr.copy()
+        i = int(np.argmax(np.diff(r) >= 1)) + 1
+        r[i] -= 1
+        r[i + 1] = r[i] - 1 if i + 1 < r.size - 1 else r[i + 1]
+        g.row_ptr = r
+    return g
+
+
+@pytest.mark.parametrize("what", ["no_action", "parent_after", "parent_negative", "offsets_short",
+                                  "row_ptr_end", "col_range", "col_unsorted", "nan",
+                                  "csc_mismatch", "row_ptr_decreasing"])
+def test_malformed_games_rejected(cfr, games, what):
+    g = _corrupt(games["cfg1"], what)
+    rc = cfr.cfr_validate(cfr.GameArrays(g))
+    assert rc == cfr.CFR_EINVAL, what
+    assert cfr.cfr_last_error() != ""
+
+
+def test_bad_options_rejected(cfr, games):
+    ga = cfr.GameArrays(games["cfg1"])
+    o = cfr.cfr_options_default()
+    o.precision = 7
+    with pytest.raises(cfr.CfrError) as ei:
+        cfr.cfr_workspace_size(ga, o)
+    assert ei.value.code == cfr.CFR_EINVAL
+    o = cfr.cfr_options_default()
+    o.dcfr_alpha = float("inf")
+    with pytest.raises(cfr.CfrError):
+        cfr.cfr_workspace_size(ga, o)
+
+
+def test_workspace_linear_in_game_size(cfr):
+    """Space is linear in the treeplex sizes plus nnz (Theorem 2): bytes per
+    (sequence + nonzero) stay within a constant band across sizes."""
+    ratios = {}
+    for prec in ("fp64", "fp32", "fp32_acc64"):
+        o = cfr.cfr_options_default()
+        o.precision = cfr.PRECISIONS[prec]
+        rs = []
+        for g in (gg.cfg1(), gg.cfg2_literal(),
+                  gg.public_game(9, S=8, max_depth=8, branch_lo=2, branch_hi=3, p_stop=0.1)):
+            n = cfr.cfr_workspace_size(cfr.GameArrays(g), o)
+            units = g.n_seq[0] + g.n_seq[1] + g.nnz
+            rs.append(n / units)
+        ratios[prec] = rs
+        # 48 bytes per sequence of state at most, 2*(4+8) per nonzero, plus alignment
+        assert max(rs[1:]) < 80
+    assert ratios["fp32"][-1] < ratios["fp64"][-1]
+
+
+def test_workspace_independent_of_numbering(cfr, games):
+    from helpers import dfs_renumber
+    g = games["stops"]
+    h = dfs_renumber(g)
+    o = cfr.cfr_options_default()
+    assert cfr.cfr_validate(cfr.GameArrays(h)) == cfr.CFR_OK
+    a = cfr.cfr_workspace_size(cfr.GameArrays(g), o)
+    b = cfr.cfr_workspace_size(cfr.GameArrays(h), o)
+    assert abs(a - b) <= 4096
+
+
+def test_create_without_device_fails_cleanly(cfr, games):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    ga = cfr.GameArrays(games["cfg1"])
+    o = cfr.cfr_options_default()
+    with pytest.raises(cfr.CfrError) as ei:
+        cfr.cfr_create(ga, o)
+    assert ei.value.code == cfr.CFR_EDEVICE
+
+
+def test_null_solver_calls(cfr):
+    lib = C.CDLL(cfr.LIB_PATH)
+    lib.cfr_step.argtypes = [C.c_void_p, C.c_int64, C.c_int, C.c_int]
+    assert lib.cfr_step(None, 1, 0, 0) == cfr.CFR_EINVAL
+    lib.cfr_destroy.argtypes = [C.c_void_p]
+    assert lib.cfr_destroy(None) == cfr.CFR_OK
