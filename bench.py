@@ -94,6 +94,7 @@ def main():
     ap.add_argument("--mode", default=None)
     ap.add_argument("--precision", default=None)
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--spmv-order", default="default", choices=["default", "sequential", "parallel"])
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle time for the CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -122,7 +123,8 @@ def main():
     log(f"[bench] game {args.config}: {g.summary()} built in {time.perf_counter() - t0:.1f}s")
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
-    s = cfr.Solver(g, precision=precision, device=0, use_graph=not args.no_graph)
+    s = cfr.Solver(g, precision=precision, device=0, use_graph=not args.no_graph,
+                   spmv_order=args.spmv_order)
     torch.cuda.synchronize()
     log(f"[bench] cfr_create {time.perf_counter() - t0:.1f}s, workspace {s.workspace_bytes / 1e9:.2f} GB")
 

@@ -25,9 +25,10 @@ acted).  Exact zeros are not stored.
 
 Sequence numbering (both players): sequence 0 is the empty sequence; then
 decision levels in order (level = number of own earlier decisions); inside a
-level, signal-major, then public nodes in breadth-first order, then actions.
+level, public nodes in breadth-first order, then signals, then actions.
 This order is topological (every infoset's parent sequence precedes its own
-sequences) and keeps the child infosets of any sequence contiguous.
+sequences), and the columns of any payoff row (the opponent's sequences at
+one public node, over all opponent signals) are one short contiguous run.
 
 Random draws (numpy PCG64, one Generator per game): the public tree level by
 level in breadth-first order (branching of every internal node of the level,
@@ -228,22 +229,30 @@ def _utility(kind, payoff, z, s1, s2):
 class _Plex:
     n_seq: int
     n_inf: int
+    S: int
     inf_parent: np.ndarray
     inf_first_seq: np.ndarray
     level_base: np.ndarray   # first sequence index of each level (int64)
-    level_K: np.ndarray      # sequences per signal block of each level
+    level_nodes: list        # decision nodes of each level, breadth-first
     node_level: np.ndarray   # per public node: level if a decision node of p, else -1
-    node_pos: np.ndarray     # per public node: offset inside its signal block
+    node_pos: np.ndarray     # per public node: actions of earlier nodes of its level
+    node_k: np.ndarray       # per public node: number of actions
     seq_node: np.ndarray
     seq_signal: np.ndarray
     seq_action: np.ndarray
 
 
 def _treeplex(tree: PublicTree, p: int, S: int) -> _Plex:
+    """Player p's treeplex.  Inside a level the decision points are ordered
+    node-major, signal-minor: sequence (n, s, a) of a level is
+    level_base + S*pos(n) + s*k(n) + a.  Nodes that follow each other in the
+    public tree are then neighbours for every signal, which keeps the
+    columns of any payoff row (and the rows of any column) close together."""
     internal = tree.n_child > 0
     owned = internal & ((tree.depth & 1) == p)
     node_level = np.full(tree.n_nodes, -1, np.int64)
     node_pos = np.full(tree.n_nodes, -1, np.int64)
+    node_k = tree.n_child.astype(np.int64)
     levels = []
     max_depth = int(tree.depth.max()) if tree.n_nodes else 0
     for d in range(p, max_depth + 1, 2):
@@ -251,41 +260,37 @@ def _treeplex(tree: PublicTree, p: int, S: int) -> _Plex:
         if ids.size == 0:
             break
         levels.append(ids)
-    n_levels = len(levels)
-    level_K = np.zeros(n_levels, np.int64)
-    level_base = np.zeros(n_levels, np.int64)
+    level_base = np.zeros(len(levels), np.int64)
     inf_parent_parts, inf_first_parts = [], []
     seq_node_parts, seq_sig_parts, seq_act_parts = [], [], []
     base = 1
     for lv, ids in enumerate(levels):
-        k = tree.n_child[ids].astype(np.int64)
+        k = node_k[ids]
         K = int(k.sum())
         pos = np.cumsum(k) - k
         node_level[ids] = lv
         node_pos[ids] = pos
-        level_K[lv] = K
         level_base[lv] = base
-        s = np.repeat(np.arange(S, dtype=np.int64), ids.size)
-        idx = np.tile(np.arange(ids.size, dtype=np.int64), S)
-        first = base + s * K + pos[idx]
+        idx = np.repeat(np.arange(ids.size, dtype=np.int64), S)
+        s = np.tile(np.arange(S, dtype=np.int64), ids.size)
+        first = base + S * pos[idx] + s * k[idx]
         if lv == 0:
             par = np.zeros(ids.size * S, np.int64)
         else:
-            pnode = tree.parent[ids]                  # opponent node
-            g = tree.parent[pnode]                    # own previous node
-            ag = tree.action[pnode]                   # own action at g
-            glv = node_level[g]
-            assert np.all(glv == lv - 1)
-            par_sig0 = level_base[lv - 1] + node_pos[g] + ag   # for signal 0
-            par = par_sig0[idx] + s * level_K[lv - 1]
+            pnode = tree.parent[ids].astype(np.int64)     # opponent node
+            g = tree.parent[pnode].astype(np.int64)       # own previous node
+            ag = tree.action[pnode].astype(np.int64)      # own action at g
+            assert np.all(node_level[g] == lv - 1)
+            par = level_base[lv - 1] + S * node_pos[g][idx] + s * node_k[g][idx] + ag[idx]
         inf_parent_parts.append(par)
         inf_first_parts.append(first)
-        # sequence descriptors (node, signal, action) in sequence order
-        nodes_rep = np.repeat(ids, k)
-        acts = np.arange(K, dtype=np.int64) - np.repeat(pos, k)
-        seq_node_parts.append(np.tile(nodes_rep, S))
-        seq_sig_parts.append(np.repeat(np.arange(S, dtype=np.int64), K))
-        seq_act_parts.append(np.tile(acts, S))
+        cnt = S * k
+        block0 = np.repeat(np.cumsum(cnt) - cnt, cnt)
+        local = np.arange(S * K, dtype=np.int64) - block0
+        kk = np.repeat(k, cnt)
+        seq_node_parts.append(np.repeat(ids, cnt))
+        seq_sig_parts.append(local // kk)
+        seq_act_parts.append(local % kk)
         base += S * K
     n_seq = base
     if inf_first_parts:
@@ -298,40 +303,48 @@ def _treeplex(tree: PublicTree, p: int, S: int) -> _Plex:
         inf_first = np.array([n_seq])
         inf_parent = np.zeros(0, np.int64)
         seq_node = seq_signal = seq_action = np.array([-1])
-    return _Plex(n_seq, inf_parent.shape[0], inf_parent.astype(np.int32),
-                 inf_first.astype(np.int32), level_base, level_K, node_level,
-                 node_pos, seq_node.astype(np.int32), seq_signal.astype(np.int32),
+    return _Plex(n_seq, inf_parent.shape[0], S, inf_parent.astype(np.int32),
+                 inf_first.astype(np.int32), level_base, levels, node_level, node_pos,
+                 node_k, seq_node.astype(np.int32), seq_signal.astype(np.int32),
                  seq_action.astype(np.int32))
 
 
 def _last_slots(tree: PublicTree, plex: _Plex, p: int):
-    """For every terminal: level and in-block offset of player p's last
-    sequence (level -1 when player p never acts on the path)."""
+    """For every terminal: the level, node and action of player p's last
+    sequence on its path (level -1 when player p never acts)."""
     z = tree.terminals.astype(np.int64)
     par = tree.parent[z].astype(np.int64)
     lvl = np.full(z.size, -1, np.int64)
-    off = np.full(z.size, -1, np.int64)
+    node = np.full(z.size, -1, np.int64)
+    act = np.full(z.size, -1, np.int64)
     own_is_parent = (tree.depth[par] & 1) == p
-    # case 1: parent of z is p's node -> (parent, action(z))
+    # the parent of z is p's node: (parent, action(z))
     m = own_is_parent
     lvl[m] = plex.node_level[par[m]]
-    off[m] = plex.node_pos[par[m]] + tree.action[z[m]]
-    # case 2: grandparent is p's node -> (grandparent, action(parent))
+    node[m] = par[m]
+    act[m] = tree.action[z[m]]
+    # else the grandparent is p's node: (grandparent, action(parent))
     m2 = ~own_is_parent & (tree.depth[par] >= 1)
     gp = tree.parent[par[m2]].astype(np.int64)
     lvl[m2] = plex.node_level[gp]
-    off[m2] = plex.node_pos[gp] + tree.action[par[m2]]
-    return lvl, off
+    node[m2] = gp
+    act[m2] = tree.action[par[m2]]
+    return lvl, node, act
 
 
-def _seq_index(plex: _Plex, lvl, off, s):
-    """Sequence index of (level, offset, signal); 0 where lvl < 0."""
+def _seq_index(plex: _Plex, lvl, node, act, s):
+    """Sequence index of (level, node, action, signal); 0 where lvl < 0."""
     lvl = np.asarray(lvl)
-    if plex.level_K.shape[0] == 0:          # the player never acts
+    if plex.level_base.shape[0] == 0:          # the player never acts
         return np.zeros(lvl.shape, np.int64)
     safe = np.where(lvl < 0, 0, lvl)
-    idx = plex.level_base[safe] + np.asarray(s, np.int64) * plex.level_K[safe] + off
+    nd = np.where(lvl < 0, 0, node)
+    idx = (plex.level_base[safe] + plex.S * plex.node_pos[nd] +
+           np.asarray(s, np.int64) * plex.node_k[nd] + act)
     return np.where(lvl < 0, 0, idx)
+
+
+_CHUNK = 1 << 23   # payoff entries expanded at once
 
 
 def _sorted_matrix(major: int, plex: list, slots: list, S: tuple,
@@ -339,14 +352,19 @@ def _sorted_matrix(major: int, plex: list, slots: list, S: tuple,
     """Payoff matrix sorted along the ``major`` player's sequences (major=0
     gives the CSR of A, major=1 the CSR of A^T, i.e. the CSC of A).
 
+    Every row is a sequence (n, s, a) of the major player; its entries come
+    from the terminals whose major-player last sequence is (n, a), one per
+    minor signal (or one entry summed over the minor signals when the minor
+    player never acts on the path).  The pattern of a slot (n, a) does not
+    depend on s, so it is built once and expanded for every signal.
+
     Returns (ptr int64[n_major+1], idx int32[nnz], val float64[nnz]).
     """
     mn = 1 - major
     PM, Pm = plex[major], plex[mn]
     SM, Sm = S[major], S[mn]
-    lvM, offM = slots[major]
-    lvm, offm = slots[mn]
-    T = lvM.shape[0]
+    lvM, ndM, acM = slots[major]
+    lvm, ndm, acm = slots[mn]
 
     def u_of(z, sM, sm):
         if major == 0:
@@ -363,23 +381,21 @@ def _sorted_matrix(major: int, plex: list, slots: list, S: tuple,
         s1 = np.arange(S[0], dtype=np.int64)
         return (chance * ufun(z[:, None], s1[None, :], s2[:, None])).sum(axis=1)
 
+    def summed(z, sM):
+        return pair_sum(z, sM) if major == 0 else pair_sum_p1(z, sM)
+
     chunks_idx, chunks_val, row_len = [], [], []
 
     # --- row 0 (major player's empty sequence): terminals where the major
     # player never acts; value summed over the major player's signal.
     zs = np.nonzero(lvM < 0)[0]
     if zs.size:
-        # entries (col(z, s_m)) for every s_m, or col 0 if minor also never acts
         zz = np.repeat(zs, Sm)
         sm = np.tile(np.arange(Sm, dtype=np.int64), zs.size)
-        cols = _seq_index(Pm, lvm[zz], offm[zz], sm)
-        if major == 0:
-            vals = pair_sum_p1(zz, sm)
-        else:
-            vals = pair_sum(zz, sm)
+        cols = _seq_index(Pm, lvm[zz], ndm[zz], acm[zz], sm)
+        vals = pair_sum_p1(zz, sm) if major == 0 else pair_sum(zz, sm)
         order = np.lexsort((zz, cols))
         cols, vals = cols[order], vals[order]
-        # merge duplicate columns
         uc, inv = np.unique(cols, return_inverse=True)
         acc = np.zeros(uc.size)
         np.add.at(acc, inv, vals)
@@ -389,44 +405,65 @@ def _sorted_matrix(major: int, plex: list, slots: list, S: tuple,
     else:
         row_len.append(np.array([0]))
 
-    for lv in range(PM.level_K.shape[0]):
-        K = int(PM.level_K[lv])
+    for lv, nodes in enumerate(PM.level_nodes):
+        k = PM.node_k[nodes]
+        K = int(k.sum())
         zl = np.nonzero(lvM == lv)[0]
-        # pattern entries per terminal: every minor signal, or one summed entry
         minor_none = lvm[zl] < 0
         z_full = zl[~minor_none]
         z_sum = zl[minor_none]
         pz = np.concatenate([np.repeat(z_full, Sm), z_sum])
         ps = np.concatenate([np.tile(np.arange(Sm, dtype=np.int64), z_full.size),
                              np.full(z_sum.size, -1, np.int64)])
-        pslot = offM[pz]
-        pcol = np.where(ps < 0, 0, _seq_index(Pm, lvm[pz], offm[pz], np.maximum(ps, 0)))
+        pslot = PM.node_pos[ndM[pz]] + acM[pz]
+        pcol = np.where(ps < 0, 0, _seq_index(Pm, lvm[pz], ndm[pz], acm[pz], np.maximum(ps, 0)))
         order = np.lexsort((pcol, pslot))
         pz, ps, pslot, pcol = pz[order], ps[order], pslot[order], pcol[order]
-        # within one slot, duplicate columns cannot occur for these trees
         if pz.size > 1:
             dup = (pslot[1:] == pslot[:-1]) & (pcol[1:] == pcol[:-1])
             if dup.any():
                 raise AssertionError("duplicate payoff entry in one row")
-        summed = ps < 0
-        for sM in range(SM):
-            vals = np.empty(pz.size)
-            f = ~summed
-            sMv = np.full(int(f.sum()), sM, np.int64)
-            vals[f] = u_of(pz[f], sMv, ps[f])
-            if summed.any():
-                if major == 0:
-                    vals[summed] = pair_sum(pz[summed], np.full(int(summed.sum()), sM, np.int64))
-                else:
-                    vals[summed] = pair_sum_p1(pz[summed], np.full(int(summed.sum()), sM, np.int64))
+        pat_len = np.bincount(pslot, minlength=K)[:K].astype(np.int64)
+        pat_ptr = np.zeros(K + 1, np.int64)
+        np.cumsum(pat_len, out=pat_ptr[1:])
+        # rows of this level in order: node-major, then signal, then action
+        cnt = SM * k
+        n_rows = int(cnt.sum())
+        block0 = np.repeat(np.cumsum(cnt) - cnt, cnt)
+        local = np.arange(n_rows, dtype=np.int64) - block0
+        kk = np.repeat(k, cnt)
+        row_sig = local // kk
+        row_slot = np.repeat(PM.node_pos[nodes], cnt) + local % kk
+        lens = pat_len[row_slot]
+        r0 = 0
+        while r0 < n_rows:
+            # rows [r0, r1) holding about _CHUNK entries
+            csum = np.cumsum(lens[r0:])
+            r1 = r0 + max(1, int(np.searchsorted(csum, _CHUNK)))
+            r1 = min(r1, n_rows)
+            L = lens[r0:r1]
+            tot = int(L.sum())
+            starts = pat_ptr[row_slot[r0:r1]]
+            ex = np.repeat(starts - (np.cumsum(L) - L), L) + np.arange(tot, dtype=np.int64)
+            z = pz[ex]
+            sm = ps[ex]
+            sMv = np.repeat(row_sig[r0:r1], L)
+            vals = np.empty(tot)
+            f = sm >= 0
+            vals[f] = u_of(z[f], sMv[f], sm[f])
+            if not f.all():
+                nf = ~f
+                vals[nf] = summed(z[nf], sMv[nf])
             keep = vals != 0.0
-            chunks_idx.append(pcol[keep]); chunks_val.append(vals[keep])
-            row_len.append(np.bincount(pslot[keep], minlength=K)[:K])
+            rid = np.repeat(np.arange(r1 - r0, dtype=np.int64), L)
+            chunks_idx.append(pcol[ex][keep]); chunks_val.append(vals[keep])
+            row_len.append(np.bincount(rid[keep], minlength=r1 - r0)[: r1 - r0])
+            r0 = r1
     n_major = PM.n_seq
-    lens = np.concatenate(row_len).astype(np.int64)
-    assert lens.shape[0] == n_major, (lens.shape, n_major)
+    lens_all = np.concatenate(row_len).astype(np.int64)
+    assert lens_all.shape[0] == n_major, (lens_all.shape, n_major)
     ptr = np.zeros(n_major + 1, np.int64)
-    np.cumsum(lens, out=ptr[1:])
+    np.cumsum(lens_all, out=ptr[1:])
     idx = (np.concatenate(chunks_idx) if chunks_idx else np.zeros(0)).astype(np.int32)
     val = (np.concatenate(chunks_val) if chunks_val else np.zeros(0)).astype(np.float64)
     return ptr, idx, val

@@ -81,6 +81,14 @@ enum { CFR_SIMULTANEOUS = 0, CFR_ALTERNATING = 1 };
  * sum_t w_t x^t / sum_t w_t in sequence form (CURRENT before iteration 1). */
 enum { CFR_CURRENT = 0, CFR_AVERAGE = 1 };
 
+/* Summation order inside a payoff-product row.  SEQUENTIAL adds a row's
+ * products strictly left to right (what a plain loop does; the FP64 path
+ * then reproduces a sequential evaluation bit for bit, which matters
+ * because regret matching amplifies rounding differences over iterations).
+ * PARALLEL lets a group of lanes share a row.  DEFAULT: SEQUENTIAL for
+ * CFR_FP64, PARALLEL otherwise.                                            */
+enum { CFR_SPMV_DEFAULT = 0, CFR_SPMV_SEQUENTIAL = 1, CFR_SPMV_PARALLEL = 2 };
+
 /* Averaging weight w_t.  DEFAULT: 1 (vanilla, PCFR), t (CFR+), t^gamma
  * (DCFR; the paper's quadratic weighting with gamma = 2), t^2 (PCFR+).   */
 enum { CFR_AVG_DEFAULT = 0, CFR_AVG_UNIFORM = 1, CFR_AVG_LINEAR = 2,
@@ -133,6 +141,7 @@ typedef struct cfr_options {
                                or NULL to let the library allocate it       */
     size_t workspace_bytes;
     int use_graph;          /* 1: replay a captured HIP graph per iteration  */
+    int spmv_order;         /* CFR_SPMV_*                                    */
 } cfr_options;
 
 typedef struct cfr_solver cfr_solver;

@@ -10,15 +10,15 @@
 // Level order (internal numbering).  The level of a decision point is the
 // number of its own earlier decisions: 0 under the empty sequence, else one
 // more than the level of its parent sequence's decision point.  Decision
-// points are numbered level by level, and inside a level by the (already
-// assigned) number of their parent sequence, ties kept in the caller's
-// order; each one's sequences follow consecutively.  Then (a) the sequences
-// of one level form one contiguous range, so each level of a sweep is one
-// launch over a range (Algorithm 2 applies one level graph per step), and
-// (b) the decision points below any sequence form one contiguous range, so
-// the observation-point sum of Algorithm 1 is a loop over a range.  When
-// the caller's numbering already has this order (the generator emits it),
-// no permutation happens and the payoff arrays are used as given.
+// points are numbered level by level, keeping the caller's order inside a
+// level; each one's sequences follow consecutively.  The sequences of one
+// level then form one contiguous range, so each level of a sweep is one
+// launch over a range (Algorithm 2 applies one level graph per step).  The
+// decision points below each sequence (the children of the observation
+// point that follows it in Algorithm 1) are listed in child_ptr/child_idx,
+// ascending.  When the caller's numbering is already level-major (the
+// generator emits it), no permutation happens and the payoff arrays are
+// used as given.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -190,9 +190,13 @@ struct PlayerPlan {
     std::vector<int32_t> old_of_new;  // internal sequence -> caller sequence
     std::vector<int32_t> inf_first;   // [n_inf+1]
     std::vector<int32_t> seq_par;     // [n_seq]
-    std::vector<int32_t> seq_child;   // [n_seq+1]
+    std::vector<int32_t> child_ptr;   // [n_seq+1]
+    std::vector<int32_t> child_idx;   // [n_inf]
     std::vector<int32_t> lvl_inf;     // [n_levels+1]
     std::vector<int32_t> lvl_seq;     // [n_levels+1]
+    int32_t top_levels = 0, n_roots = 0;
+    std::vector<int32_t> top_off;     // [top_levels*(n_roots+1)]
+    std::vector<int32_t> top_list;    // decision points of the shallow levels by level, then root
 };
 
 void plan_player(const cfr_player_desc &d, PlayerPlan &pl)
@@ -211,57 +215,93 @@ void plan_player(const cfr_player_desc &d, PlayerPlan &pl)
         n_levels = std::max(n_levels, level[j] + 1);
     }
     pl.n_levels = n_levels;
-    std::vector<std::vector<int32_t>> bucket((size_t)n_levels);
-    for (int32_t j = 0; j < n_inf; ++j) bucket[level[j]].push_back(j);
-
+    // stable bucket by level
+    std::vector<int32_t> count((size_t)n_levels + 1, 0);
+    for (int32_t j = 0; j < n_inf; ++j) count[level[j] + 1]++;
+    for (int32_t lv = 0; lv < n_levels; ++lv) count[lv + 1] += count[lv];
+    std::vector<int32_t> old_inf_of_new((size_t)n_inf);
+    {
+        std::vector<int32_t> fill(count.begin(), count.end() - 1);
+        for (int32_t j = 0; j < n_inf; ++j) old_inf_of_new[fill[level[j]]++] = j;
+    }
     pl.new_of_old.assign((size_t)n_seq, 0);
     pl.old_of_new.assign((size_t)n_seq, 0);
-    pl.inf_first.clear();
-    pl.inf_first.reserve((size_t)n_inf + 1);
-    std::vector<int32_t> old_inf_of_new;
-    old_inf_of_new.reserve((size_t)n_inf);
-    pl.lvl_inf.assign((size_t)n_levels + 1, 0);
-    pl.lvl_seq.assign((size_t)n_levels + 1, 0);
+    pl.inf_first.assign((size_t)n_inf + 1, n_seq);
+    pl.lvl_inf.assign((size_t)n_levels + 1, n_inf);
+    pl.lvl_seq.assign((size_t)n_levels + 1, n_seq);
     int32_t next = 1;
-    for (int32_t lv = 0; lv < n_levels; ++lv) {
-        auto &list = bucket[lv];
-        std::stable_sort(list.begin(), list.end(), [&](int32_t a, int32_t b) {
-            return pl.new_of_old[d.inf_parent[a]] < pl.new_of_old[d.inf_parent[b]];
-        });
-        pl.lvl_inf[lv] = (int32_t)old_inf_of_new.size();
-        pl.lvl_seq[lv] = next;
-        for (int32_t j : list) {
-            old_inf_of_new.push_back(j);
-            pl.inf_first.push_back(next);
-            for (int32_t a = d.inf_first_seq[j]; a < d.inf_first_seq[j + 1]; ++a) {
-                pl.new_of_old[a] = next;
-                pl.old_of_new[next] = a;
-                ++next;
-            }
+    for (int32_t k = 0; k < n_inf; ++k) {
+        int32_t j = old_inf_of_new[k];
+        if (k == count[level[j]]) {
+            pl.lvl_inf[level[j]] = k;
+            pl.lvl_seq[level[j]] = next;
+        }
+        pl.inf_first[k] = next;
+        for (int32_t a = d.inf_first_seq[j]; a < d.inf_first_seq[j + 1]; ++a) {
+            pl.new_of_old[a] = next;
+            pl.old_of_new[next] = a;
+            ++next;
         }
     }
-    pl.lvl_inf[n_levels] = n_inf;
-    pl.lvl_seq[n_levels] = n_seq;
-    pl.inf_first.push_back(n_seq);
     pl.identity = true;
     for (int32_t k = 0; k < n_inf; ++k)
         if (old_inf_of_new[k] != k) {
             pl.identity = false;
             break;
         }
-    // parent sequence of each decision point / of each sequence, in the new numbering
+    // parent sequence of each decision point / of each sequence, new numbering
     std::vector<int32_t> inf_par((size_t)n_inf);
     pl.seq_par.assign((size_t)n_seq, 0);
     for (int32_t k = 0; k < n_inf; ++k) {
         inf_par[k] = pl.new_of_old[d.inf_parent[old_inf_of_new[k]]];
         for (int32_t a = pl.inf_first[k]; a < pl.inf_first[k + 1]; ++a) pl.seq_par[a] = inf_par[k];
     }
-    // decision points below each sequence: inf_par is non-decreasing in this order
-    pl.seq_child.assign((size_t)n_seq + 1, n_inf);
-    int32_t k = 0;
-    for (int32_t s = 0; s <= n_seq; ++s) {
-        while (k < n_inf && inf_par[k] < s) ++k;
-        pl.seq_child[s] = k;
+    // decision points below each sequence, ascending
+    pl.child_ptr.assign((size_t)n_seq + 1, 0);
+    for (int32_t k = 0; k < n_inf; ++k) pl.child_ptr[inf_par[k] + 1]++;
+    for (int32_t s = 0; s < n_seq; ++s) pl.child_ptr[s + 1] += pl.child_ptr[s];
+    pl.child_idx.assign((size_t)std::max(n_inf, 1), 0);
+    {
+        std::vector<int32_t> fill(pl.child_ptr.begin(), pl.child_ptr.end() - 1);
+        for (int32_t k = 0; k < n_inf; ++k) pl.child_idx[fill[inf_par[k]]++] = k;
+    }
+    // One launch per root subtree for the whole sweep, when every root
+    // decision point's share of every level is at most kTopMaxGroup decision
+    // points (one pass of the block).  The levels of one sweep form a chain
+    // of dependent memory accesses either way, so this only pays when it
+    // removes every per-level launch; otherwise each level gets a launch
+    // over all its decision points.
+    pl.top_levels = 0;
+    pl.n_roots = n_levels > 0 ? pl.lvl_inf[1] - pl.lvl_inf[0] : 0;
+    pl.top_off.clear();
+    pl.top_list.clear();
+    if (n_levels == 0) return;
+    std::vector<int32_t> root((size_t)n_inf, 0);
+    std::vector<int32_t> seq_new_inf((size_t)n_seq, 0);
+    for (int32_t k = 0; k < n_inf; ++k)
+        for (int32_t a = pl.inf_first[k]; a < pl.inf_first[k + 1]; ++a) seq_new_inf[a] = k;
+    for (int32_t k = 0; k < n_inf; ++k)
+        root[k] = inf_par[k] == 0 ? k : root[seq_new_inf[inf_par[k]]];
+    const int32_t R = pl.n_roots;
+    std::vector<int32_t> cnt((size_t)R + 1);
+    for (int32_t lv = 0; lv < n_levels; ++lv) {
+        std::fill(cnt.begin(), cnt.end(), 0);
+        for (int32_t k = pl.lvl_inf[lv]; k < pl.lvl_inf[lv + 1]; ++k) cnt[root[k] + 1]++;
+        int32_t mx = *std::max_element(cnt.begin(), cnt.end());
+        if (mx > cfr::kTopMaxGroup) break;
+        for (int32_t r = 0; r < R; ++r) cnt[r + 1] += cnt[r];
+        const int32_t base = (int32_t)pl.top_list.size();
+        for (int32_t r = 0; r <= R; ++r) pl.top_off.push_back(base + cnt[r]);
+        pl.top_list.resize((size_t)base + (size_t)cnt[R]);
+        std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+        for (int32_t k = pl.lvl_inf[lv]; k < pl.lvl_inf[lv + 1]; ++k)
+            pl.top_list[(size_t)base + (size_t)fill[root[k]]++] = k;
+        pl.top_levels = lv + 1;
+    }
+    if (pl.top_levels < n_levels) {
+        pl.top_levels = 0;
+        pl.top_off.clear();
+        pl.top_list.clear();
     }
 }
 
@@ -309,6 +349,7 @@ struct Carver {
 struct Sizes {
     int64_t nnz;
     int32_t n_seq[2], n_inf[2], n_blk_csr, n_blk_csc;
+    int32_t top_off[2], top_list[2];
 };
 
 struct Buffers {
@@ -330,7 +371,8 @@ Buffers carve(Carver &c, const Sizes &z, int prec)
         size_t n = (size_t)z.n_seq[p], ni = (size_t)z.n_inf[p];
         d.inf_first = (int32_t *)c.take(4 * (ni + 1));
         d.seq_par = (int32_t *)c.take(4 * n);
-        d.seq_child = (int32_t *)c.take(4 * (n + 1));
+        d.child_ptr = (int32_t *)c.take(4 * (n + 1));
+        d.child_idx = (int32_t *)c.take(4 * (ni > 0 ? ni : 1));
         d.r = c.take(R * n);
         d.m = c.take(R * n);
         d.s = c.take(R * n);
@@ -339,6 +381,8 @@ Buffers carve(Carver &c, const Sizes &z, int prec)
         d.g = c.take(V * n);
         d.xbar = c.take(V * n);
         d.vinf = c.take(C * (ni > 0 ? ni : 1));
+        d.top_off = (int32_t *)c.take(4 * (size_t)std::max(z.top_off[p], 1));
+        d.top_list = (int32_t *)c.take(4 * (size_t)std::max(z.top_list[p], 1));
     }
     b.csr_ptr = (int32_t *)c.take(4 * ((size_t)z.n_seq[0] + 1));
     b.csr_idx = (int32_t *)c.take(4 * (size_t)z.nnz);
@@ -375,10 +419,13 @@ void make_plan(const cfr_game_desc *g, Plan &P)
     });
     std::vector<int64_t> cc = column_counts(g);
     P.blk_csc = partition_rows(b.n_seq, [&](int32_t r) { return cc[b.old_of_new[r]]; });
+
     P.sizes.nnz = g->nnz;
     for (int p = 0; p < 2; ++p) {
         P.sizes.n_seq[p] = P.pl[p].n_seq;
         P.sizes.n_inf[p] = P.pl[p].n_inf;
+        P.sizes.top_off[p] = (int32_t)P.pl[p].top_off.size();
+        P.sizes.top_list[p] = (int32_t)P.pl[p].top_list.size();
     }
     P.sizes.n_blk_csr = (int32_t)P.blk_csr.size() - 1;
     P.sizes.n_blk_csc = (int32_t)P.blk_csc.size() - 1;
@@ -391,6 +438,8 @@ int check_options(const cfr_options *o)
         return fail(CFR_EINVAL, "unknown precision");
     if (o->avg_weight < CFR_AVG_DEFAULT || o->avg_weight > CFR_AVG_POW_GAMMA)
         return fail(CFR_EINVAL, "unknown averaging weight");
+    if (o->spmv_order < CFR_SPMV_DEFAULT || o->spmv_order > CFR_SPMV_PARALLEL)
+        return fail(CFR_EINVAL, "unknown summation order");
     if (!std::isfinite(o->dcfr_alpha) || !std::isfinite(o->dcfr_beta) ||
         !std::isfinite(o->dcfr_gamma))
         return fail(CFR_EINVAL, "DCFR exponents must be finite");
@@ -441,38 +490,66 @@ struct cfr_solver {
     double total_ms[2] = {0, 0};
     double bytes_per_launch[2] = {0, 0};
 
-    hipError_t spmv(int which, const void *xin, void *yout, hipStream_t s)
+    int sequential() const
+    {
+        if (opt.spmv_order == CFR_SPMV_SEQUENTIAL) return 1;
+        if (opt.spmv_order == CFR_SPMV_PARALLEL) return 0;
+        return prec == CFR_FP64 ? 1 : 0;
+    }
+
+    cfr::IterParams iter_params() const
+    {
+        cfr::IterParams ip;
+        ip.variant = variant;
+        ip.avg_kind = opt.avg_weight;
+        ip.alpha = opt.dcfr_alpha;
+        ip.beta = opt.dcfr_beta;
+        ip.gamma = opt.dcfr_gamma;
+        return ip;
+    }
+
+    // Payoff product over the CSR (which = 0) or the CSC (which = 1); with
+    // begin set, its first block also advances the iteration scalars.
+    hipError_t spmv(int which, const void *xin, void *yout, bool begin, hipStream_t s)
     {
         const DevMatrix &A = which == 0 ? csr : csc;
+        Scalars *bsc = begin ? buf.sc : nullptr;
+        cfr::IterParams ip = iter_params();
         if (timing && s == st) {
             hipEvent_t a, b;
             hipError_t e = hipEventCreate(&a);
             if (e == hipSuccess) e = hipEventCreate(&b);
             if (e != hipSuccess) return e;
             (void)hipEventRecord(a, s);
-            e = cfr::launch_spmv(prec, A, xin, yout, xcd_remap, s);
+            e = cfr::launch_spmv(prec, A, xin, yout, xcd_remap, sequential(), bsc, ip, s);
             (void)hipEventRecord(b, s);
             events[which].emplace_back(a, b);
             launches[which]++;
             return e;
         }
-        return cfr::launch_spmv(prec, A, xin, yout, xcd_remap, s);
+        return cfr::launch_spmv(prec, A, xin, yout, xcd_remap, sequential(), bsc, ip, s);
     }
 
-    hipError_t up_sweep(int p, double usign, hipStream_t s)
+    // One player's ObserveUtility + NextStrategy: the deep levels one launch
+    // each (bottom-up), the shallow levels in one launch (bottom-up, then
+    // top-down), then the deep levels again (top-down, with averaging).
+    hipError_t sweeps(int p, double usign, hipStream_t s)
     {
         const DevPlayer &d = buf.dp[p];
-        for (int lv = d.n_levels - 1; lv >= 0; --lv) {
-            hipError_t e = cfr::launch_up_level(prec, variant, d, lv, usign, d.g, buf.sc, s);
-            if (e != hipSuccess) return e;
-        }
-        return hipSuccess;
+        hipError_t e;
+        for (int lv = d.n_levels - 1; lv >= d.top_levels; --lv)
+            if ((e = cfr::launch_up_level(prec, variant, d, lv, usign, d.g, buf.sc, s)) != hipSuccess)
+                return e;
+        if (d.top_levels > 0 &&
+            (e = cfr::launch_top(prec, variant, d, usign, 1, buf.sc, s)) != hipSuccess)
+            return e;
+        return down_sweep(p, 1, d.top_levels, s);
     }
 
-    hipError_t down_sweep(int p, int average, hipStream_t s)
+    hipError_t down_sweep(int p, int average, int from_level, hipStream_t s)
     {
         const DevPlayer &d = buf.dp[p];
-        for (int lv = 0; lv < d.n_levels; ++lv) {
+        for (int lv = from_level; lv < d.n_levels; ++lv) {
             hipError_t e = cfr::launch_down_level(prec, d, lv, average, buf.sc, s);
             if (e != hipSuccess) return e;
         }
@@ -482,24 +559,20 @@ struct cfr_solver {
     // One iteration, enqueued on stream s.
     hipError_t enqueue_iteration(hipStream_t s)
     {
-        hipError_t e = cfr::launch_begin(prec, buf.sc, variant, opt.avg_weight, opt.dcfr_alpha,
-                                         opt.dcfr_beta, opt.dcfr_gamma, s);
+        hipError_t e;
         DevPlayer &P1 = buf.dp[0], &P2 = buf.dp[1];
-        if (e != hipSuccess) return e;
         if (mode == CFR_SIMULTANEOUS) {
-            if ((e = spmv(0, P2.x, P1.g, s)) != hipSuccess) return e;
-            if ((e = spmv(1, P1.x, P2.g, s)) != hipSuccess) return e;
-            if ((e = up_sweep(0, 1.0, s)) != hipSuccess) return e;
-            if ((e = up_sweep(1, -1.0, s)) != hipSuccess) return e;
-            if ((e = down_sweep(0, 1, s)) != hipSuccess) return e;
-            return down_sweep(1, 1, s);
+            // both products read the strategies of iteration t before either
+            // player moves on
+            if ((e = spmv(0, P2.x, P1.g, true, s)) != hipSuccess) return e;
+            if ((e = spmv(1, P1.x, P2.g, false, s)) != hipSuccess) return e;
+            if ((e = sweeps(0, 1.0, s)) != hipSuccess) return e;
+            return sweeps(1, -1.0, s);
         }
-        if ((e = spmv(0, P2.x, P1.g, s)) != hipSuccess) return e;
-        if ((e = up_sweep(0, 1.0, s)) != hipSuccess) return e;
-        if ((e = down_sweep(0, 1, s)) != hipSuccess) return e;
-        if ((e = spmv(1, P1.x, P2.g, s)) != hipSuccess) return e;
-        if ((e = up_sweep(1, -1.0, s)) != hipSuccess) return e;
-        return down_sweep(1, 1, s);
+        if ((e = spmv(0, P2.x, P1.g, true, s)) != hipSuccess) return e;
+        if ((e = sweeps(0, 1.0, s)) != hipSuccess) return e;
+        if ((e = spmv(1, P1.x, P2.g, false, s)) != hipSuccess) return e;
+        return sweeps(1, -1.0, s);
     }
 
     hipError_t build_graph()
@@ -659,7 +732,12 @@ int create_impl(const cfr_game_desc *g, const cfr_options *o, cfr_solver *s)
         d.lvl_seq = pl.lvl_seq.data();
         CHECK(h2d(d.inf_first, pl.inf_first.data(), pl.inf_first.size(), st));
         CHECK(h2d(d.seq_par, pl.seq_par.data(), pl.seq_par.size(), st));
-        CHECK(h2d(d.seq_child, pl.seq_child.data(), pl.seq_child.size(), st));
+        CHECK(h2d(d.child_ptr, pl.child_ptr.data(), pl.child_ptr.size(), st));
+        CHECK(h2d(d.child_idx, pl.child_idx.data(), pl.child_idx.size(), st));
+        CHECK(h2d(d.top_off, pl.top_off.data(), pl.top_off.size(), st));
+        CHECK(h2d(d.top_list, pl.top_list.data(), pl.top_list.size(), st));
+        d.top_levels = pl.top_levels;
+        d.n_roots = pl.n_roots;
         size_t R = cfr::accum_bytes(s->prec) * (size_t)pl.n_seq;
         CHECK(hipMemsetAsync(d.r, 0, R, st));
         CHECK(hipMemsetAsync(d.m, 0, R, st));
@@ -737,7 +815,7 @@ int create_impl(const cfr_game_desc *g, const cfr_options *o, cfr_solver *s)
             CHECK(hipStreamSynchronize(st));
         }
         CHECK(cfr::launch_uniform_b(s->prec, d, st));
-        CHECK(s->down_sweep(p, 0, st));
+        CHECK(s->down_sweep(p, 0, 0, st));
     }
     CHECK(hipStreamSynchronize(st));
 #undef CHECK
@@ -942,8 +1020,11 @@ int cfr_exploitability(cfr_solver *s, int kind, double *out)
             src[p] = s->buf.dp[p].xbar;
         }
     }
-    CHECK(cfr::launch_spmv(s->prec, s->csr, src[1], P1.g, s->xcd_remap, st));
-    CHECK(cfr::launch_spmv(s->prec, s->csc, src[0], P2.g, s->xcd_remap, st));
+    cfr::IterParams ip = s->iter_params();
+    CHECK(cfr::launch_spmv(s->prec, s->csr, src[1], P1.g, s->xcd_remap, s->sequential(), nullptr,
+                           ip, st));
+    CHECK(cfr::launch_spmv(s->prec, s->csc, src[0], P2.g, s->xcd_remap, s->sequential(), nullptr,
+                           ip, st));
     for (int p = 0; p < 2; ++p) {
         const DevPlayer &d = s->buf.dp[p];
         double usign = p == 0 ? 1.0 : -1.0;

@@ -22,6 +22,14 @@ struct Scalars {
     double out[8]; // scalar results of the evaluation kernels
 };
 
+// Constants of the iteration that the first product launch uses to advance
+// the device-side scalars.
+struct IterParams {
+    int variant = 0;
+    int avg_kind = 0;
+    double alpha = 1.5, beta = 0.0, gamma = 2.0;
+};
+
 // Payoff matrix sorted along one player's sequences: CSR of A (player 1
 // rows) or CSR of A^T (player 2 rows), with the row-block partition the
 // product kernel walks.
@@ -45,7 +53,8 @@ struct DevPlayer {
     const int32_t *lvl_seq = nullptr;  // host array [n_levels+1]
     int32_t *inf_first = nullptr;      // [n_inf+1]
     int32_t *seq_par = nullptr;        // [n_seq] parent sequence of each sequence's decision point
-    int32_t *seq_child = nullptr;      // [n_seq+1] child decision points of each sequence
+    int32_t *child_ptr = nullptr;      // [n_seq+1] decision points below each sequence:
+    int32_t *child_idx = nullptr;      //   child_idx[child_ptr[s] .. child_ptr[s+1])
     void *r = nullptr;                 // [n_seq] accumulator type
     void *m = nullptr;                 // [n_seq] accumulator type
     void *s = nullptr;                 // [n_seq] accumulator type
@@ -54,19 +63,29 @@ struct DevPlayer {
     void *g = nullptr;                 // [n_seq] value type
     void *xbar = nullptr;              // [n_seq] value type
     void *vinf = nullptr;              // [n_inf] compute type
+    // shallow levels 0 .. top_levels-1 run in one launch (k_top), one block
+    // per root decision point (n_roots of them)
+    int32_t top_levels = 0;
+    int32_t n_roots = 0;
+    int32_t *top_off = nullptr;        // [top_levels*(n_roots+1)]
+    int32_t *top_list = nullptr;       // decision points grouped by level, then root
 };
 
 // Kernel launchers (cfr_kernels.hip).  All enqueue on `st` and return the
 // launch status.
-hipError_t launch_begin(int prec, Scalars *sc, int variant, int avg_kind, double alpha,
-                        double beta, double gamma, hipStream_t st);
 hipError_t launch_uniform_b(int prec, const DevPlayer &p, hipStream_t st);
+// begin_sc != nullptr: the first block also advances the iteration scalars.
 hipError_t launch_spmv(int prec, const DevMatrix &A, const void *xin, void *yout,
-                       int xcd_remap, hipStream_t st);
+                       int xcd_remap, int sequential, Scalars *begin_sc, const IterParams &ip,
+                       hipStream_t st);
 hipError_t launch_up_level(int prec, int variant, const DevPlayer &p, int level, double usign,
                            const void *g, const Scalars *sc, hipStream_t st);
 hipError_t launch_down_level(int prec, const DevPlayer &p, int level, int average,
                              const Scalars *sc, hipStream_t st);
+// ObserveUtility on levels top_levels-1..0, then the top-down pass on levels
+// 0..top_levels-1 (with averaging when `average`).
+hipError_t launch_top(int prec, int variant, const DevPlayer &p, double usign, int average,
+                      const Scalars *sc, hipStream_t st);
 hipError_t launch_normalize(int prec, const DevPlayer &p, const Scalars *sc, hipStream_t st);
 hipError_t launch_br_level(int prec, const DevPlayer &p, int level, double usign,
                            const void *g, hipStream_t st);
@@ -79,10 +98,19 @@ size_t value_bytes(int prec);
 size_t accum_bytes(int prec);
 size_t compute_bytes(int prec);
 
+// Payoff-product tiling (overridable at build time for tuning sweeps).
+#ifndef CFR_SPMV_ITEMS
+#define CFR_SPMV_ITEMS 8
+#endif
+#ifndef CFR_SPMV_NONTEMPORAL
+#define CFR_SPMV_NONTEMPORAL 1
+#endif
 constexpr int kSpmvThreads = 256;
-constexpr int kSpmvItems = 8;
+constexpr int kSpmvItems = CFR_SPMV_ITEMS;
 constexpr int kSpmvCap = kSpmvThreads * kSpmvItems;  // nonzeros staged per block
 constexpr int kSpmvRowCap = 2048;                    // rows per block
 constexpr int kDotPartials = 512;
+constexpr int kTopThreads = 1024;   // threads of the shallow-level block
+constexpr int kTopMaxGroup = 1024;  // decision points per root and level it takes
 
 }  // namespace cfr

@@ -16,9 +16,13 @@
 //   k_down      one treeplex level of NextStrategy's top-down pass, fused
 //               with the average-strategy accumulation of the strategy it
 //               overwrites: one thread per sequence.
+//   k_top       the shallow levels of a player, bottom-up then top-down, in
+//               one launch: one block per root decision point's subtree.
 //   k_br        one level of the best-response max-sweep.
-//   k_begin / k_normalize / k_root / k_dot   per-iteration scalars, average
-//               normalisation and deterministic scalar reductions.
+//   k_normalize / k_root / k_dot   average normalisation and deterministic
+//               scalar reductions.  The per-iteration scalars (t, the
+//               averaging weight, the DCFR factors) are advanced by the first
+//               block of the iteration's first payoff product.
 // Precision modes select the value type (payoffs, strategies, utilities),
 // the accumulator type (regrets, predictions, averages) and the compute
 // type (in-register arithmetic).  No kernel uses atomics, so every result
@@ -67,25 +71,24 @@ inline unsigned grid_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kTh
 // Per-iteration scalars
 // ---------------------------------------------------------------------------
 
-__global__ void k_begin(Scalars *sc, int variant, int avg_kind, double alpha, double beta,
-                        double gamma)
+__device__ void begin_iteration(Scalars *sc, const IterParams &ip)
 {
     double t = sc->t + 1.0;
     sc->t = t;
-    int kind = avg_kind;
+    int kind = ip.avg_kind;
     if (kind == CFR_AVG_DEFAULT) {
-        kind = variant == CFR_PLUS        ? CFR_AVG_LINEAR
-               : variant == CFR_DCFR      ? CFR_AVG_POW_GAMMA
-               : variant == CFR_PCFR_PLUS ? CFR_AVG_QUADRATIC
-                                          : CFR_AVG_UNIFORM;
+        kind = ip.variant == CFR_PLUS        ? CFR_AVG_LINEAR
+               : ip.variant == CFR_DCFR      ? CFR_AVG_POW_GAMMA
+               : ip.variant == CFR_PCFR_PLUS ? CFR_AVG_QUADRATIC
+                                             : CFR_AVG_UNIFORM;
     }
     double w = 1.0;
     if (kind == CFR_AVG_LINEAR) w = t;
     else if (kind == CFR_AVG_QUADRATIC) w = t * t;
-    else if (kind == CFR_AVG_POW_GAMMA) w = pow(t, gamma);
+    else if (kind == CFR_AVG_POW_GAMMA) w = pow(t, ip.gamma);
     sc->w = w;
     sc->W = sc->W + w;
-    double ta = pow(t, alpha), tb = pow(t, beta);
+    double ta = pow(t, ip.alpha), tb = pow(t, ip.beta);
     sc->dpos = ta / (ta + 1.0);
     sc->dneg = tb / (tb + 1.0);
 }
@@ -94,17 +97,22 @@ __global__ void k_begin(Scalars *sc, int variant, int avg_kind, double alpha, do
 // Payoff product y = M x over a row-sorted matrix
 // ---------------------------------------------------------------------------
 
-template <int P>
+// SEQ: every row is summed strictly left to right (the order of a plain
+// sequential loop), which the FP64 path needs to reproduce a sequential
+// evaluation bit for bit; otherwise a power-of-two group of lanes shares
+// each row and combines its partial sums with cross-lane shuffles.
+template <int P, bool SEQ>
 __global__ __launch_bounds__(kSpmvThreads) void k_spmv(
     int32_t n_blk, const int32_t *__restrict__ blk, const int32_t *__restrict__ ptr,
     const int32_t *__restrict__ idx, const typename Types<P>::V *__restrict__ val,
     const typename Types<P>::V *__restrict__ xin, typename Types<P>::V *__restrict__ yout,
-    int xcd_remap)
+    int xcd_remap, Scalars *begin_sc, IterParams ip)
 {
     using V = typename Types<P>::V;
     using C = typename Types<P>::C;
     __shared__ C prod[kSpmvCap];
 
+    if (begin_sc && blockIdx.x == 0 && threadIdx.x == 0) begin_iteration(begin_sc, ip);
     int32_t bid = (int32_t)blockIdx.x;
     if (xcd_remap) {
         // Workgroups are dealt round-robin over the 8 XCDs; give each XCD a
@@ -140,8 +148,13 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(
     for (int k = 0; k < kSpmvItems; ++k) {
         int32_t i = k * kSpmvThreads + tid;
         bool ok = i < n;
+#if CFR_SPMV_NONTEMPORAL
         c[k] = ok ? __builtin_nontemporal_load(idx + e0 + i) : 0;
         v[k] = ok ? __builtin_nontemporal_load(val + e0 + i) : (V)0;
+#else
+        c[k] = ok ? idx[e0 + i] : 0;
+        v[k] = ok ? val[e0 + i] : (V)0;
+#endif
     }
 #pragma unroll
     for (int k = 0; k < kSpmvItems; ++k) {
@@ -149,11 +162,37 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(
         if (i < n) prod[i] = (C)v[k] * (C)xin[c[k]];
     }
     __syncthreads();
-    for (int32_t r = rb + tid; r < re; r += kSpmvThreads) {
-        int32_t a = ptr[r] - e0, z = ptr[r + 1] - e0;
+    if (SEQ) {
+        for (int32_t r = rb + tid; r < re; r += kSpmvThreads) {
+            int32_t i = ptr[r] - e0;
+            const int32_t z = ptr[r + 1] - e0;
+            C acc = 0;
+            for (; i + 4 <= z; i += 4) {
+                C p0 = prod[i], p1 = prod[i + 1], p2 = prod[i + 2], p3 = prod[i + 3];
+                acc = acc + p0;
+                acc = acc + p1;
+                acc = acc + p2;
+                acc = acc + p3;
+            }
+            for (; i < z; ++i) acc = acc + prod[i];
+            yout[r] = (V)acc;
+        }
+        return;
+    }
+    // lanes per row: the largest power of two (<= 64) that still gives every
+    // row of the block its own group, and not far above the mean row length
+    const int32_t nrows = re - rb;
+    int L = 64;
+    while (L > 1 && L * nrows > kSpmvThreads) L >>= 1;
+    while (L > 1 && L > 2 * (n / nrows + 1)) L >>= 1;
+    const int lane = tid & (L - 1);
+    const int groups = kSpmvThreads / L;
+    for (int32_t r = rb + tid / L; r < re; r += groups) {
+        const int32_t a = ptr[r] - e0, z = ptr[r + 1] - e0;
         C acc = 0;
-        for (int32_t i = a; i < z; ++i) acc = acc + prod[i];
-        yout[r] = (V)acc;
+        for (int32_t i = a + lane; i < z; i += L) acc = acc + prod[i];
+        for (int off = L >> 1; off > 0; off >>= 1) acc = acc + __shfl_xor(acc, off, L);
+        if (lane == 0) yout[r] = (V)acc;
     }
 }
 
@@ -174,32 +213,29 @@ __device__ __forceinline__ typename Types<P>::C post_step(typename Types<P>::C r
     return r;
 }
 
+// One decision point of ObserveUtility: counterfactual utilities of its
+// actions (own utility plus the values of the decision points below), its
+// value, the regret update with the variant's post-step, and regret
+// matching for the next strategy.
 template <int P, int VAR>
-__global__ __launch_bounds__(kThreads) void k_up(
-    int32_t j0, int32_t j1, const int32_t *__restrict__ inf_first,
-    const int32_t *__restrict__ seq_child, const typename Types<P>::V *__restrict__ g,
+__device__ __forceinline__ void up_infoset(
+    int32_t j, const int32_t *__restrict__ inf_first, const int32_t *__restrict__ child_ptr,
+    const int32_t *__restrict__ child_idx, const typename Types<P>::V *__restrict__ g,
     typename Types<P>::C usign, typename Types<P>::C *__restrict__ vinf,
     typename Types<P>::V *__restrict__ b, typename Types<P>::R *__restrict__ r,
-    typename Types<P>::R *__restrict__ m, const Scalars *__restrict__ sc)
+    typename Types<P>::R *__restrict__ m, typename Types<P>::C dpos, typename Types<P>::C dneg)
 {
     using V = typename Types<P>::V;
     using R = typename Types<P>::R;
     using C = typename Types<P>::C;
     constexpr bool kPred = VAR == CFR_PCFR_PLUS || VAR == CFR_PCFR;
-    int32_t j = j0 + (int32_t)(blockIdx.x * kThreads + threadIdx.x);
-    if (j >= j1) return;
-    C dpos = 1, dneg = 1;
-    if (VAR == CFR_DCFR) {
-        dpos = (C)sc->dpos;
-        dneg = (C)sc->dneg;
-    }
     const int32_t a0 = inf_first[j], a1 = inf_first[j + 1];
     const int32_t n = a1 - a0;
 
     auto cf_utility = [&](int32_t a) -> C {
         C acc = usign * (C)g[a];
-        const int32_t c1 = seq_child[a + 1];
-        for (int32_t c = seq_child[a]; c < c1; ++c) acc = acc + vinf[c];
+        const int32_t c1 = child_ptr[a + 1];
+        for (int32_t c = child_ptr[a]; c < c1; ++c) acc = acc + vinf[child_idx[c]];
         return acc;
     };
 
@@ -264,6 +300,88 @@ __global__ __launch_bounds__(kThreads) void k_up(
     }
 }
 
+template <int P, int VAR>
+__global__ __launch_bounds__(kThreads) void k_up(
+    int32_t j0, int32_t j1, const int32_t *__restrict__ inf_first,
+    const int32_t *__restrict__ child_ptr, const int32_t *__restrict__ child_idx,
+    const typename Types<P>::V *__restrict__ g, typename Types<P>::C usign,
+    typename Types<P>::C *__restrict__ vinf, typename Types<P>::V *__restrict__ b,
+    typename Types<P>::R *__restrict__ r, typename Types<P>::R *__restrict__ m,
+    const Scalars *__restrict__ sc)
+{
+    using C = typename Types<P>::C;
+    int32_t j = j0 + (int32_t)(blockIdx.x * kThreads + threadIdx.x);
+    if (j >= j1) return;
+    C dpos = 1, dneg = 1;
+    if (VAR == CFR_DCFR) {
+        dpos = (C)sc->dpos;
+        dneg = (C)sc->dneg;
+    }
+    up_infoset<P, VAR>(j, inf_first, child_ptr, child_idx, g, usign, vinf, b, r, m, dpos, dneg);
+}
+
+// One decision point of NextStrategy's top-down pass, accumulating the
+// strategy it overwrites into the average first.
+template <int P>
+__device__ __forceinline__ void down_infoset(int32_t j, const int32_t *__restrict__ inf_first,
+                                             const int32_t *__restrict__ seq_par,
+                                             const typename Types<P>::V *__restrict__ b,
+                                             typename Types<P>::V *__restrict__ x,
+                                             typename Types<P>::R *__restrict__ s,
+                                             typename Types<P>::R w, int average)
+{
+    using V = typename Types<P>::V;
+    using R = typename Types<P>::R;
+    const int32_t a0 = inf_first[j], a1 = inf_first[j + 1];
+    const V xp = x[seq_par[a0]];
+    for (int32_t a = a0; a < a1; ++a) {
+        if (average) s[a] = s[a] + w * (R)x[a];
+        x[a] = xp * b[a];
+    }
+}
+
+// The shallow levels of one player in one launch: block `root` owns the
+// subtree below root decision point `root` (subtrees are disjoint and the
+// sweeps never cross them).  It runs ObserveUtility on levels
+// top_levels-1 .. 0 of its subtree, then the top-down pass on levels
+// 0 .. top_levels-1, with a block barrier between levels.  The decision
+// points of level l under root r are top_list[top_off[l*(n_roots+1) + r] ..
+// top_off[l*(n_roots+1) + r + 1]).
+template <int P, int VAR>
+__global__ __launch_bounds__(kTopThreads) void k_top(
+    int32_t top_levels, int32_t n_roots, const int32_t *__restrict__ top_off,
+    const int32_t *__restrict__ top_list, const int32_t *__restrict__ inf_first,
+    const int32_t *__restrict__ child_ptr, const int32_t *__restrict__ child_idx,
+    const int32_t *__restrict__ seq_par, const typename Types<P>::V *__restrict__ g,
+    typename Types<P>::C usign, typename Types<P>::C *__restrict__ vinf,
+    typename Types<P>::V *__restrict__ b, typename Types<P>::R *__restrict__ r,
+    typename Types<P>::R *__restrict__ m, typename Types<P>::V *__restrict__ x,
+    typename Types<P>::R *__restrict__ s, const Scalars *__restrict__ sc, int average)
+{
+    using R = typename Types<P>::R;
+    using C = typename Types<P>::C;
+    const int32_t root = (int32_t)blockIdx.x;
+    C dpos = 1, dneg = 1;
+    if (VAR == CFR_DCFR) {
+        dpos = (C)sc->dpos;
+        dneg = (C)sc->dneg;
+    }
+    const R w = average ? (R)sc->w : (R)0;
+    for (int lv = top_levels - 1; lv >= 0; --lv) {
+        const int32_t *off = top_off + (size_t)lv * (n_roots + 1);
+        for (int32_t i = off[root] + (int32_t)threadIdx.x; i < off[root + 1]; i += kTopThreads)
+            up_infoset<P, VAR>(top_list[i], inf_first, child_ptr, child_idx, g, usign, vinf, b, r,
+                               m, dpos, dneg);
+        __syncthreads();
+    }
+    for (int lv = 0; lv < top_levels; ++lv) {
+        const int32_t *off = top_off + (size_t)lv * (n_roots + 1);
+        for (int32_t i = off[root] + (int32_t)threadIdx.x; i < off[root + 1]; i += kTopThreads)
+            down_infoset<P>(top_list[i], inf_first, seq_par, b, x, s, w, average);
+        __syncthreads();
+    }
+}
+
 template <int P>
 __global__ __launch_bounds__(kThreads) void k_uniform_b(int32_t n_inf,
                                                         const int32_t *__restrict__ inf_first,
@@ -316,7 +434,8 @@ __global__ __launch_bounds__(kThreads) void k_normalize(int32_t n, const typenam
 template <int P>
 __global__ __launch_bounds__(kThreads) void k_br(int32_t j0, int32_t j1,
                                                  const int32_t *__restrict__ inf_first,
-                                                 const int32_t *__restrict__ seq_child,
+                                                 const int32_t *__restrict__ child_ptr,
+                                                 const int32_t *__restrict__ child_idx,
                                                  const typename Types<P>::V *__restrict__ g,
                                                  typename Types<P>::C usign,
                                                  typename Types<P>::C *__restrict__ vmax)
@@ -328,7 +447,7 @@ __global__ __launch_bounds__(kThreads) void k_br(int32_t j0, int32_t j1,
     C best = 0;
     for (int32_t a = a0; a < a1; ++a) {
         C acc = usign * (C)g[a];
-        for (int32_t c = seq_child[a]; c < seq_child[a + 1]; ++c) acc = acc + vmax[c];
+        for (int32_t c = child_ptr[a]; c < child_ptr[a + 1]; ++c) acc = acc + vmax[child_idx[c]];
         if (a == a0 || acc > best) best = acc;
     }
     vmax[j] = best;
@@ -389,13 +508,20 @@ __global__ __launch_bounds__(kThreads) void k_dot_final(int n_partials, const do
 // ---------------------------------------------------------------------------
 
 template <int P>
-hipError_t spmv_t(const DevMatrix &A, const void *xin, void *yout, int xcd_remap, hipStream_t st)
+hipError_t spmv_t(const DevMatrix &A, const void *xin, void *yout, int xcd_remap, int sequential,
+                  Scalars *begin_sc, const IterParams &ip, hipStream_t st)
 {
     using V = typename Types<P>::V;
     if (A.n_blk == 0) return hipSuccess;
     unsigned grid = xcd_remap ? (unsigned)(((A.n_blk + 7) / 8) * 8) : (unsigned)A.n_blk;
-    hipLaunchKernelGGL((k_spmv<P>), dim3(grid), dim3(kSpmvThreads), 0, st, A.n_blk, A.blk, A.ptr,
-                       A.idx, (const V *)A.val, (const V *)xin, (V *)yout, xcd_remap);
+    if (sequential)
+        hipLaunchKernelGGL((k_spmv<P, true>), dim3(grid), dim3(kSpmvThreads), 0, st, A.n_blk,
+                           A.blk, A.ptr, A.idx, (const V *)A.val, (const V *)xin, (V *)yout,
+                           xcd_remap, begin_sc, ip);
+    else
+        hipLaunchKernelGGL((k_spmv<P, false>), dim3(grid), dim3(kSpmvThreads), 0, st, A.n_blk,
+                           A.blk, A.ptr, A.idx, (const V *)A.val, (const V *)xin, (V *)yout,
+                           xcd_remap, begin_sc, ip);
     return hipGetLastError();
 }
 
@@ -407,7 +533,7 @@ hipError_t up_t(const DevPlayer &p, int level, double usign, const void *g, cons
     int32_t j0 = p.lvl_inf[level], j1 = p.lvl_inf[level + 1];
     if (j1 <= j0) return hipSuccess;
     hipLaunchKernelGGL((k_up<P, VAR>), dim3(grid_for(j1 - j0)), dim3(kThreads), 0, st, j0, j1,
-                       p.inf_first, p.seq_child, (const typename T::V *)g,
+                       p.inf_first, p.child_ptr, p.child_idx, (const typename T::V *)g,
                        (typename T::C)usign, (typename T::C *)p.vinf, (typename T::V *)p.b,
                        (typename T::R *)p.r, (typename T::R *)p.m, sc);
     return hipGetLastError();
@@ -423,6 +549,34 @@ hipError_t up_dispatch(int variant, const DevPlayer &p, int level, double usign,
     case CFR_DCFR: return up_t<P, CFR_DCFR>(p, level, usign, g, sc, st);
     case CFR_PCFR_PLUS: return up_t<P, CFR_PCFR_PLUS>(p, level, usign, g, sc, st);
     case CFR_PCFR: return up_t<P, CFR_PCFR>(p, level, usign, g, sc, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int P, int VAR>
+hipError_t top_t(const DevPlayer &p, double usign, int average, const Scalars *sc, hipStream_t st)
+{
+    using T = Types<P>;
+    if (p.top_levels == 0 || p.n_roots == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_top<P, VAR>), dim3(p.n_roots), dim3(kTopThreads), 0, st, p.top_levels,
+                       p.n_roots, p.top_off, p.top_list, p.inf_first, p.child_ptr, p.child_idx,
+                       p.seq_par, (const typename T::V *)p.g, (typename T::C)usign,
+                       (typename T::C *)p.vinf, (typename T::V *)p.b, (typename T::R *)p.r,
+                       (typename T::R *)p.m, (typename T::V *)p.x, (typename T::R *)p.s, sc,
+                       average);
+    return hipGetLastError();
+}
+
+template <int P>
+hipError_t top_dispatch(int variant, const DevPlayer &p, double usign, int average,
+                        const Scalars *sc, hipStream_t st)
+{
+    switch (variant) {
+    case CFR_VANILLA: return top_t<P, CFR_VANILLA>(p, usign, average, sc, st);
+    case CFR_PLUS: return top_t<P, CFR_PLUS>(p, usign, average, sc, st);
+    case CFR_DCFR: return top_t<P, CFR_DCFR>(p, usign, average, sc, st);
+    case CFR_PCFR_PLUS: return top_t<P, CFR_PCFR_PLUS>(p, usign, average, sc, st);
+    case CFR_PCFR: return top_t<P, CFR_PCFR>(p, usign, average, sc, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -465,8 +619,8 @@ hipError_t br_t(const DevPlayer &p, int level, double usign, const void *g, hipS
     int32_t j0 = p.lvl_inf[level], j1 = p.lvl_inf[level + 1];
     if (j1 <= j0) return hipSuccess;
     hipLaunchKernelGGL((k_br<P>), dim3(grid_for(j1 - j0)), dim3(kThreads), 0, st, j0, j1,
-                       p.inf_first, p.seq_child, (const typename T::V *)g, (typename T::C)usign,
-                       (typename T::C *)p.vinf);
+                       p.inf_first, p.child_ptr, p.child_idx, (const typename T::V *)g,
+                       (typename T::C)usign, (typename T::C *)p.vinf);
     return hipGetLastError();
 }
 
@@ -505,29 +659,27 @@ hipError_t dot_t(int32_t n, const void *a, const void *b, double *partials, int 
     default: return hipErrorInvalidValue;                          \
     }
 
-hipError_t launch_begin(int prec, Scalars *sc, int variant, int avg_kind, double alpha,
-                        double beta, double gamma, hipStream_t st)
-{
-    (void)prec;
-    hipLaunchKernelGGL(k_begin, dim3(1), dim3(1), 0, st, sc, variant, avg_kind, alpha, beta, gamma);
-    return hipGetLastError();
-}
-
 hipError_t launch_uniform_b(int prec, const DevPlayer &p, hipStream_t st)
 {
     CFR_DISPATCH(prec, uniform_t<P>(p, st));
 }
 
 hipError_t launch_spmv(int prec, const DevMatrix &A, const void *xin, void *yout, int xcd_remap,
-                       hipStream_t st)
+                       int sequential, Scalars *begin_sc, const IterParams &ip, hipStream_t st)
 {
-    CFR_DISPATCH(prec, spmv_t<P>(A, xin, yout, xcd_remap, st));
+    CFR_DISPATCH(prec, spmv_t<P>(A, xin, yout, xcd_remap, sequential, begin_sc, ip, st));
 }
 
 hipError_t launch_up_level(int prec, int variant, const DevPlayer &p, int level, double usign,
                            const void *g, const Scalars *sc, hipStream_t st)
 {
     CFR_DISPATCH(prec, up_dispatch<P>(variant, p, level, usign, g, sc, st));
+}
+
+hipError_t launch_top(int prec, int variant, const DevPlayer &p, double usign, int average,
+                      const Scalars *sc, hipStream_t st)
+{
+    CFR_DISPATCH(prec, top_dispatch<P>(variant, p, usign, average, sc, st));
 }
 
 hipError_t launch_down_level(int prec, const DevPlayer &p, int level, int average,
