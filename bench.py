@@ -84,6 +84,23 @@ def cpu_baseline(g, variant, mode, budget_s: float):
     return n, el
 
 
+def copy_probe(torch, nbytes: int = 1600 << 20, reps: int = 5):
+    """A plain copy of known size: each launch reads and writes nbytes."""
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes,
+                      "ms_per_copy": ms, "copy_GBs": 2 * nbytes / (ms * 1e-3) / 1e9}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +115,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle time for the CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="time a plain device copy of 1.6 GiB (the HBM reference that "
+                         "scales the FETCH_SIZE/WRITE_SIZE counters) and exit")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -106,6 +126,10 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_probe:
+        copy_probe(torch)
+        return
 
     import gamegen as gg
     import paper_2605_14277_amd as cfr

@@ -51,6 +51,9 @@ struct DevPlayer {
     int32_t n_levels = 0;
     const int32_t *lvl_inf = nullptr;  // host array [n_levels+1]
     const int32_t *lvl_seq = nullptr;  // host array [n_levels+1]
+    const uint8_t *lvl_fast = nullptr; // host array [n_levels]: every decision point of the
+                                       // level has <= kFastActs actions, each with
+                                       // <= kFastKids decision points below it
     int32_t *inf_first = nullptr;      // [n_inf+1]
     int32_t *seq_par = nullptr;        // [n_seq] parent sequence of each sequence's decision point
     int32_t *child_ptr = nullptr;      // [n_seq+1] decision points below each sequence:
@@ -69,6 +72,7 @@ struct DevPlayer {
     int32_t n_roots = 0;
     int32_t *top_off = nullptr;        // [top_levels*(n_roots+1)]
     int32_t *top_list = nullptr;       // decision points grouped by level, then root
+    int top_fast = 0;                  // every level in k_top is a fast level
 };
 
 // Kernel launchers (cfr_kernels.hip).  All enqueue on `st` and return the
@@ -100,7 +104,7 @@ size_t compute_bytes(int prec);
 
 // Payoff-product tiling (overridable at build time for tuning sweeps).
 #ifndef CFR_SPMV_ITEMS
-#define CFR_SPMV_ITEMS 8
+#define CFR_SPMV_ITEMS 16
 #endif
 #ifndef CFR_SPMV_NONTEMPORAL
 #define CFR_SPMV_NONTEMPORAL 1
@@ -108,8 +112,10 @@ size_t compute_bytes(int prec);
 constexpr int kSpmvThreads = 256;
 constexpr int kSpmvItems = CFR_SPMV_ITEMS;
 constexpr int kSpmvCap = kSpmvThreads * kSpmvItems;  // nonzeros staged per block
-constexpr int kSpmvRowCap = 2048;                    // rows per block
+constexpr int kSpmvRowCap = 256;                     // rows per block
 constexpr int kDotPartials = 512;
+constexpr int kFastActs = 4;        // fast sweep path: actions per decision point
+constexpr int kFastKids = 4;        // fast sweep path: decision points below a sequence
 constexpr int kTopThreads = 1024;   // threads of the shallow-level block
 constexpr int kTopMaxGroup = 1024;  // decision points per root and level it takes
 

@@ -142,24 +142,31 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(
         return;
     }
 
+    // inactive lanes read the block's first entry (any valid address), so
+    // every load is unconditional and all of them are in flight together
     int32_t c[kSpmvItems];
     V v[kSpmvItems];
+    V gx[kSpmvItems];
+    if (n > 0) {
 #pragma unroll
-    for (int k = 0; k < kSpmvItems; ++k) {
-        int32_t i = k * kSpmvThreads + tid;
-        bool ok = i < n;
+        for (int k = 0; k < kSpmvItems; ++k) {
+            const int32_t i = k * kSpmvThreads + tid;
+            const int32_t at = e0 + (i < n ? i : 0);
 #if CFR_SPMV_NONTEMPORAL
-        c[k] = ok ? __builtin_nontemporal_load(idx + e0 + i) : 0;
-        v[k] = ok ? __builtin_nontemporal_load(val + e0 + i) : (V)0;
+            c[k] = __builtin_nontemporal_load(idx + at);
+            v[k] = __builtin_nontemporal_load(val + at);
 #else
-        c[k] = ok ? idx[e0 + i] : 0;
-        v[k] = ok ? val[e0 + i] : (V)0;
+            c[k] = idx[at];
+            v[k] = val[at];
 #endif
-    }
+        }
 #pragma unroll
-    for (int k = 0; k < kSpmvItems; ++k) {
-        int32_t i = k * kSpmvThreads + tid;
-        if (i < n) prod[i] = (C)v[k] * (C)xin[c[k]];
+        for (int k = 0; k < kSpmvItems; ++k) gx[k] = xin[c[k]];
+#pragma unroll
+        for (int k = 0; k < kSpmvItems; ++k) {
+            const int32_t i = k * kSpmvThreads + tid;
+            if (i < n) prod[i] = (C)v[k] * (C)gx[k];
+        }
     }
     __syncthreads();
     if (SEQ) {
@@ -300,7 +307,90 @@ __device__ __forceinline__ void up_infoset(
     }
 }
 
+// Fast path of up_infoset for a decision point with at most kFastActs
+// actions, each with at most kFastKids decision points below it.  Every
+// load is issued unconditionally (lanes past the end read a valid clamped
+// address and ignore the value), so one dependent round trip serves all
+// actions and children at once: offsets -> action data and child
+// pointers -> child ids -> child values.  The arithmetic and its order are
+// exactly those of up_infoset.
 template <int P, int VAR>
+__device__ __forceinline__ void up_infoset_fast(
+    int32_t j, const int32_t *__restrict__ inf_first, const int32_t *__restrict__ child_ptr,
+    const int32_t *__restrict__ child_idx, const typename Types<P>::V *__restrict__ g,
+    typename Types<P>::C usign, typename Types<P>::C *__restrict__ vinf,
+    typename Types<P>::V *__restrict__ b, typename Types<P>::R *__restrict__ r,
+    typename Types<P>::R *__restrict__ m, typename Types<P>::C dpos, typename Types<P>::C dneg)
+{
+    using V = typename Types<P>::V;
+    using R = typename Types<P>::R;
+    using C = typename Types<P>::C;
+    constexpr int NA = kFastActs, NC = kFastKids;
+    constexpr bool kPred = VAR == CFR_PCFR_PLUS || VAR == CFR_PCFR;
+    const int32_t a0 = inf_first[j], a1 = inf_first[j + 1];
+    const int32_t n = a1 - a0;
+    V gv[NA], bv[NA];
+    R rv[NA], mv[NA];
+    int32_t c0[NA], c1[NA];
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+        const int32_t a = a0 + (k < n ? k : 0);
+        gv[k] = g[a];
+        bv[k] = b[a];
+        rv[k] = r[a];
+        if (kPred) mv[k] = m[a];
+        c0[k] = child_ptr[a];
+        c1[k] = child_ptr[a + 1];
+    }
+    int32_t cid[NA][NC];
+#pragma unroll
+    for (int k = 0; k < NA; ++k)
+#pragma unroll
+        for (int i = 0; i < NC; ++i) cid[k][i] = child_idx[c0[k] + i < c1[k] ? c0[k] + i : 0];
+    C cv[NA][NC];
+#pragma unroll
+    for (int k = 0; k < NA; ++k)
+#pragma unroll
+        for (int i = 0; i < NC; ++i) cv[k][i] = vinf[cid[k][i]];
+    C q[NA];
+    C V_ = 0;
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+        if (k < n) {
+            C acc = usign * (C)gv[k];
+#pragma unroll
+            for (int i = 0; i < NC; ++i)
+                if (c0[k] + i < c1[k]) acc = acc + cv[k][i];
+            q[k] = acc;
+            V_ = V_ + (C)bv[k] * acc;
+        }
+    }
+    vinf[j] = V_;
+    C z[NA];
+    C Z = 0;
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+        if (k < n) {
+            const int32_t a = a0 + k;
+            C inst = q[k] - V_;
+            C rr = post_step<P, VAR>((C)rv[k] + inst, dpos, dneg);
+            r[a] = (R)rr;
+            C zz = (C)(R)rr;
+            if (kPred) {
+                m[a] = (R)inst;
+                zz = zz + (C)(R)inst;
+            }
+            zz = zz > 0 ? zz : 0;
+            z[k] = zz;
+            Z = Z + zz;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NA; ++k)
+        if (k < n) b[a0 + k] = (V)(Z > 0 ? z[k] / Z : (C)1 / (C)n);
+}
+
+template <int P, int VAR, bool FAST>
 __global__ __launch_bounds__(kThreads) void k_up(
     int32_t j0, int32_t j1, const int32_t *__restrict__ inf_first,
     const int32_t *__restrict__ child_ptr, const int32_t *__restrict__ child_idx,
@@ -317,7 +407,12 @@ __global__ __launch_bounds__(kThreads) void k_up(
         dpos = (C)sc->dpos;
         dneg = (C)sc->dneg;
     }
-    up_infoset<P, VAR>(j, inf_first, child_ptr, child_idx, g, usign, vinf, b, r, m, dpos, dneg);
+    if (FAST)
+        up_infoset_fast<P, VAR>(j, inf_first, child_ptr, child_idx, g, usign, vinf, b, r, m, dpos,
+                                dneg);
+    else
+        up_infoset<P, VAR>(j, inf_first, child_ptr, child_idx, g, usign, vinf, b, r, m, dpos,
+                           dneg);
 }
 
 // One decision point of NextStrategy's top-down pass, accumulating the
@@ -333,6 +428,28 @@ __device__ __forceinline__ void down_infoset(int32_t j, const int32_t *__restric
     using V = typename Types<P>::V;
     using R = typename Types<P>::R;
     const int32_t a0 = inf_first[j], a1 = inf_first[j + 1];
+    const int32_t n = a1 - a0;
+    if (n <= kFastActs) {
+        // all loads at once (clamped addresses), then the stores
+        V bv[kFastActs], xv[kFastActs];
+        R sv[kFastActs];
+        const V xp = x[seq_par[a0]];
+#pragma unroll
+        for (int k = 0; k < kFastActs; ++k) {
+            const int32_t a = a0 + (k < n ? k : 0);
+            bv[k] = b[a];
+            xv[k] = x[a];
+            sv[k] = s[a];
+        }
+#pragma unroll
+        for (int k = 0; k < kFastActs; ++k) {
+            if (k < n) {
+                if (average) s[a0 + k] = sv[k] + w * (R)xv[k];
+                x[a0 + k] = xp * bv[k];
+            }
+        }
+        return;
+    }
     const V xp = x[seq_par[a0]];
     for (int32_t a = a0; a < a1; ++a) {
         if (average) s[a] = s[a] + w * (R)x[a];
@@ -356,7 +473,8 @@ __global__ __launch_bounds__(kTopThreads) void k_top(
     typename Types<P>::C usign, typename Types<P>::C *__restrict__ vinf,
     typename Types<P>::V *__restrict__ b, typename Types<P>::R *__restrict__ r,
     typename Types<P>::R *__restrict__ m, typename Types<P>::V *__restrict__ x,
-    typename Types<P>::R *__restrict__ s, const Scalars *__restrict__ sc, int average)
+    typename Types<P>::R *__restrict__ s, const Scalars *__restrict__ sc, int average,
+    int all_fast)
 {
     using R = typename Types<P>::R;
     using C = typename Types<P>::C;
@@ -369,9 +487,14 @@ __global__ __launch_bounds__(kTopThreads) void k_top(
     const R w = average ? (R)sc->w : (R)0;
     for (int lv = top_levels - 1; lv >= 0; --lv) {
         const int32_t *off = top_off + (size_t)lv * (n_roots + 1);
-        for (int32_t i = off[root] + (int32_t)threadIdx.x; i < off[root + 1]; i += kTopThreads)
-            up_infoset<P, VAR>(top_list[i], inf_first, child_ptr, child_idx, g, usign, vinf, b, r,
-                               m, dpos, dneg);
+        for (int32_t i = off[root] + (int32_t)threadIdx.x; i < off[root + 1]; i += kTopThreads) {
+            if (all_fast)
+                up_infoset_fast<P, VAR>(top_list[i], inf_first, child_ptr, child_idx, g, usign,
+                                        vinf, b, r, m, dpos, dneg);
+            else
+                up_infoset<P, VAR>(top_list[i], inf_first, child_ptr, child_idx, g, usign, vinf,
+                                   b, r, m, dpos, dneg);
+        }
         __syncthreads();
     }
     for (int lv = 0; lv < top_levels; ++lv) {
@@ -532,7 +655,15 @@ hipError_t up_t(const DevPlayer &p, int level, double usign, const void *g, cons
     using T = Types<P>;
     int32_t j0 = p.lvl_inf[level], j1 = p.lvl_inf[level + 1];
     if (j1 <= j0) return hipSuccess;
-    hipLaunchKernelGGL((k_up<P, VAR>), dim3(grid_for(j1 - j0)), dim3(kThreads), 0, st, j0, j1,
+    if (p.lvl_fast[level]) {
+        hipLaunchKernelGGL((k_up<P, VAR, true>), dim3(grid_for(j1 - j0)), dim3(kThreads), 0, st,
+                           j0, j1, p.inf_first, p.child_ptr, p.child_idx,
+                           (const typename T::V *)g, (typename T::C)usign,
+                           (typename T::C *)p.vinf, (typename T::V *)p.b, (typename T::R *)p.r,
+                           (typename T::R *)p.m, sc);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL((k_up<P, VAR, false>), dim3(grid_for(j1 - j0)), dim3(kThreads), 0, st, j0, j1,
                        p.inf_first, p.child_ptr, p.child_idx, (const typename T::V *)g,
                        (typename T::C)usign, (typename T::C *)p.vinf, (typename T::V *)p.b,
                        (typename T::R *)p.r, (typename T::R *)p.m, sc);
@@ -563,7 +694,7 @@ hipError_t top_t(const DevPlayer &p, double usign, int average, const Scalars *s
                        p.seq_par, (const typename T::V *)p.g, (typename T::C)usign,
                        (typename T::C *)p.vinf, (typename T::V *)p.b, (typename T::R *)p.r,
                        (typename T::R *)p.m, (typename T::V *)p.x, (typename T::R *)p.s, sc,
-                       average);
+                       average, p.top_fast);
     return hipGetLastError();
 }
 
