@@ -396,11 +396,11 @@ Buffers carve(Carver &c, const Sizes &z, int prec)
     b.csr_ptr = (int32_t *)c.take(4 * ((size_t)z.n_seq[0] + 1));
     b.csr_idx = (int32_t *)c.take(4 * (size_t)z.nnz);
     b.csr_val = c.take(V * (size_t)z.nnz);
-    b.csr_blk = (int32_t *)c.take(4 * ((size_t)z.n_blk_csr + 1));
+    b.csr_blk = (int32_t *)c.take(8 * ((size_t)z.n_blk_csr + 1));
     b.csc_ptr = (int32_t *)c.take(4 * ((size_t)z.n_seq[1] + 1));
     b.csc_idx = (int32_t *)c.take(4 * (size_t)z.nnz);
     b.csc_val = c.take(V * (size_t)z.nnz);
-    b.csc_blk = (int32_t *)c.take(4 * ((size_t)z.n_blk_csc + 1));
+    b.csc_blk = (int32_t *)c.take(8 * ((size_t)z.n_blk_csc + 1));
     return b;
 }
 
@@ -683,6 +683,17 @@ void permute_rows(int32_t n_rows, const std::vector<int32_t> &old_of_new_row,
     }
 }
 
+// (first row, first nonzero) of every row block, interleaved.
+std::vector<int32_t> block_extents(const std::vector<int32_t> &blk, const std::vector<int32_t> &ptr)
+{
+    std::vector<int32_t> out(2 * blk.size());
+    for (size_t i = 0; i < blk.size(); ++i) {
+        out[2 * i] = blk[i];
+        out[2 * i + 1] = ptr[(size_t)blk[i]];
+    }
+    return out;
+}
+
 std::vector<int32_t> narrow_ptr(const int64_t *ptr, size_t n)
 {
     std::vector<int32_t> out(n);
@@ -777,7 +788,8 @@ int create_impl(const cfr_game_desc *g, const cfr_options *o, cfr_solver *s)
     CHECK(h2d(B.csr_ptr, ptr32.data(), ptr32.size(), st));
     CHECK(h2d(B.csr_idx, ridx, (size_t)g->nnz, st));
     CHECK(h2d_values(B.csr_val, rval, (size_t)g->nnz, s->prec, ftmp, st));
-    CHECK(h2d(B.csr_blk, P.blk_csr.data(), P.blk_csr.size(), st));
+    std::vector<int32_t> blk_csr = block_extents(P.blk_csr, ptr32);
+    CHECK(h2d(B.csr_blk, blk_csr.data(), blk_csr.size(), st));
     CHECK(hipStreamSynchronize(st));  // host buffers below are rebuilt
     {
         std::vector<int64_t> tptr;
@@ -800,7 +812,8 @@ int create_impl(const cfr_game_desc *g, const cfr_options *o, cfr_solver *s)
         CHECK(h2d(B.csc_ptr, cptr32.data(), cptr32.size(), st));
         CHECK(h2d(B.csc_idx, cidx, (size_t)g->nnz, st));
         CHECK(h2d_values(B.csc_val, cval, (size_t)g->nnz, s->prec, ftmp, st));
-        CHECK(h2d(B.csc_blk, P.blk_csc.data(), P.blk_csc.size(), st));
+        std::vector<int32_t> blk_csc = block_extents(P.blk_csc, cptr32);
+        CHECK(h2d(B.csc_blk, blk_csc.data(), blk_csc.size(), st));
         CHECK(hipStreamSynchronize(st));
     }
     s->csr = DevMatrix{p1.n_seq, p2.n_seq, g->nnz, P.sizes.n_blk_csr, B.csr_ptr, B.csr_idx,

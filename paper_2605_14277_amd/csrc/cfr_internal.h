@@ -41,7 +41,7 @@ struct DevMatrix {
     const int32_t *ptr = nullptr;  // [n_rows+1]
     const int32_t *idx = nullptr;  // [nnz]
     const void *val = nullptr;     // [nnz] value type
-    const int32_t *blk = nullptr;  // [n_blk+1] first row of each block
+    const int32_t *blk = nullptr;  // [2*(n_blk+1)] (first row, first nonzero) of each block
 };
 
 // One player's treeplex in level order (see the runtime for the layout).
@@ -109,10 +109,15 @@ size_t compute_bytes(int prec);
 #ifndef CFR_SPMV_NONTEMPORAL
 #define CFR_SPMV_NONTEMPORAL 1
 #endif
+// 1: the FP32 modes stage products in LDS in the value type (float)
+#ifndef CFR_SPMV_LDS_VALUE
+#define CFR_SPMV_LDS_VALUE 1
+#endif
 constexpr int kSpmvThreads = 256;
 constexpr int kSpmvItems = CFR_SPMV_ITEMS;
 constexpr int kSpmvCap = kSpmvThreads * kSpmvItems;  // nonzeros staged per block
 constexpr int kSpmvRowCap = 256;                     // rows per block
+static_assert(kSpmvRowCap <= kSpmvThreads, "a block's row pointers are one per thread");
 constexpr int kDotPartials = 512;
 constexpr int kFastActs = 4;        // fast sweep path: actions per decision point
 constexpr int kFastKids = 4;        // fast sweep path: decision points below a sequence

@@ -30,6 +30,7 @@
 #include "cfr_internal.h"
 
 #include <cfloat>
+#include <type_traits>
 
 #include "cfr.h"
 
@@ -101,6 +102,12 @@ __device__ void begin_iteration(Scalars *sc, const IterParams &ip)
 // sequential loop), which the FP64 path needs to reproduce a sequential
 // evaluation bit for bit; otherwise a power-of-two group of lanes shares
 // each row and combines its partial sums with cross-lane shuffles.
+//
+// blk holds (first row, first nonzero) of every row block, so one load
+// gives the block's extent.  The loads of a block are all issued
+// unconditionally (lanes past the end read the block's first entry and
+// ignore it): index/value stream and row pointers in one round, gathers in
+// the next; the reduction then reads only LDS.
 template <int P, bool SEQ>
 __global__ __launch_bounds__(kSpmvThreads) void k_spmv(
     int32_t n_blk, const int32_t *__restrict__ blk, const int32_t *__restrict__ ptr,
@@ -110,7 +117,12 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(
 {
     using V = typename Types<P>::V;
     using C = typename Types<P>::C;
-    __shared__ C prod[kSpmvCap];
+    // products staged in LDS: the compute type, or the value type when the
+    // FP32 modes are built to stage them compactly
+    using L = typename std::conditional<(CFR_SPMV_LDS_VALUE != 0) && P != CFR_FP64, V, C>::type;
+    __shared__ L prod[kSpmvCap];
+    __shared__ int32_t s_ptr[kSpmvRowCap + 1];
+    __shared__ C red[kSpmvThreads];
 
     if (begin_sc && blockIdx.x == 0 && threadIdx.x == 0) begin_iteration(begin_sc, ip);
     int32_t bid = (int32_t)blockIdx.x;
@@ -123,30 +135,30 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(
     }
     if (bid >= n_blk) return;
     const int tid = threadIdx.x;
-    const int32_t rb = blk[bid], re = blk[bid + 1];
-    const int32_t e0 = ptr[rb], e1 = ptr[re];
-    const int32_t n = e1 - e0;
+    const int32_t rb = blk[2 * bid], e0 = blk[2 * bid + 1];
+    const int32_t nr = blk[2 * bid + 2] - rb, n = blk[2 * bid + 3] - e0;
 
     if (n > kSpmvCap) {
         // a single long row: strided partial sums, then a fixed-order tree
         C acc = 0;
         for (int32_t i = tid; i < n; i += kSpmvThreads)
             acc = acc + (C)val[e0 + i] * (C)xin[idx[e0 + i]];
-        prod[tid] = acc;
+        red[tid] = acc;
         __syncthreads();
         for (int w = kSpmvThreads / 2; w > 0; w >>= 1) {
-            if (tid < w) prod[tid] = prod[tid] + prod[tid + w];
+            if (tid < w) red[tid] = red[tid] + red[tid + w];
             __syncthreads();
         }
-        if (tid == 0) yout[rb] = (V)prod[0];
+        if (tid == 0) yout[rb] = (V)red[0];
         return;
     }
 
-    // inactive lanes read the block's first entry (any valid address), so
-    // every load is unconditional and all of them are in flight together
     int32_t c[kSpmvItems];
     V v[kSpmvItems];
     V gx[kSpmvItems];
+    // this block's row pointers: one per thread (a block has at most
+    // kSpmvRowCap = kSpmvThreads rows)
+    const int32_t pr = ptr[rb + (tid < nr ? tid : 0)];
     if (n > 0) {
 #pragma unroll
         for (int k = 0; k < kSpmvItems; ++k) {
@@ -165,14 +177,16 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(
 #pragma unroll
         for (int k = 0; k < kSpmvItems; ++k) {
             const int32_t i = k * kSpmvThreads + tid;
-            if (i < n) prod[i] = (C)v[k] * (C)gx[k];
+            if (i < n) prod[i] = (L)((C)v[k] * (C)gx[k]);
         }
     }
+    if (tid < nr) s_ptr[tid] = pr - e0;
+    if (tid == 0) s_ptr[nr] = n;
     __syncthreads();
     if (SEQ) {
-        for (int32_t r = rb + tid; r < re; r += kSpmvThreads) {
-            int32_t i = ptr[r] - e0;
-            const int32_t z = ptr[r + 1] - e0;
+        if (tid < nr) {
+            int32_t i = s_ptr[tid];
+            const int32_t z = s_ptr[tid + 1];
             C acc = 0;
             for (; i + 4 <= z; i += 4) {
                 C p0 = prod[i], p1 = prod[i + 1], p2 = prod[i + 2], p3 = prod[i + 3];
@@ -181,25 +195,24 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(
                 acc = acc + p2;
                 acc = acc + p3;
             }
-            for (; i < z; ++i) acc = acc + prod[i];
-            yout[r] = (V)acc;
+            for (; i < z; ++i) acc = acc + (C)prod[i];
+            yout[rb + tid] = (V)acc;
         }
         return;
     }
     // lanes per row: the largest power of two (<= 64) that still gives every
     // row of the block its own group, and not far above the mean row length
-    const int32_t nrows = re - rb;
-    int L = 64;
-    while (L > 1 && L * nrows > kSpmvThreads) L >>= 1;
-    while (L > 1 && L > 2 * (n / nrows + 1)) L >>= 1;
-    const int lane = tid & (L - 1);
-    const int groups = kSpmvThreads / L;
-    for (int32_t r = rb + tid / L; r < re; r += groups) {
-        const int32_t a = ptr[r] - e0, z = ptr[r + 1] - e0;
+    int Lr = 64;
+    while (Lr > 1 && Lr * nr > kSpmvThreads) Lr >>= 1;
+    while (Lr > 1 && Lr > 2 * (n / nr + 1)) Lr >>= 1;
+    const int lane = tid & (Lr - 1);
+    const int groups = kSpmvThreads / Lr;
+    for (int32_t r = tid / Lr; r < nr; r += groups) {
+        const int32_t a = s_ptr[r], z = s_ptr[r + 1];
         C acc = 0;
-        for (int32_t i = a + lane; i < z; i += L) acc = acc + prod[i];
-        for (int off = L >> 1; off > 0; off >>= 1) acc = acc + __shfl_xor(acc, off, L);
-        if (lane == 0) yout[r] = (V)acc;
+        for (int32_t i = a + lane; i < z; i += Lr) acc = acc + (C)prod[i];
+        for (int off = Lr >> 1; off > 0; off >>= 1) acc = acc + __shfl_xor(acc, off, Lr);
+        if (lane == 0) yout[rb + r] = (V)acc;
     }
 }
 
