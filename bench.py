@@ -33,10 +33,19 @@ def log(*a):
 
 
 def kernel_source_digest() -> str:
-    h = hashlib.sha256()
-    for f in ("cfr_kernels.hip", "cfr_internal.h"):
-        with open(os.path.join(ROOT, "paper_2605_14277_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    """Digest of the payoff-product kernel's source and of its tiling
+    constants: the committed HBM-traffic figures are valid only for the
+    kernel they were measured on."""
+    csrc = os.path.join(ROOT, "paper_2605_14277_amd", "csrc")
+    with open(os.path.join(csrc, "cfr_kernels.hip")) as fh:
+        text = fh.read()
+    start = text.index("// SEQ: every row is summed strictly left to right")
+    end = text.index("// ----", start)
+    h = hashlib.sha256(text[start:end].encode())
+    with open(os.path.join(csrc, "cfr_internal.h")) as fh:
+        for line in fh:
+            if "SPMV" in line or "kSpmv" in line:
+                h.update(line.encode())
     return h.hexdigest()[:16]
 
 

@@ -307,7 +307,7 @@ void plan_player(const cfr_player_desc &d, PlayerPlan &pl)
             pl.top_list[(size_t)base + (size_t)fill[root[k]]++] = k;
         pl.top_levels = lv + 1;
     }
-    if (pl.top_levels < n_levels) {
+    if (pl.top_levels < n_levels && !CFR_TOP_PARTIAL) {
         pl.top_levels = 0;
         pl.top_off.clear();
         pl.top_list.clear();

@@ -119,6 +119,11 @@ constexpr int kSpmvCap = kSpmvThreads * kSpmvItems;  // nonzeros staged per bloc
 constexpr int kSpmvRowCap = 256;                     // rows per block
 static_assert(kSpmvRowCap <= kSpmvThreads, "a block's row pointers are one per thread");
 constexpr int kDotPartials = 512;
+// 1: run the shallow levels in one launch (k_top) even when deeper levels
+// remain as per-level launches
+#ifndef CFR_TOP_PARTIAL
+#define CFR_TOP_PARTIAL 0
+#endif
 constexpr int kFastActs = 4;        // fast sweep path: actions per decision point
 constexpr int kFastKids = 4;        // fast sweep path: decision points below a sequence
 constexpr int kTopThreads = 1024;   // threads of the shallow-level block
