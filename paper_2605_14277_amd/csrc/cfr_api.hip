@@ -194,7 +194,7 @@ struct PlayerPlan {
     std::vector<int32_t> child_idx;   // [n_inf]
     std::vector<int32_t> lvl_inf;     // [n_levels+1]
     std::vector<int32_t> lvl_seq;     // [n_levels+1]
-    std::vector<uint8_t> lvl_fast;    // [n_levels]
+    std::vector<uint8_t> lvl_kind;    // [n_levels]
     int32_t top_levels = 0, n_roots = 0;
     std::vector<int32_t> top_off;     // [top_levels*(n_roots+1)]
     std::vector<int32_t> top_list;    // decision points of the shallow levels by level, then root
@@ -266,13 +266,17 @@ void plan_player(const cfr_player_desc &d, PlayerPlan &pl)
         std::vector<int32_t> fill(pl.child_ptr.begin(), pl.child_ptr.end() - 1);
         for (int32_t k = 0; k < n_inf; ++k) pl.child_idx[fill[inf_par[k]]++] = k;
     }
-    // levels whose decision points fit the fast sweep path
-    pl.lvl_fast.assign((size_t)n_levels, 1);
+    // levels whose decision points fit the fast sweep path (2: and have
+    // nothing below them)
+    pl.lvl_kind.assign((size_t)n_levels, 2);
     for (int32_t lv = 0; lv < n_levels; ++lv)
         for (int32_t k = pl.lvl_inf[lv]; k < pl.lvl_inf[lv + 1]; ++k) {
-            if (pl.inf_first[k + 1] - pl.inf_first[k] > cfr::kFastActs) pl.lvl_fast[lv] = 0;
-            for (int32_t a = pl.inf_first[k]; a < pl.inf_first[k + 1]; ++a)
-                if (pl.child_ptr[a + 1] - pl.child_ptr[a] > cfr::kFastKids) pl.lvl_fast[lv] = 0;
+            if (pl.inf_first[k + 1] - pl.inf_first[k] > cfr::kFastActs) pl.lvl_kind[lv] = 0;
+            for (int32_t a = pl.inf_first[k]; a < pl.inf_first[k + 1]; ++a) {
+                const int32_t kids = pl.child_ptr[a + 1] - pl.child_ptr[a];
+                if (kids > cfr::kFastKids) pl.lvl_kind[lv] = 0;
+                else if (kids > 0 && pl.lvl_kind[lv] == 2) pl.lvl_kind[lv] = 1;
+            }
         }
     // One launch per root subtree for the whole sweep, when every root
     // decision point's share of every level is at most kTopMaxGroup decision
@@ -546,13 +550,20 @@ struct cfr_solver {
     {
         const DevPlayer &d = buf.dp[p];
         hipError_t e;
-        for (int lv = d.n_levels - 1; lv >= d.top_levels; --lv)
+        if (d.top_levels > 0) {
+            // the whole sweep in one launch per root subtree
+            for (int lv = d.n_levels - 1; lv >= d.top_levels; --lv)
+                if ((e = cfr::launch_up_level(prec, variant, d, lv, usign, d.g, buf.sc, s)) !=
+                    hipSuccess)
+                    return e;
+            if ((e = cfr::launch_top(prec, variant, d, usign, 1, buf.sc, s)) != hipSuccess) return e;
+            return down_sweep(p, 1, d.top_levels, s);
+        }
+        // level 0's launch also does its top-down step
+        for (int lv = d.n_levels - 1; lv >= 0; --lv)
             if ((e = cfr::launch_up_level(prec, variant, d, lv, usign, d.g, buf.sc, s)) != hipSuccess)
                 return e;
-        if (d.top_levels > 0 &&
-            (e = cfr::launch_top(prec, variant, d, usign, 1, buf.sc, s)) != hipSuccess)
-            return e;
-        return down_sweep(p, 1, d.top_levels, s);
+        return down_sweep(p, 1, 1, s);
     }
 
     hipError_t down_sweep(int p, int average, int from_level, hipStream_t s)
@@ -750,7 +761,7 @@ int create_impl(const cfr_game_desc *g, const cfr_options *o, cfr_solver *s)
         d.n_levels = pl.n_levels;
         d.lvl_inf = pl.lvl_inf.data();
         d.lvl_seq = pl.lvl_seq.data();
-        d.lvl_fast = pl.lvl_fast.data();
+        d.lvl_kind = pl.lvl_kind.data();
         CHECK(h2d(d.inf_first, pl.inf_first.data(), pl.inf_first.size(), st));
         CHECK(h2d(d.seq_par, pl.seq_par.data(), pl.seq_par.size(), st));
         CHECK(h2d(d.child_ptr, pl.child_ptr.data(), pl.child_ptr.size(), st));
@@ -760,7 +771,7 @@ int create_impl(const cfr_game_desc *g, const cfr_options *o, cfr_solver *s)
         d.top_levels = pl.top_levels;
         d.n_roots = pl.n_roots;
         d.top_fast = 1;
-        for (int32_t lv = 0; lv < pl.top_levels; ++lv) d.top_fast &= pl.lvl_fast[lv];
+        for (int32_t lv = 0; lv < pl.top_levels; ++lv) d.top_fast &= pl.lvl_kind[lv] != 0;
         size_t R = cfr::accum_bytes(s->prec) * (size_t)pl.n_seq;
         CHECK(hipMemsetAsync(d.r, 0, R, st));
         CHECK(hipMemsetAsync(d.m, 0, R, st));

@@ -51,9 +51,10 @@ struct DevPlayer {
     int32_t n_levels = 0;
     const int32_t *lvl_inf = nullptr;  // host array [n_levels+1]
     const int32_t *lvl_seq = nullptr;  // host array [n_levels+1]
-    const uint8_t *lvl_fast = nullptr; // host array [n_levels]: every decision point of the
-                                       // level has <= kFastActs actions, each with
-                                       // <= kFastKids decision points below it
+    const uint8_t *lvl_kind = nullptr; // host array [n_levels]: 1 if every decision point of
+                                       // the level has <= kFastActs actions, each with
+                                       // <= kFastKids decision points below it; 2 if in
+                                       // addition nothing lies below the level; else 0
     int32_t *inf_first = nullptr;      // [n_inf+1]
     int32_t *seq_par = nullptr;        // [n_seq] parent sequence of each sequence's decision point
     int32_t *child_ptr = nullptr;      // [n_seq+1] decision points below each sequence:
@@ -86,6 +87,7 @@ hipError_t launch_up_level(int prec, int variant, const DevPlayer &p, int level,
                            const void *g, const Scalars *sc, hipStream_t st);
 hipError_t launch_down_level(int prec, const DevPlayer &p, int level, int average,
                              const Scalars *sc, hipStream_t st);
+// launch_up_level on level 0 also runs that level's top-down step.
 // ObserveUtility on levels top_levels-1..0, then the top-down pass on levels
 // 0..top_levels-1 (with averaging when `average`).
 hipError_t launch_top(int prec, int variant, const DevPlayer &p, double usign, int average,

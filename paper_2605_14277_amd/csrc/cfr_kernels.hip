@@ -327,7 +327,7 @@ __device__ __forceinline__ void up_infoset(
 // actions and children at once: offsets -> action data and child
 // pointers -> child ids -> child values.  The arithmetic and its order are
 // exactly those of up_infoset.
-template <int P, int VAR>
+template <int P, int VAR, int NC>
 __device__ __forceinline__ void up_infoset_fast(
     int32_t j, const int32_t *__restrict__ inf_first, const int32_t *__restrict__ child_ptr,
     const int32_t *__restrict__ child_idx, const typename Types<P>::V *__restrict__ g,
@@ -338,7 +338,8 @@ __device__ __forceinline__ void up_infoset_fast(
     using V = typename Types<P>::V;
     using R = typename Types<P>::R;
     using C = typename Types<P>::C;
-    constexpr int NA = kFastActs, NC = kFastKids;
+    // NC = 0: a level without children below it (no child loads at all)
+    constexpr int NA = kFastActs, NCA = NC > 0 ? NC : 1;
     constexpr bool kPred = VAR == CFR_PCFR_PLUS || VAR == CFR_PCFR;
     const int32_t a0 = inf_first[j], a1 = inf_first[j + 1];
     const int32_t n = a1 - a0;
@@ -352,19 +353,25 @@ __device__ __forceinline__ void up_infoset_fast(
         bv[k] = b[a];
         rv[k] = r[a];
         if (kPred) mv[k] = m[a];
-        c0[k] = child_ptr[a];
-        c1[k] = child_ptr[a + 1];
+        if (NC > 0) {
+            c0[k] = child_ptr[a];
+            c1[k] = child_ptr[a + 1];
+        } else {
+            c0[k] = c1[k] = 0;
+        }
     }
-    int32_t cid[NA][NC];
+    int32_t cid[NA][NCA];
+    C cv[NA][NCA];
+    if (NC > 0) {
 #pragma unroll
-    for (int k = 0; k < NA; ++k)
+        for (int k = 0; k < NA; ++k)
 #pragma unroll
-        for (int i = 0; i < NC; ++i) cid[k][i] = child_idx[c0[k] + i < c1[k] ? c0[k] + i : 0];
-    C cv[NA][NC];
+            for (int i = 0; i < NC; ++i) cid[k][i] = child_idx[c0[k] + i < c1[k] ? c0[k] + i : 0];
 #pragma unroll
-    for (int k = 0; k < NA; ++k)
+        for (int k = 0; k < NA; ++k)
 #pragma unroll
-        for (int i = 0; i < NC; ++i) cv[k][i] = vinf[cid[k][i]];
+            for (int i = 0; i < NC; ++i) cv[k][i] = vinf[cid[k][i]];
+    }
     C q[NA];
     C V_ = 0;
 #pragma unroll
@@ -401,31 +408,6 @@ __device__ __forceinline__ void up_infoset_fast(
 #pragma unroll
     for (int k = 0; k < NA; ++k)
         if (k < n) b[a0 + k] = (V)(Z > 0 ? z[k] / Z : (C)1 / (C)n);
-}
-
-template <int P, int VAR, bool FAST>
-__global__ __launch_bounds__(kThreads) void k_up(
-    int32_t j0, int32_t j1, const int32_t *__restrict__ inf_first,
-    const int32_t *__restrict__ child_ptr, const int32_t *__restrict__ child_idx,
-    const typename Types<P>::V *__restrict__ g, typename Types<P>::C usign,
-    typename Types<P>::C *__restrict__ vinf, typename Types<P>::V *__restrict__ b,
-    typename Types<P>::R *__restrict__ r, typename Types<P>::R *__restrict__ m,
-    const Scalars *__restrict__ sc)
-{
-    using C = typename Types<P>::C;
-    int32_t j = j0 + (int32_t)(blockIdx.x * kThreads + threadIdx.x);
-    if (j >= j1) return;
-    C dpos = 1, dneg = 1;
-    if (VAR == CFR_DCFR) {
-        dpos = (C)sc->dpos;
-        dneg = (C)sc->dneg;
-    }
-    if (FAST)
-        up_infoset_fast<P, VAR>(j, inf_first, child_ptr, child_idx, g, usign, vinf, b, r, m, dpos,
-                                dneg);
-    else
-        up_infoset<P, VAR>(j, inf_first, child_ptr, child_idx, g, usign, vinf, b, r, m, dpos,
-                           dneg);
 }
 
 // One decision point of NextStrategy's top-down pass, accumulating the
@@ -470,6 +452,41 @@ __device__ __forceinline__ void down_infoset(int32_t j, const int32_t *__restric
     }
 }
 
+// One level of ObserveUtility.  KIND 0: any shape; 1: fast path; 2: fast
+// path for a level with no decision points below it.  ROOT: the level under
+// the empty sequence, whose top-down step (x = 1 * b, averaging the old x)
+// needs nothing but this thread's own new strategy, so it is done here too.
+template <int P, int VAR, int KIND, bool ROOT>
+__global__ __launch_bounds__(kThreads) void k_up(
+    int32_t j0, int32_t j1, const int32_t *__restrict__ inf_first,
+    const int32_t *__restrict__ child_ptr, const int32_t *__restrict__ child_idx,
+    const typename Types<P>::V *__restrict__ g, typename Types<P>::C usign,
+    typename Types<P>::C *__restrict__ vinf, typename Types<P>::V *__restrict__ b,
+    typename Types<P>::R *__restrict__ r, typename Types<P>::R *__restrict__ m,
+    const Scalars *__restrict__ sc, const int32_t *__restrict__ seq_par,
+    typename Types<P>::V *__restrict__ x, typename Types<P>::R *__restrict__ s)
+{
+    using R = typename Types<P>::R;
+    using C = typename Types<P>::C;
+    int32_t j = j0 + (int32_t)(blockIdx.x * kThreads + threadIdx.x);
+    if (j >= j1) return;
+    C dpos = 1, dneg = 1;
+    if (VAR == CFR_DCFR) {
+        dpos = (C)sc->dpos;
+        dneg = (C)sc->dneg;
+    }
+    if (KIND == 1)
+        up_infoset_fast<P, VAR, kFastKids>(j, inf_first, child_ptr, child_idx, g, usign, vinf, b,
+                                           r, m, dpos, dneg);
+    else if (KIND == 2)
+        up_infoset_fast<P, VAR, 0>(j, inf_first, child_ptr, child_idx, g, usign, vinf, b, r, m,
+                                   dpos, dneg);
+    else
+        up_infoset<P, VAR>(j, inf_first, child_ptr, child_idx, g, usign, vinf, b, r, m, dpos,
+                           dneg);
+    if (ROOT) down_infoset<P>(j, inf_first, seq_par, b, x, s, (R)sc->w, 1);
+}
+
 // The shallow levels of one player in one launch: block `root` owns the
 // subtree below root decision point `root` (subtrees are disjoint and the
 // sweeps never cross them).  It runs ObserveUtility on levels
@@ -502,8 +519,8 @@ __global__ __launch_bounds__(kTopThreads) void k_top(
         const int32_t *off = top_off + (size_t)lv * (n_roots + 1);
         for (int32_t i = off[root] + (int32_t)threadIdx.x; i < off[root + 1]; i += kTopThreads) {
             if (all_fast)
-                up_infoset_fast<P, VAR>(top_list[i], inf_first, child_ptr, child_idx, g, usign,
-                                        vinf, b, r, m, dpos, dneg);
+                up_infoset_fast<P, VAR, kFastKids>(top_list[i], inf_first, child_ptr, child_idx, g,
+                                                   usign, vinf, b, r, m, dpos, dneg);
             else
                 up_infoset<P, VAR>(top_list[i], inf_first, child_ptr, child_idx, g, usign, vinf,
                                    b, r, m, dpos, dneg);
@@ -661,26 +678,34 @@ hipError_t spmv_t(const DevMatrix &A, const void *xin, void *yout, int xcd_remap
     return hipGetLastError();
 }
 
+template <int P, int VAR, int KIND, bool ROOT>
+hipError_t up_launch(const DevPlayer &p, int32_t j0, int32_t j1, double usign, const void *g,
+                     const Scalars *sc, hipStream_t st)
+{
+    using T = Types<P>;
+    hipLaunchKernelGGL((k_up<P, VAR, KIND, ROOT>), dim3(grid_for(j1 - j0)), dim3(kThreads), 0, st,
+                       j0, j1, p.inf_first, p.child_ptr, p.child_idx, (const typename T::V *)g,
+                       (typename T::C)usign, (typename T::C *)p.vinf, (typename T::V *)p.b,
+                       (typename T::R *)p.r, (typename T::R *)p.m, sc, p.seq_par,
+                       (typename T::V *)p.x, (typename T::R *)p.s);
+    return hipGetLastError();
+}
+
 template <int P, int VAR>
 hipError_t up_t(const DevPlayer &p, int level, double usign, const void *g, const Scalars *sc,
                 hipStream_t st)
 {
-    using T = Types<P>;
     int32_t j0 = p.lvl_inf[level], j1 = p.lvl_inf[level + 1];
     if (j1 <= j0) return hipSuccess;
-    if (p.lvl_fast[level]) {
-        hipLaunchKernelGGL((k_up<P, VAR, true>), dim3(grid_for(j1 - j0)), dim3(kThreads), 0, st,
-                           j0, j1, p.inf_first, p.child_ptr, p.child_idx,
-                           (const typename T::V *)g, (typename T::C)usign,
-                           (typename T::C *)p.vinf, (typename T::V *)p.b, (typename T::R *)p.r,
-                           (typename T::R *)p.m, sc);
-        return hipGetLastError();
+    const int kind = p.lvl_kind[level];
+    if (level == 0) {
+        if (kind == 1) return up_launch<P, VAR, 1, true>(p, j0, j1, usign, g, sc, st);
+        if (kind == 2) return up_launch<P, VAR, 2, true>(p, j0, j1, usign, g, sc, st);
+        return up_launch<P, VAR, 0, true>(p, j0, j1, usign, g, sc, st);
     }
-    hipLaunchKernelGGL((k_up<P, VAR, false>), dim3(grid_for(j1 - j0)), dim3(kThreads), 0, st, j0, j1,
-                       p.inf_first, p.child_ptr, p.child_idx, (const typename T::V *)g,
-                       (typename T::C)usign, (typename T::C *)p.vinf, (typename T::V *)p.b,
-                       (typename T::R *)p.r, (typename T::R *)p.m, sc);
-    return hipGetLastError();
+    if (kind == 1) return up_launch<P, VAR, 1, false>(p, j0, j1, usign, g, sc, st);
+    if (kind == 2) return up_launch<P, VAR, 2, false>(p, j0, j1, usign, g, sc, st);
+    return up_launch<P, VAR, 0, false>(p, j0, j1, usign, g, sc, st);
 }
 
 template <int P>
