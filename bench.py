@@ -49,9 +49,10 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, digest: str):
+def measured_traffic(kernel: str, digest: str, tiling: dict):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they
-    were taken on the current kernel source; else None."""
+    were taken on the current kernel source with the same tiling; else
+    None."""
     path = os.path.join(ROOT, "profiles", "spmv_traffic.json")
     try:
         with open(path) as f:
@@ -59,7 +60,7 @@ def measured_traffic(kernel: str, digest: str):
     except OSError:
         return None
     ent = rec.get(kernel)
-    if not ent or ent.get("kernel_digest") != digest:
+    if not ent or ent.get("kernel_digest") != digest or ent.get("tiling") != tiling:
         return None
     return ent.get("bytes_per_launch")
 
@@ -110,17 +111,272 @@ def copy_probe(torch, nbytes: int = 1600 << 20, reps: int = 5):
                       "ms_per_copy": ms, "copy_GBs": 2 * nbytes / (ms * 1e-3) / 1e9}), flush=True)
 
 
+def solve_alone(cfr, g, variant, target, max_it, K, precision):
+    """One game solved alone with the same stopping rule as in a batch:
+    checks every K iterations, stop at exploitability <= target or max_it."""
+    s = cfr.Solver(g, precision=precision)
+    t0 = time.perf_counter()
+    while True:
+        s.step(K, variant, "alternating")
+        e = s.exploitability("average")["expl"]
+        if e <= target or s.iteration >= max_it:
+            break
+    el = time.perf_counter() - t0
+    it = s.iteration
+    s.close()
+    return el, it, e
+
+
+def bench_batched(args, torch):
+    """Many games of uneven size solved together (one batch, every launch
+    covering all games still iterating) against the same games solved one at
+    a time on the same GPU with the same stopping rule."""
+    import numpy as np
+
+    import gamegen as gg
+    import paper_2605_14277_amd as cfr
+
+    n, K, max_it = args.games, args.check_every, args.max_iterations
+    variant, precision = args.variant or "pcfr+", args.precision or "fp32_acc64"
+    t0 = time.perf_counter()
+    specs = gg.batch_specs(n)
+    games = [gg.batch_game(sp) for sp in specs]
+    gen_s = time.perf_counter() - t0
+    targets = [args.rel_target * gg.payoff_range(g) for g in games]
+    nnz = np.array([g.nnz for g in games])
+    log(f"[bench] {n} games generated in {gen_s:.1f}s: nnz total {nnz.sum():.3e}, "
+        f"median {np.median(nnz):.3e}, max {nnz.max():.3e}")
+    torch.cuda.set_device(0)
+    units = np.sum([cfr.Batch.game_size(g) for g in games], axis=0)
+    b = cfr.Batch([units[0], units[1]], [units[2], units[3]], int(units[4]), max_games=n,
+                  precision=precision, mode="alternating", check_every=K,
+                  use_graph=not args.no_graph)
+    t0 = time.perf_counter()
+    ids = [b.add(g, variant, target=tg, max_iterations=max_it) for g, tg in zip(games, targets)]
+    torch.cuda.synchronize()
+    add_s = time.perf_counter() - t0
+    log(f"[bench] batch workspace {b.workspace_bytes / 1e9:.1f} GB, games added in {add_s:.1f}s")
+    t0 = time.perf_counter()
+    tiling = b.tune(reps=args.tune_reps)
+    tune_s = time.perf_counter() - t0
+    log(f"[bench] tuner chose {tiling} in {tune_s:.1f}s")
+
+    torch.cuda.synchronize()
+    finish = {}
+    t0 = time.perf_counter()
+    while True:
+        left = b.run(K)
+        now = time.perf_counter() - t0
+        for gid in ids:
+            if gid not in finish and b.status(gid)["state"] == "done":
+                finish[gid] = now
+        if left == 0:
+            break
+    wall = time.perf_counter() - t0
+    st = [b.status(gid) for gid in ids]
+    iters = np.array([x["iterations"] for x in st])
+    reached = int(sum(x["reached_target"] for x in st))
+    done_t = np.array([finish[gid] for gid in ids])
+    log(f"[bench] batch: {n} games in {wall:.2f}s ({n / wall:.2f} solves/s); {reached} reached "
+        f"the target, iterations median {np.median(iters):.0f} max {iters.max()}")
+    b.close()
+
+    # one game at a time, same games, variant, stopping rule and precision
+    idx = list(range(0, n, max(1, args.baseline_stride)))
+    seq_s, seq_it, seq_e = 0.0, [], []
+    for i in idx:
+        el, it, e = solve_alone(cfr, games[i], variant, targets[i], max_it, K, precision)
+        seq_s += el
+        seq_it.append(it)
+        seq_e.append(e)
+    scale = n / len(idx)
+    seq_total = seq_s * scale
+    same_iters = all(seq_it[j] == iters[i] for j, i in enumerate(idx))
+    log(f"[bench] one at a time: {len(idx)} games in {seq_s:.2f}s -> {n / seq_total:.2f} solves/s "
+        f"(same iteration counts as in the batch: {same_iters})")
+    plain = None
+    if args.plain_stride > 0:
+        pidx = list(range(0, n, args.plain_stride))
+        ps, pr = 0.0, 0
+        for i in pidx:
+            el, it, e = solve_alone(cfr, games[i], "vanilla", targets[i], max_it, K, "fp32_acc64")
+            ps += el
+            pr += int(e <= targets[i])
+        plain = {"games": len(pidx), "seconds": ps, "solves_per_s": len(pidx) / ps,
+                 "reached_target": pr, "variant": "vanilla", "max_iterations": max_it}
+        log(f"[bench] plain CFR one at a time: {len(pidx)} games in {ps:.2f}s, {pr} reached")
+
+    out = {
+        "metric": "batched solves/s to expl 1e-3 of the payoff range",
+        "value": n / wall,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": int(iters.max()),
+        "warmup": 0,
+        "ms_per_step": wall * 1e3 / max(1, int(iters.max())),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "fp32_acc64": "f32+f64acc"}[precision],
+        "data": "synthetic",
+        "config": {"workload": f"batch of {n} games, {variant}, alternating, {precision}, "
+                               f"target {args.rel_target:g} of the payoff range or {max_it} "
+                               f"iterations, checks every {K}",
+                   "games": n, "nnz_total": int(nnz.sum()), "nnz_median": float(np.median(nnz)),
+                   "nnz_max": int(nnz.max()), "graph": not args.no_graph},
+        "batch": {"seconds": wall, "solves_per_s": n / wall, "reached_target": reached,
+                  "iterations_median": float(np.median(iters)), "iterations_max": int(iters.max()),
+                  "finish_p50_s": float(np.percentile(done_t, 50)),
+                  "finish_p99_s": float(np.percentile(done_t, 99)), "tiling": tiling,
+                  "tune_s": tune_s, "add_s": add_s, "generate_s": gen_s},
+        "one_at_a_time": {"games_timed": len(idx), "seconds_timed": seq_s,
+                          "solves_per_s": n / seq_total, "same_iterations": bool(same_iters)},
+        "speedup_vs_one_at_a_time": seq_total / wall,
+        "plain_cfr_one_at_a_time": plain,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_serving(args, torch):
+    """Requests arriving as Poisson streams, served with continuous batching
+    (games join the batch at check boundaries while others iterate), against
+    one-at-a-time FIFO service of the same requests with the same solver."""
+    import numpy as np
+
+    import gamegen as gg
+    import paper_2605_14277_amd as cfr
+    from paper_2605_14277_amd import serve
+
+    K, max_it, precision = args.check_every, args.max_iterations, args.precision or "fp32_acc64"
+    rates = [float(r) for r in args.rates.split(",")]
+    t0 = time.perf_counter()
+    pool_games = [gg.batch_game(sp) for sp in gg.batch_specs(args.pool)]
+    gen_s = time.perf_counter() - t0
+    ranges = [gg.payoff_range(g) for g in pool_games]
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        prepared = list(ex.map(lambda g: serve.Prepared(g, precision), pool_games))
+    prep_s = time.perf_counter() - t0
+    nnz = np.array([g.nnz for g in pool_games])
+    log(f"[bench] pool of {args.pool} games (nnz median {np.median(nnz):.3e}, max {nnz.max():.3e}) "
+        f"generated in {gen_s:.1f}s, prepared in {prep_s:.1f}s")
+    rng = np.random.Generator(np.random.PCG64(5000))
+    n = args.requests
+    which = rng.integers(0, args.pool, size=n)
+    rel = rng.choice([1e-2, 1e-3], size=n)
+    var = rng.choice(["cfr+", "dcfr"], size=n)
+    gaps = rng.exponential(1.0, size=n)
+    budget = int(args.budget_gb * 1e9)
+    mix = np.sum([p.units for p in prepared], axis=0) / args.pool
+    seq, inf, nz = serve.capacities_for_bytes(budget, mix, args.max_games, precision)
+    log(f"[bench] device budget {budget / 1e9:.0f} GB -> capacity {nz:.3e} nonzeros, "
+        f"{args.max_games} slots")
+
+    # one game at a time: each distinct request solved alone once
+    service = {}
+    t0 = time.perf_counter()
+    for k in range(n):
+        key = (int(which[k]), str(var[k]), float(rel[k]))
+        if key not in service:
+            el, it, e = solve_alone(cfr, pool_games[key[0]], key[1], key[2] * ranges[key[0]], max_it,
+                                    K, precision)
+            service[key] = (el, it)
+    log(f"[bench] {len(service)} distinct requests solved alone in {time.perf_counter() - t0:.1f}s")
+    svc = np.array([service[(int(which[k]), str(var[k]), float(rel[k]))][0] for k in range(n)])
+
+    per_rate = {}
+    for rate in rates:
+        arrivals = np.cumsum(gaps / rate)
+        reqs = [{"arrival": float(arrivals[k]), "prepared": int(which[k]), "variant": str(var[k]),
+                 "target": float(rel[k] * ranges[which[k]]), "max_iterations": max_it}
+                for k in range(n)]
+        srv = serve.Server(seq, inf, nz, max_games=args.max_games, precision=precision,
+                           check_every=K)
+        t0 = time.perf_counter()
+        out = srv.serve(reqs, prepared=prepared)
+        srv.close()
+        lat = np.array([o["latency"] for o in out])
+        span = max(o["finished"] for o in out) - float(arrivals[0])
+        same = all(out[k]["iterations"] == service[(int(which[k]), str(var[k]),
+                                                    float(rel[k]))][1] for k in range(n))
+        seq_lat = serve.sequential_latencies(arrivals, svc)
+        seq_span = float(np.max(arrivals + seq_lat)) - float(arrivals[0])
+        per_rate[str(int(rate))] = {
+            "served": {"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+                       "solves_per_s": n / span, "reached_target": int(sum(o["reached_target"]
+                                                                           for o in out)),
+                       "same_iterations_as_alone": bool(same)},
+            "one_at_a_time": {"p50_s": float(np.percentile(seq_lat, 50)),
+                              "p99_s": float(np.percentile(seq_lat, 99)),
+                              "solves_per_s": n / seq_span},
+        }
+        log(f"[bench] {rate:g} req/s: served p50 {np.percentile(lat, 50) * 1e3:.0f} ms, p99 "
+            f"{np.percentile(lat, 99) * 1e3:.0f} ms, {n / span:.1f} solves/s; one at a time p50 "
+            f"{np.percentile(seq_lat, 50) * 1e3:.0f} ms, p99 {np.percentile(seq_lat, 99) * 1e3:.0f} ms, "
+            f"{n / seq_span:.1f} solves/s")
+    for p in prepared:
+        p.close()
+    mid = per_rate[str(int(rates[len(rates) // 2]))]
+    out = {
+        "metric": "served solves/s and p50/p99 latency to expl 1e-2/1e-3 of the payoff range",
+        "value": mid["served"]["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": n,
+        "warmup": 0,
+        "ms_per_step": None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "fp32_acc64": "f32+f64acc"}[precision],
+        "data": "synthetic",
+        "config": {"workload": f"{n} requests per rate, Poisson arrivals at {args.rates} req/s, "
+                               f"games from a pool of {args.pool} of the batch distribution, "
+                               f"CFR+ or DCFR, target 1e-2 or 1e-3 of the payoff range or "
+                               f"{max_it} iterations, checks every {K}, {args.budget_gb:g} GB "
+                               f"device budget, {args.max_games} slots",
+                   "value_rate": rates[len(rates) // 2]},
+        "rates": per_rate,
+        "pool": {"games": args.pool, "nnz_median": float(np.median(nnz)),
+                 "nnz_max": int(nnz.max()), "generate_s": gen_s, "prepare_s": prep_s},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--config", default="cfg3", choices=["cfg1", "cfg2", "cfg2_d8", "cfg3"])
+    ap.add_argument("--config", default="cfg3",
+                    choices=["cfg1", "cfg2", "cfg2_d8", "cfg3", "batch", "serve"])
+    ap.add_argument("--games", type=int, default=256, help="batch: number of games")
+    ap.add_argument("--check-every", type=int, default=10, help="batch: iterations per check")
+    ap.add_argument("--max-iterations", type=int, default=2000, help="batch: iteration limit")
+    ap.add_argument("--rel-target", type=float, default=1e-3,
+                    help="batch: exploitability target as a fraction of the payoff range")
+    ap.add_argument("--tune-reps", type=int, default=5, help="batch: autotuner launches each")
+    ap.add_argument("--baseline-stride", type=int, default=1,
+                    help="batch: solve every k-th game alone for the one-at-a-time rate")
+    ap.add_argument("--rates", default="50,200,800", help="serve: arrival rates (req/s)")
+    ap.add_argument("--requests", type=int, default=128, help="serve: requests per rate")
+    ap.add_argument("--pool", type=int, default=64, help="serve: distinct games")
+    ap.add_argument("--budget-gb", type=float, default=200.0, help="serve: device budget")
+    ap.add_argument("--max-games", type=int, default=256, help="serve: game slots")
+    ap.add_argument("--plain-stride", type=int, default=0,
+                    help="batch: also solve every k-th game alone with vanilla CFR (0: skip)")
     ap.add_argument("--variant", default=None)
     ap.add_argument("--mode", default=None)
     ap.add_argument("--precision", default=None)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--spmv-order", default="default", choices=["default", "sequential", "parallel"])
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default product tiling instead of running the autotuner")
+    ap.add_argument("--tiling", default=None,
+                    help="fixed product tiling 'items_Ay,items_ATx:rows_Ay,rows_ATx' "
+                         "(skips the autotuner)")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle time for the CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -138,6 +394,12 @@ def main():
 
     if args.copy_probe:
         copy_probe(torch)
+        return
+    if args.config == "batch":
+        bench_batched(args, torch)
+        return
+    if args.config == "serve":
+        bench_serving(args, torch)
         return
 
     import gamegen as gg
@@ -160,6 +422,17 @@ def main():
                    spmv_order=args.spmv_order)
     torch.cuda.synchronize()
     log(f"[bench] cfr_create {time.perf_counter() - t0:.1f}s, workspace {s.workspace_bytes / 1e9:.2f} GB")
+    tune_s = None
+    if args.tiling:
+        it_s, rows_s = args.tiling.split(":")
+        s.tiling = {"items": [int(v) for v in it_s.split(",")],
+                    "rows": [int(v) for v in rows_s.split(",")]}
+    elif not args.no_tune:
+        t0 = time.perf_counter()
+        s.tune(reps=10)
+        tune_s = time.perf_counter() - t0
+    tiling = s.tiling
+    log(f"[bench] product tiling {tiling}" + (f" (autotuner, {tune_s:.1f}s)" if tune_s else ""))
 
     s.step(args.warmup, variant, mode)
     torch.cuda.synchronize()
@@ -194,7 +467,7 @@ def main():
     avg_ms = tot / nl
     achieved = by / (avg_ms * 1e-3) / 1e9
     digest = kernel_source_digest()
-    traffic = measured_traffic(kname, digest)
+    traffic = measured_traffic(kname, digest, tiling)
     e = s.exploitability("average")
     log(f"[bench] {kname}: {nl} launches, {avg_ms * 1e3:.1f} us avg, {achieved:.0f} GB/s "
         f"(algorithmic); expl after {s.iteration} it = {e['expl']:.4g}")
@@ -226,7 +499,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {g.name}, {variant}, {mode}, {precision}",
                    "nnz": g.nnz, "n_seq": list(g.n_seq), "terminals": g.tree.n_terminals
-                   if g.tree is not None else None, "graph": not args.no_graph},
+                   if g.tree is not None else None, "graph": not args.no_graph,
+                   "tiling": tiling, "tuned": tune_s is not None},
         "nnz_iters_per_s": g.nnz * its,
         "algorithmic_gb_per_iter": alg / 1e9,
         "iteration_gbs": alg / (ms_per_step * 1e-3) / 1e9,

@@ -77,13 +77,15 @@ class PublicTree:
 
 def make_public_tree(rng: np.random.Generator, max_depth: int,
                      branch_lo: int, branch_hi: int, p_stop: float,
-                     fixed_branching: bool = False) -> PublicTree:
+                     fixed_branching: bool = False,
+                     branch_p_hi: float | None = None) -> PublicTree:
     """Breadth-first random public tree.
 
     Each internal node draws its branching uniformly from
-    {branch_lo..branch_hi}; each child above ``max_depth`` becomes terminal
-    with probability ``p_stop``; children at ``max_depth`` are terminal.  The
-    root never stops.
+    {branch_lo..branch_hi} (or, with ``branch_p_hi``, branch_hi with that
+    probability and branch_lo otherwise); each child above ``max_depth``
+    becomes terminal with probability ``p_stop``; children at ``max_depth``
+    are terminal.  The root never stops.
     """
     if max_depth < 1:
         raise ValueError("max_depth must be >= 1")
@@ -99,6 +101,8 @@ def make_public_tree(rng: np.random.Generator, max_depth: int,
             break
         if fixed_branching:
             k = np.full(cur.size, branch_lo, np.int64)
+        elif branch_p_hi is not None:
+            k = np.where(rng.random(cur.size) < branch_p_hi, branch_hi, branch_lo).astype(np.int64)
         else:
             k = rng.integers(branch_lo, branch_hi + 1, size=cur.size)
         nchild_of[d] = (cur, k)
@@ -498,11 +502,12 @@ def build_game(tree: PublicTree, S1: int, S2: int, payoff_kind: str,
 
 def public_game(seed: int, S: int, max_depth: int, branch_lo: int, branch_hi: int,
                 p_stop: float, payoff_kind: str = "iid", name: str = "game",
-                fixed_branching: bool = False, S2: int | None = None) -> Game:
+                fixed_branching: bool = False, S2: int | None = None,
+                branch_p_hi: float | None = None) -> Game:
     """One seeded public-tree game (tree draws first, then payoffs)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     tree = make_public_tree(rng, max_depth, branch_lo, branch_hi, p_stop,
-                            fixed_branching=fixed_branching)
+                            fixed_branching=fixed_branching, branch_p_hi=branch_p_hi)
     S1 = S
     S2 = S if S2 is None else S2
     T = tree.n_terminals
@@ -602,6 +607,60 @@ def cfg3() -> Game:
     sign(s1-s2)*pot with pot ~ U[1,8] per terminal, ~1e5 terminals,
     ~1e8 payoff nonzeros (ties are exact zeros and are not stored)."""
     return _seed_select(3000, 96000, 106000, 32, 10, 2, 4, 0.0, "showdown", "cfg3-large")
+
+
+# --------------------------------------------------------------------------
+# Many games of uneven size (batched solving and the request stream)
+# --------------------------------------------------------------------------
+
+def batch_specs(n: int = 256, seed: int = 4000, t_lo: float = 1e2, t_hi: float = 1e5,
+                s_lo: int = 3, s_hi: int = 32, d_lo: int = 4, d_hi: int = 10) -> list:
+    """Sizes of n games: signals S ~ U{s_lo..s_hi}, a target terminal count
+    T log-uniform in [t_lo, t_hi], depth D ~ U{d_lo..d_hi}; every internal
+    node branches to floor(T^(1/D)) or one more, the larger with probability
+    T^(1/D) - floor(T^(1/D)), so the expected terminal count is T.  Game k
+    takes seed `seed * 10 + k`; payoffs are U[-1,1]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    S = rng.integers(s_lo, s_hi + 1, size=n)
+    T = np.exp(rng.uniform(np.log(t_lo), np.log(t_hi), size=n))
+    D = rng.integers(d_lo, d_hi + 1, size=n)
+    out = []
+    for k in range(n):
+        root = float(T[k]) ** (1.0 / int(D[k]))
+        lo = max(1, int(np.floor(root)))
+        out.append({"index": k, "seed": seed * 10 + k, "S": int(S[k]), "T_target": float(T[k]),
+                    "depth": int(D[k]), "branch_lo": lo, "branch_p_hi": root - lo})
+    return out
+
+
+def batch_game(spec: dict) -> Game:
+    g = public_game(spec["seed"], S=spec["S"], max_depth=spec["depth"],
+                    branch_lo=spec["branch_lo"], branch_hi=spec["branch_lo"] + 1, p_stop=0.0,
+                    payoff_kind="iid", name=f"batch-{spec['index']}",
+                    branch_p_hi=spec["branch_p_hi"])
+    g.meta["spec"] = dict(spec)
+    return g
+
+
+def payoff_range(g: Game) -> float:
+    """max - min of the terminal payoffs before chance weighting."""
+    if g.payoff_kind == "showdown":
+        return 2.0 * float(np.max(g.payoff))
+    return float(np.max(g.payoff) - np.min(g.payoff))
+
+
+def request_stream(n: int, rate: float, seed: int = 5000) -> list:
+    """Poisson arrivals at `rate` per second: arrival times, game sizes from
+    batch_specs' distribution, an exploitability target of 1e-2 or 1e-3 of
+    the payoff range and CFR+ or DCFR, each with probability 1/2."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    gaps = rng.exponential(1.0 / rate, size=n)
+    rel = rng.choice([1e-2, 1e-3], size=n)
+    var = rng.choice(["cfr+", "dcfr"], size=n)
+    specs = batch_specs(n, seed=seed + 1)
+    t = np.cumsum(gaps)
+    return [{"arrival": float(t[k]), "spec": specs[k], "rel_target": float(rel[k]),
+             "variant": str(var[k])} for k in range(n)]
 
 
 CONFIGS = {"cfg1": cfg1, "cfg2": cfg2, "cfg2_d8": cfg2_literal, "cfg3": cfg3}

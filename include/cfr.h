@@ -212,9 +212,150 @@ int cfr_kernel_timing(cfr_solver *s, int enable);
 int cfr_kernel_stats(cfr_solver *s, int kernel, int64_t *launches, double *total_ms,
                      double *bytes_per_launch);
 
+/* Payoff-product tiling: nonzeros per thread (4, 8 or 16; a block stages
+ * 256 times that many) and rows per block (64..256) of the A y product
+ * (index 0) and of the A^T x product (index 1).  Rows longer than one
+ * block's capacity are summed by a tree in every order.                    */
+typedef struct cfr_spmv_tiling {
+    int items[2];
+    int rows[2];
+} cfr_spmv_tiling;
+
+/* Reads / sets the solver's tiling (CFR_EINVAL outside the ranges above).  */
+int cfr_get_tiling(cfr_solver *s, cfr_spmv_tiling *t);
+int cfr_set_tiling(cfr_solver *s, const cfr_spmv_tiling *t);
+
+/* Autotuner: times every supported tiling of each product on this game
+ * (reps launches each, HIP events on the solver's stream), keeps the
+ * fastest and writes it to *chosen (may be NULL).  Overwrites only the
+ * products' outputs, which every iteration recomputes first.  Waits for
+ * the stream.                                                              */
+int cfr_tune(cfr_solver *s, int reps, cfr_spmv_tiling *chosen);
+
 /* Releases the solver (and the workspace it allocated, if any).  NULL is
  * accepted.                                                                */
 int cfr_destroy(cfr_solver *s);
+
+/* ---- batches of games ----------------------------------------------------
+ * Many independent games solved together (the repeated-game and research
+ * use cases of Section 6): every launch of an iteration covers all games
+ * that are still iterating, and one iteration of the whole batch is one
+ * captured HIP graph, so the launch count per iteration does not grow with
+ * the number of games.  Each game has its own regret minimiser, iteration
+ * counter and stopping rule; no reduction mixes two games, so a game's
+ * results do not depend on the other games in the batch.
+ *
+ * Storage: one device workspace with per-player arenas of sequence and
+ * decision-point indices and an arena of payoff nonzeros.  A game takes
+ * n_seq + 1 sequence indices and n_inf + 1 decision-point indices per
+ * player and nnz nonzeros (cfr_batch_game_size); cfr_batch_add fails with
+ * CFR_ENOMEM when no free range or slot fits, and cfr_batch_remove returns
+ * the ranges.  Checks: every check_every iterations the average strategy
+ * of each iterating game is evaluated; a game stops when its
+ * exploitability is at most its target or its iteration count has reached
+ * its limit.  A game added between two checks starts at the next check, so
+ * its iterates and checks are those of the game solved alone with the same
+ * check period.                                                           */
+typedef struct cfr_batch cfr_batch;
+
+typedef struct cfr_batch_options {
+    int precision;             /* CFR_FP64 | CFR_FP32 | CFR_FP32_ACC64           */
+    int mode;                  /* CFR_SIMULTANEOUS | CFR_ALTERNATING (all games) */
+    int spmv_order;            /* CFR_SPMV_*                                     */
+    int64_t max_games;         /* game slots                                     */
+    int64_t seq_capacity[2];   /* sequence indices per player                    */
+    int64_t inf_capacity[2];   /* decision-point indices per player              */
+    int64_t nnz_capacity;      /* payoff nonzeros                                */
+    int64_t check_every;       /* iterations between checks (>= 1)              */
+    void *stream;              /* hipStream_t; NULL = null stream                */
+    int device;                /* HIP device ordinal                             */
+    int use_graph;             /* 1: replay a captured graph per iteration       */
+} cfr_batch_options;
+
+typedef struct cfr_game_params {
+    int variant;                    /* CFR_VANILLA .. CFR_PCFR                  */
+    int avg_weight;                 /* CFR_AVG_*                                */
+    double dcfr_alpha, dcfr_beta, dcfr_gamma;
+    double target_exploitability;   /* stop at a check with expl <= this (0: never) */
+    int64_t max_iterations;         /* stop at a check at or beyond this (0: never) */
+} cfr_game_params;
+
+enum { CFR_GAME_ACTIVE = 0, CFR_GAME_WAITING = 1, CFR_GAME_DONE = 2 };
+
+typedef struct cfr_game_status {
+    int state;             /* CFR_GAME_*                                        */
+    int reached_target;    /* 1 if it stopped on its exploitability target      */
+    int64_t iterations;    /* iterations completed                              */
+    int64_t evaluated_at;  /* iteration of the last evaluation (-1: none)       */
+    double exploitability; /* average-strategy exploitability at that evaluation */
+} cfr_game_status;
+
+/* Defaults: FP32_ACC64, alternating, 256 slots, capacities 0 (must be
+ * set), check every 10 iterations, null stream, device 0, graphs on; game
+ * parameters: PCFR+, default averaging, DCFR 1.5/0/2, no target, no limit. */
+int cfr_batch_options_default(cfr_batch_options *opt);
+int cfr_game_params_default(cfr_game_params *gp);
+
+/* Index units a game takes in a batch: out[0..1] sequence indices of each
+ * player, out[2..3] decision-point indices, out[4] nonzeros.  Host only.  */
+int cfr_batch_game_size(const cfr_game_desc *game, int64_t *out);
+
+/* Device bytes of a batch with these capacities.                         */
+int cfr_batch_workspace_size(const cfr_batch_options *opt, size_t *bytes);
+
+/* Allocates the batch's workspace (library-owned) on opt->device.        */
+int cfr_batch_create(const cfr_batch_options *opt, cfr_batch **out);
+
+/* Validates and adds a game (copied; the caller may free its arrays).
+ * *id receives the game's handle.  CFR_ENOMEM: no free slot or range.    */
+int cfr_batch_add(cfr_batch *b, const cfr_game_desc *game, const cfr_game_params *gp,
+                  int64_t *id);
+
+/* A game validated, laid out in level order and converted to one
+ * precision's value type on the host, ready to be added to batches of that
+ * precision: cfr_prepare touches no device and may run on worker threads
+ * while a batch iterates (the serving path prepares arriving requests this
+ * way, so that admission is only the copy to the device).  A prepared game
+ * owns copies of everything it needs and may be added any number of times. */
+typedef struct cfr_prepared cfr_prepared;
+int cfr_prepare(const cfr_game_desc *game, int precision, cfr_prepared **out);
+/* Index units of a prepared game, as cfr_batch_game_size.                 */
+int cfr_prepared_size(const cfr_prepared *p, int64_t *out);
+/* As cfr_batch_add; CFR_EINVAL if the batch's precision differs.          */
+int cfr_batch_add_prepared(cfr_batch *b, const cfr_prepared *p, const cfr_game_params *gp,
+                           int64_t *id);
+int cfr_prepared_destroy(cfr_prepared *p);
+
+/* Runs up to n iterations of the iterating games with checks every
+ * check_every iterations, stopping early when no game is left; waits for
+ * the stream at each check.  *n_active (may be NULL) receives the number
+ * of games still iterating or waiting to start.                          */
+int cfr_batch_run(cfr_batch *b, int64_t n, int64_t *n_active);
+
+int cfr_batch_status(cfr_batch *b, int64_t id, cfr_game_status *out);
+
+/* As cfr_strategy / cfr_exploitability for one game of the batch (the
+ * evaluation also becomes the game's last evaluation).                    */
+int cfr_batch_strategy(cfr_batch *b, int64_t id, int player, int kind, double *out,
+                       int64_t len);
+int cfr_batch_exploitability(cfr_batch *b, int64_t id, int kind, double *out);
+
+/* Frees a game's slot and ranges.                                         */
+int cfr_batch_remove(cfr_batch *b, int64_t id);
+
+/* Tiling of the batch's products, as for a single solver; cfr_batch_tune
+ * times the candidates on the games currently iterating.                  */
+int cfr_batch_get_tiling(cfr_batch *b, cfr_spmv_tiling *t);
+int cfr_batch_set_tiling(cfr_batch *b, const cfr_spmv_tiling *t);
+int cfr_batch_tune(cfr_batch *b, int reps, cfr_spmv_tiling *chosen);
+
+/* Total launches and milliseconds of the products of the last
+ * cfr_batch_run while timing was enabled, as cfr_kernel_stats.           */
+int cfr_batch_kernel_timing(cfr_batch *b, int enable);
+int cfr_batch_kernel_stats(cfr_batch *b, int kernel, int64_t *launches, double *total_ms,
+                           double *bytes_per_launch);
+
+int cfr_batch_destroy(cfr_batch *b);
 
 /* Message of the last failing call on this thread ("" if none).           */
 const char *cfr_last_error(void);

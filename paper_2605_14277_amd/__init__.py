@@ -26,6 +26,7 @@ MODES = {"simultaneous": 0, "alternating": 1}
 KINDS = {"current": 0, "average": 1}
 AVG = {"default": 0, "uniform": 1, "linear": 2, "quadratic": 3, "pow_gamma": 4}
 SPMV_ORDER = {"default": 0, "sequential": 1, "parallel": 2}
+GAME_STATES = {0: "active", 1: "waiting", 2: "done"}
 ERRORS = {CFR_EINVAL: "EINVAL", CFR_ENOMEM: "ENOMEM", CFR_EDEVICE: "EDEVICE",
           CFR_ESTATE: "ESTATE", CFR_EUNSUPPORTED: "EUNSUPPORTED"}
 
@@ -54,6 +55,29 @@ class cfr_options(C.Structure):
                 ("use_graph", C.c_int), ("spmv_order", C.c_int)]
 
 
+class cfr_spmv_tiling(C.Structure):
+    _fields_ = [("items", C.c_int * 2), ("rows", C.c_int * 2)]
+
+
+class cfr_batch_options(C.Structure):
+    _fields_ = [("precision", C.c_int), ("mode", C.c_int), ("spmv_order", C.c_int),
+                ("max_games", C.c_int64), ("seq_capacity", C.c_int64 * 2),
+                ("inf_capacity", C.c_int64 * 2), ("nnz_capacity", C.c_int64),
+                ("check_every", C.c_int64), ("stream", C.c_void_p), ("device", C.c_int),
+                ("use_graph", C.c_int)]
+
+
+class cfr_game_params(C.Structure):
+    _fields_ = [("variant", C.c_int), ("avg_weight", C.c_int), ("dcfr_alpha", C.c_double),
+                ("dcfr_beta", C.c_double), ("dcfr_gamma", C.c_double),
+                ("target_exploitability", C.c_double), ("max_iterations", C.c_int64)]
+
+
+class cfr_game_status(C.Structure):
+    _fields_ = [("state", C.c_int), ("reached_target", C.c_int), ("iterations", C.c_int64),
+                ("evaluated_at", C.c_int64), ("exploitability", C.c_double)]
+
+
 _lib = C.CDLL(LIB_PATH)
 _P = C.POINTER
 _lib.cfr_options_default.argtypes = [_P(cfr_options)]
@@ -68,11 +92,45 @@ _lib.cfr_iteration.argtypes = [C.c_void_p, _P(C.c_int64)]
 _lib.cfr_kernel_timing.argtypes = [C.c_void_p, C.c_int]
 _lib.cfr_kernel_stats.argtypes = [C.c_void_p, C.c_int, _P(C.c_int64), _P(C.c_double),
                                   _P(C.c_double)]
+_lib.cfr_get_tiling.argtypes = [C.c_void_p, _P(cfr_spmv_tiling)]
+_lib.cfr_set_tiling.argtypes = [C.c_void_p, _P(cfr_spmv_tiling)]
+_lib.cfr_tune.argtypes = [C.c_void_p, C.c_int, _P(cfr_spmv_tiling)]
 _lib.cfr_destroy.argtypes = [C.c_void_p]
 _lib.cfr_last_error.restype = C.c_char_p
+_lib.cfr_batch_options_default.argtypes = [_P(cfr_batch_options)]
+_lib.cfr_game_params_default.argtypes = [_P(cfr_game_params)]
+_lib.cfr_batch_game_size.argtypes = [_P(cfr_game_desc), _P(C.c_int64)]
+_lib.cfr_batch_workspace_size.argtypes = [_P(cfr_batch_options), _P(C.c_size_t)]
+_lib.cfr_batch_create.argtypes = [_P(cfr_batch_options), _P(C.c_void_p)]
+_lib.cfr_batch_add.argtypes = [C.c_void_p, _P(cfr_game_desc), _P(cfr_game_params), _P(C.c_int64)]
+_lib.cfr_batch_run.argtypes = [C.c_void_p, C.c_int64, _P(C.c_int64)]
+_lib.cfr_batch_status.argtypes = [C.c_void_p, C.c_int64, _P(cfr_game_status)]
+_lib.cfr_batch_strategy.argtypes = [C.c_void_p, C.c_int64, C.c_int, C.c_int, _P(C.c_double),
+                                    C.c_int64]
+_lib.cfr_batch_exploitability.argtypes = [C.c_void_p, C.c_int64, C.c_int, _P(C.c_double)]
+_lib.cfr_batch_remove.argtypes = [C.c_void_p, C.c_int64]
+_lib.cfr_batch_get_tiling.argtypes = [C.c_void_p, _P(cfr_spmv_tiling)]
+_lib.cfr_batch_set_tiling.argtypes = [C.c_void_p, _P(cfr_spmv_tiling)]
+_lib.cfr_batch_tune.argtypes = [C.c_void_p, C.c_int, _P(cfr_spmv_tiling)]
+_lib.cfr_batch_kernel_timing.argtypes = [C.c_void_p, C.c_int]
+_lib.cfr_batch_kernel_stats.argtypes = [C.c_void_p, C.c_int, _P(C.c_int64), _P(C.c_double),
+                                        _P(C.c_double)]
+_lib.cfr_batch_destroy.argtypes = [C.c_void_p]
+_lib.cfr_prepare.argtypes = [_P(cfr_game_desc), C.c_int, _P(C.c_void_p)]
+_lib.cfr_prepared_size.argtypes = [C.c_void_p, _P(C.c_int64)]
+_lib.cfr_batch_add_prepared.argtypes = [C.c_void_p, C.c_void_p, _P(cfr_game_params),
+                                        _P(C.c_int64)]
+_lib.cfr_prepared_destroy.argtypes = [C.c_void_p]
 for _f in ("cfr_options_default", "cfr_validate", "cfr_workspace_size", "cfr_create", "cfr_step",
            "cfr_strategy", "cfr_regrets", "cfr_exploitability", "cfr_iteration",
-           "cfr_kernel_timing", "cfr_kernel_stats", "cfr_destroy"):
+           "cfr_kernel_timing", "cfr_kernel_stats", "cfr_get_tiling", "cfr_set_tiling",
+           "cfr_tune", "cfr_destroy", "cfr_batch_options_default", "cfr_game_params_default",
+           "cfr_batch_game_size", "cfr_batch_workspace_size", "cfr_batch_create",
+           "cfr_batch_add", "cfr_batch_run", "cfr_batch_status", "cfr_batch_strategy",
+           "cfr_batch_exploitability", "cfr_batch_remove", "cfr_batch_get_tiling",
+           "cfr_batch_set_tiling", "cfr_batch_tune", "cfr_batch_kernel_timing",
+           "cfr_batch_kernel_stats", "cfr_batch_destroy", "cfr_prepare", "cfr_prepared_size",
+           "cfr_batch_add_prepared", "cfr_prepared_destroy"):
     getattr(_lib, _f).restype = C.c_int
 
 
@@ -196,8 +254,142 @@ def cfr_kernel_stats(h, kernel: int):
     return int(n.value), float(ms.value), float(by.value)
 
 
+def _tiling_dict(t: cfr_spmv_tiling) -> dict:
+    return {"items": [int(t.items[0]), int(t.items[1])], "rows": [int(t.rows[0]), int(t.rows[1])]}
+
+
+def _tiling_struct(d: dict) -> cfr_spmv_tiling:
+    t = cfr_spmv_tiling()
+    for w in range(2):
+        t.items[w] = int(d["items"][w])
+        t.rows[w] = int(d["rows"][w])
+    return t
+
+
+def cfr_get_tiling(h) -> dict:
+    t = cfr_spmv_tiling()
+    _check(_lib.cfr_get_tiling(h, C.byref(t)), "cfr_get_tiling")
+    return _tiling_dict(t)
+
+
+def cfr_set_tiling(h, tiling: dict):
+    t = _tiling_struct(tiling)
+    _check(_lib.cfr_set_tiling(h, C.byref(t)), "cfr_set_tiling")
+
+
+def cfr_tune(h, reps: int = 10) -> dict:
+    t = cfr_spmv_tiling()
+    _check(_lib.cfr_tune(h, int(reps), C.byref(t)), "cfr_tune")
+    return _tiling_dict(t)
+
+
 def cfr_destroy(h):
     _check(_lib.cfr_destroy(h), "cfr_destroy")
+
+
+def cfr_batch_options_default() -> cfr_batch_options:
+    o = cfr_batch_options()
+    _check(_lib.cfr_batch_options_default(C.byref(o)), "cfr_batch_options_default")
+    return o
+
+
+def cfr_game_params_default() -> cfr_game_params:
+    g = cfr_game_params()
+    _check(_lib.cfr_game_params_default(C.byref(g)), "cfr_game_params_default")
+    return g
+
+
+def cfr_batch_game_size(game_arrays: GameArrays) -> np.ndarray:
+    out = np.zeros(5, dtype=np.int64)
+    _check(_lib.cfr_batch_game_size(C.byref(game_arrays.desc),
+                                    out.ctypes.data_as(C.POINTER(C.c_int64))),
+           "cfr_batch_game_size")
+    return out
+
+
+def cfr_batch_workspace_size(opts: cfr_batch_options) -> int:
+    n = C.c_size_t(0)
+    _check(_lib.cfr_batch_workspace_size(C.byref(opts), C.byref(n)), "cfr_batch_workspace_size")
+    return int(n.value)
+
+
+def cfr_batch_create(opts: cfr_batch_options) -> C.c_void_p:
+    h = C.c_void_p()
+    _check(_lib.cfr_batch_create(C.byref(opts), C.byref(h)), "cfr_batch_create")
+    return h
+
+
+def cfr_batch_add(h, game_arrays: GameArrays, params: cfr_game_params) -> int:
+    """Returns the game's id, or raises CfrError (code CFR_ENOMEM when the
+    game does not fit the free capacity)."""
+    i = C.c_int64(-1)
+    _check(_lib.cfr_batch_add(h, C.byref(game_arrays.desc), C.byref(params), C.byref(i)),
+           "cfr_batch_add")
+    return int(i.value)
+
+
+def cfr_batch_run(h, n: int) -> int:
+    k = C.c_int64(0)
+    _check(_lib.cfr_batch_run(h, int(n), C.byref(k)), "cfr_batch_run")
+    return int(k.value)
+
+
+def cfr_batch_status(h, gid: int) -> dict:
+    s = cfr_game_status()
+    _check(_lib.cfr_batch_status(h, int(gid), C.byref(s)), "cfr_batch_status")
+    return {"state": GAME_STATES[int(s.state)], "reached_target": bool(s.reached_target),
+            "iterations": int(s.iterations), "evaluated_at": int(s.evaluated_at),
+            "expl": float(s.exploitability)}
+
+
+def cfr_batch_strategy(h, gid: int, player: int, kind: int, n_seq: int) -> np.ndarray:
+    out = np.empty(n_seq)
+    _check(_lib.cfr_batch_strategy(h, int(gid), player, kind, _dptr(out), n_seq),
+           "cfr_batch_strategy")
+    return out
+
+
+def cfr_batch_exploitability(h, gid: int, kind: int) -> np.ndarray:
+    out = np.empty(5)
+    _check(_lib.cfr_batch_exploitability(h, int(gid), kind, _dptr(out)),
+           "cfr_batch_exploitability")
+    return out
+
+
+def cfr_batch_remove(h, gid: int):
+    _check(_lib.cfr_batch_remove(h, int(gid)), "cfr_batch_remove")
+
+
+def cfr_batch_get_tiling(h) -> dict:
+    t = cfr_spmv_tiling()
+    _check(_lib.cfr_batch_get_tiling(h, C.byref(t)), "cfr_batch_get_tiling")
+    return _tiling_dict(t)
+
+
+def cfr_batch_set_tiling(h, tiling: dict):
+    t = _tiling_struct(tiling)
+    _check(_lib.cfr_batch_set_tiling(h, C.byref(t)), "cfr_batch_set_tiling")
+
+
+def cfr_batch_tune(h, reps: int = 10) -> dict:
+    t = cfr_spmv_tiling()
+    _check(_lib.cfr_batch_tune(h, int(reps), C.byref(t)), "cfr_batch_tune")
+    return _tiling_dict(t)
+
+
+def cfr_batch_kernel_timing(h, enable: bool):
+    _check(_lib.cfr_batch_kernel_timing(h, int(bool(enable))), "cfr_batch_kernel_timing")
+
+
+def cfr_batch_kernel_stats(h, kernel: int):
+    n, ms, by = C.c_int64(0), C.c_double(0), C.c_double(0)
+    _check(_lib.cfr_batch_kernel_stats(h, kernel, C.byref(n), C.byref(ms), C.byref(by)),
+           "cfr_batch_kernel_stats")
+    return int(n.value), float(ms.value), float(by.value)
+
+
+def cfr_batch_destroy(h):
+    _check(_lib.cfr_batch_destroy(h), "cfr_batch_destroy")
 
 
 # ---- convenience wrapper --------------------------------------------------------
@@ -258,9 +450,119 @@ class Solver:
     def kernel_stats(self, kernel: int):
         return cfr_kernel_stats(self.h, kernel)
 
+    @property
+    def tiling(self) -> dict:
+        return cfr_get_tiling(self.h)
+
+    @tiling.setter
+    def tiling(self, t: dict):
+        cfr_set_tiling(self.h, t)
+
+    def tune(self, reps: int = 10) -> dict:
+        return cfr_tune(self.h, reps)
+
     def close(self):
         if getattr(self, "h", None):
             cfr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many games solved together on one GPU (library-owned workspace, work
+    on torch's current stream of the device).  Capacities are in index
+    units (cfr_batch_game_size); games are added with their own regret
+    minimiser and stopping rule and run with checks every `check_every`
+    iterations."""
+
+    def __init__(self, seq_capacity, inf_capacity, nnz_capacity: int, max_games: int = 256,
+                 precision: str = "fp32_acc64", mode: str = "alternating",
+                 check_every: int = 10, device: int = 0, use_graph: bool = True, stream=None,
+                 spmv_order: str = "default"):
+        import torch
+        o = cfr_batch_options_default()
+        o.precision = PRECISIONS[precision]
+        o.mode = MODES[mode]
+        o.spmv_order = SPMV_ORDER[spmv_order]
+        o.max_games = int(max_games)
+        for p in range(2):
+            o.seq_capacity[p] = int(seq_capacity[p])
+            o.inf_capacity[p] = int(inf_capacity[p])
+        o.nnz_capacity = int(nnz_capacity)
+        o.check_every = int(check_every)
+        o.device = int(device)
+        o.use_graph = int(bool(use_graph))
+        dev = torch.device("cuda", int(device))
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        self.stream = stream
+        o.stream = C.c_void_p(int(stream.cuda_stream))
+        self.opts = o
+        self.workspace_bytes = cfr_batch_workspace_size(o)
+        self.h = cfr_batch_create(o)
+        self.n_seq = {}
+
+    @staticmethod
+    def game_size(game) -> np.ndarray:
+        return cfr_batch_game_size(GameArrays(game, with_csc=False))
+
+    def add(self, game, variant: str = "pcfr+", target: float = 0.0, max_iterations: int = 0,
+            avg: str = "default", alpha: float = 1.5, beta: float = 0.0,
+            gamma: float = 2.0) -> int:
+        arrays = GameArrays(game)
+        gp = cfr_game_params_default()
+        gp.variant = VARIANTS[variant]
+        gp.avg_weight = AVG[avg]
+        gp.dcfr_alpha, gp.dcfr_beta, gp.dcfr_gamma = float(alpha), float(beta), float(gamma)
+        gp.target_exploitability = float(target)
+        gp.max_iterations = int(max_iterations)
+        gid = cfr_batch_add(self.h, arrays, gp)
+        self.n_seq[gid] = list(arrays.n_seq)
+        return gid
+
+    def run(self, n: int) -> int:
+        return cfr_batch_run(self.h, n)
+
+    def status(self, gid: int) -> dict:
+        return cfr_batch_status(self.h, gid)
+
+    def strategy(self, gid: int, player: int, kind: str = "average") -> np.ndarray:
+        return cfr_batch_strategy(self.h, gid, player, KINDS[kind], self.n_seq[gid][player])
+
+    def exploitability(self, gid: int, kind: str = "average") -> dict:
+        out = cfr_batch_exploitability(self.h, gid, KINDS[kind])
+        return {"expl": out[0], "nash_conv": out[1], "br1": out[2], "br2": out[3],
+                "value": out[4]}
+
+    def remove(self, gid: int):
+        cfr_batch_remove(self.h, gid)
+        self.n_seq.pop(gid, None)
+
+    @property
+    def tiling(self) -> dict:
+        return cfr_batch_get_tiling(self.h)
+
+    @tiling.setter
+    def tiling(self, t: dict):
+        cfr_batch_set_tiling(self.h, t)
+
+    def tune(self, reps: int = 10) -> dict:
+        return cfr_batch_tune(self.h, reps)
+
+    def kernel_timing(self, enable: bool):
+        cfr_batch_kernel_timing(self.h, enable)
+
+    def kernel_stats(self, kernel: int):
+        return cfr_batch_kernel_stats(self.h, kernel)
+
+    def close(self):
+        if getattr(self, "h", None):
+            cfr_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):

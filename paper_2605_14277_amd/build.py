@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libcfr.so")
-SOURCES = ["cfr_api.hip", "cfr_kernels.hip"]
+SOURCES = ["cfr_api.hip", "cfr_engine.hip", "cfr_kernels.hip"]
 
 
 def hipcc() -> str:

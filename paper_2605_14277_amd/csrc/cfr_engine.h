@@ -1,0 +1,248 @@
+// Host runtime shared by the single-game solver and the batch of games
+// (cfr_api.hip): level-order planning of a game, the device arenas that
+// hold any set of games, the block tables every launch walks, graph capture
+// of one iteration and the evaluation pass.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "cfr.h"
+#include "cfr_internal.h"
+
+namespace cfr {
+
+// Records the message of a failing call for cfr_last_error; returns code.
+int fail(int code, const std::string &msg);
+const char *last_error_message();
+std::string hip_msg(const char *what, hipError_t e);
+
+// ---------------------------------------------------------------------------
+// Level order of one game (local numbering)
+// ---------------------------------------------------------------------------
+//
+// The level of a decision point is the number of its own earlier decisions:
+// 0 under the empty sequence, else one more than the level of its parent
+// sequence's decision point.  Decision points are numbered level by level,
+// keeping the caller's order inside a level; each one's sequences follow
+// consecutively.  The sequences of one level then form one contiguous
+// range, so each level of a sweep is one launch over ranges (Algorithm 2
+// applies one level graph per step).  The decision points below each
+// sequence (the children of the observation point that follows it in
+// Algorithm 1) are listed in child_ptr/child_idx, ascending.
+struct PlayerPlan {
+    int32_t n_seq = 1, n_inf = 0, n_levels = 0;
+    bool identity = true;
+    std::vector<int32_t> new_of_old;  // caller sequence -> internal sequence
+    std::vector<int32_t> old_of_new;  // internal sequence -> caller sequence
+    std::vector<int32_t> inf_first;   // [n_inf+1]
+    std::vector<int32_t> seq_par;     // [n_seq]
+    std::vector<int32_t> child_ptr;   // [n_seq+1]
+    std::vector<int32_t> child_idx;   // [n_inf]
+    std::vector<int32_t> lvl_inf;     // [n_levels+1]
+    std::vector<int32_t> lvl_seq;     // [n_levels+1]
+    std::vector<uint8_t> lvl_kind;    // [n_levels] 0 generic, 1 fast, 2 fast without children
+    int32_t top_levels = 0, n_roots = 0;
+    std::vector<int32_t> top_off;     // [top_levels*(n_roots+1)]
+    std::vector<int32_t> top_list;    // decision points of the shallow levels by level, then root
+};
+
+// CSR -> CSR of the transpose, every output row in ascending input-row order.
+void transpose(int64_t n_rows, int64_t n_cols, const int64_t *ptr, const int32_t *idx,
+               const double *val, std::vector<int64_t> &tptr, std::vector<int32_t> &tidx,
+               std::vector<double> &tval);
+
+// A validated game in level order, ready for upload: both players' plans
+// and the payoff matrix sorted by player-1 rows (csr) and by player-2 rows
+// (csc), with local indices.  The index/value pointers refer either to the
+// owned vectors or, when no renumbering was needed, to the caller's arrays
+// (valid for the duration of the call that prepared the game).
+struct HostGame {
+    PlayerPlan pl[2];
+    int64_t nnz = 0;
+    std::vector<int32_t> ptr[2];  // [n_seq+1] row pointers of csr (0) and csc (1)
+    const int32_t *idx[2] = {nullptr, nullptr};
+    const double *val[2] = {nullptr, nullptr};
+    std::vector<int32_t> own_idx[2];
+    std::vector<double> own_val[2];
+    std::vector<float> own_valf[2];  // values already in float (then val[] is unused)
+};
+// Makes a prepared game self-contained: copies any arrays still owned by
+// the caller and, for a float value type, converts the values once.
+void own_game(HostGame &hg, int prec);
+// lone: also group the shallow levels for the one-launch sweep (k_top).
+// with_matrix = false: plans and row pointers only (for sizing).
+void prepare_game(const cfr_game_desc *g, bool lone, bool with_matrix, HostGame &hg);
+
+// Per-game constants of the regret minimiser and the stopping rule.
+struct GameParams {
+    int variant = -1;  // fixed at the first step for the single-game solver
+    int avg_kind = CFR_AVG_DEFAULT;
+    double alpha = 1.5, beta = 0.0, gamma = 2.0;
+    double target = 0.0;    // stop when the average's exploitability is at most this
+    int64_t max_it = 0;     // stop at the first check at or beyond this many iterations
+};
+
+// Index space, storage and table capacities of an engine.
+struct Capacity {
+    int64_t slots = 1;
+    int64_t seq[2] = {0, 0};  // sequence indices per player (a game takes n_seq + 1)
+    int64_t inf[2] = {0, 0};  // decision-point indices per player (a game takes n_inf + 1)
+    int64_t nnz = 0;
+    int64_t t_csr = 0, t_csc = 0;               // product blocks
+    int64_t t_up[2] = {0, 0}, t_down[2] = {0, 0}, t_seq[2] = {0, 0};  // range blocks
+    int64_t top_off[2] = {0, 0}, top_list[2] = {0, 0};
+};
+// Exact capacity of one game alone (the single-game solver).
+Capacity lone_capacity(const HostGame &hg, int items_csr, int rows_csr, int items_csc,
+                       int rows_csc);
+// Table capacities that hold any set of games fitting the index capacities.
+void bound_tables(Capacity &c);
+// Device bytes of an engine of this capacity (256-byte aligned buffers).
+size_t engine_bytes(const Capacity &c, int prec);
+
+// First-fit allocator of index ranges.
+struct RangeAlloc {
+    int64_t cap = 0;
+    std::map<int64_t, int64_t> free_;  // start -> length
+    void init(int64_t c);
+    int64_t take(int64_t n);  // start of a free range of n, or -1
+    void give(int64_t at, int64_t n);
+    int64_t largest() const;
+};
+
+// One game held by an engine.
+struct Slot {
+    bool live = false;     // holds a game
+    bool active = false;   // iterates
+    bool pending = false;  // admitted between checks; joins at the next one
+    int64_t id = -1;
+    GameParams gp;
+    int64_t t = 0;
+    int32_t n_seq[2] = {0, 0}, n_inf[2] = {0, 0}, n_levels[2] = {0, 0};
+    int64_t sb[2] = {0, 0}, ib[2] = {0, 0}, nb = 0, nnz = 0;
+    std::vector<int32_t> lvl_inf[2], lvl_seq[2];
+    std::vector<uint8_t> lvl_kind[2];
+    std::vector<int32_t> ptr[2];         // local row pointers of csr / csc (re-partitioning)
+    std::vector<int32_t> old_of_new[2];  // internal -> caller numbering
+    std::vector<SpmvBlock> blocks[2];    // product blocks (global fields)
+    double last[5] = {0, 0, 0, 0, 0};    // last evaluation: expl, NashConv, BR1, BR2, value
+    int64_t last_t = -1;                 // iteration of that evaluation
+    bool reached = false;
+};
+
+// Block tables of one set of games, in device memory, plus the host-side
+// launch plan over them.
+struct Tables {
+    SpmvBlock *csr = nullptr, *csc = nullptr;
+    RangeBlock *up[2] = {nullptr, nullptr}, *down[2] = {nullptr, nullptr},
+               *seq[2] = {nullptr, nullptr};
+    SlotRef *root[2] = {nullptr, nullptr}, *fin = nullptr;
+    int32_t n_csr = 0, n_csc = 0, n_seq[2] = {0, 0}, n_root[2] = {0, 0}, n_fin = 0;
+    struct Up {
+        int32_t off, n;
+        int variant, kind;
+    };
+    std::vector<std::vector<Up>> up_l[2];                      // per level: one launch per variant
+    std::vector<std::pair<int32_t, int32_t>> up_level[2];      // per level: all of its entries
+    std::vector<std::pair<int32_t, int32_t>> down_l[2];        // per level (level 0 unused)
+    // host copies of the last upload (kept until the next one: the copies
+    // are asynchronous)
+    std::vector<SpmvBlock> h_csr, h_csc;
+    std::vector<RangeBlock> h_up[2], h_down[2], h_seq[2];
+    std::vector<SlotRef> h_root[2], h_fin;
+    double bytes[2] = {0, 0};  // algorithmic bytes of one product launch over these games
+    bool valid = false;
+};
+
+struct Engine {
+    int prec = CFR_FP64;
+    int mode = -1;  // CFR_SIMULTANEOUS / CFR_ALTERNATING, fixed by the first step
+    int spmv_order = CFR_SPMV_DEFAULT;
+    int items[2] = {kSpmvItemsDefault, kSpmvItemsDefault};
+    int rows[2] = {kSpmvRowCap, kSpmvRowCap};
+    int xcd_remap = 1;
+    int device = 0;
+    bool use_graph = true;
+    bool lone = false;  // a single game: shallow levels may run as one launch
+    hipStream_t st = nullptr;
+    hipStream_t cap_st = nullptr;  // private stream used only to capture graphs
+    Capacity cap;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    bool own_ws = false;
+    bool failed = false;
+
+    // device buffers
+    Scalars *sc = nullptr;
+    double *partials = nullptr;
+    DevPlayer dp[2];
+    int32_t *ptr[2] = {nullptr, nullptr}, *idx[2] = {nullptr, nullptr};
+    void *val[2] = {nullptr, nullptr};
+    char *tab_region[2] = {nullptr, nullptr};  // iteration tables, evaluation tables
+    size_t tab_bytes = 0;
+
+    RangeAlloc seq_alloc[2], inf_alloc[2], nnz_alloc;
+    std::vector<Slot> slots;
+    int64_t next_id = 0;
+    Tables it, ev;  // tables of the iterating games / of the last evaluated set
+    std::vector<int> ev_set;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int64_t check_every = 0;  // 0: no checks (single-game solver)
+    int64_t phase = 0;        // iterations since the last check
+
+    // per-launch timing of the payoff products (HIP events on st)
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> events[2];
+    int64_t launches[2] = {0, 0};
+    double total_ms[2] = {0, 0};
+
+    // Carves the device buffers for `c` out of `workspace` (or allocates).
+    int init(const Capacity &c, int precision, int dev, hipStream_t stream, void *workspace,
+             size_t workspace_bytes);
+    void release();
+    int device_error(const char *what, hipError_t e);
+    int sync(const char *what);
+
+    int sequential() const;
+    // Uploads a prepared game into free ranges and puts it at the uniform
+    // strategy; *slot_out receives its slot.  CFR_ENOMEM when it does not fit.
+    int add(const HostGame &hg, const GameParams &gp, bool join_now, int *slot_out);
+    void remove(int slot);
+    int set_params(int slot, const GameParams &gp);  // writes the game's constants to the device
+    // Re-partitions every game's product blocks for a new tiling.
+    void repartition(int which, int items_, int rows_);
+    void partition(Slot &s, int which);
+
+    std::vector<int> active_set() const;
+    int build_tables(Tables &T, char *region, const std::vector<int> &set);
+    bool tables_in_bounds(const Tables &T) const;
+    int rebuild();  // iteration tables of the active games; drops the graph
+    void drop_graph();
+
+    hipError_t spmv(const Tables &T, int which, const void *xin, void *yout, bool begin,
+                    hipStream_t s, bool timed);
+    hipError_t sweeps(const Tables &T, int p, double usign, hipStream_t s);
+    hipError_t enqueue_iteration(hipStream_t s);
+    hipError_t build_graph();
+    // n iterations of every active game (no checks).
+    int iterate(int64_t n);
+    // Evaluates the average (or current) profile of the games in `set`;
+    // results land in each slot's `last`.
+    int evaluate(const std::vector<int> &set, int kind);
+    // n iterations with checks every check_every iterations; games that meet
+    // their stopping rule at a check stop iterating.
+    int run(int64_t n);
+    // Times `reps` launches of one product with the current tiling (ms each).
+    int time_spmv(int which, int reps, double *ms);
+
+    int fetch_vector(int slot, int player, int what, std::vector<double> &out);
+};
+
+}  // namespace cfr

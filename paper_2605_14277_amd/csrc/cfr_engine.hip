@@ -1,0 +1,1337 @@
+// Host runtime shared by the single-game solver and the batch of games.
+//
+// An engine owns one device workspace holding per-player arenas of
+// sequence and decision-point indices, an arena of payoff nonzeros, one
+// Scalars record per game slot and two regions of block tables (one for the
+// iterating games, one for the last evaluated set).  Adding a game takes
+// free ranges of each arena, uploads the game with its indices shifted to
+// the global positions and sets it to the uniform strategy; every launch of
+// an iteration then covers all iterating games at once, and one iteration
+// is captured as a HIP graph that is replayed until the set of iterating
+// games changes.
+#include "cfr_engine.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+
+namespace cfr {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+int fail(int code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+const char *last_error_message() { return g_last_error.c_str(); }
+
+std::string hip_msg(const char *what, hipError_t e)
+{
+    return std::string(what) + ": " + hipGetErrorString(e);
+}
+
+// ---------------------------------------------------------------------------
+// Planning
+// ---------------------------------------------------------------------------
+
+namespace {
+
+void plan_player(const cfr_player_desc &d, bool lone, PlayerPlan &pl)
+{
+    const int32_t n_seq = (int32_t)d.n_seq, n_inf = (int32_t)d.n_inf;
+    pl.n_seq = n_seq;
+    pl.n_inf = n_inf;
+    std::vector<int32_t> seq_inf((size_t)n_seq, -1);
+    for (int32_t j = 0; j < n_inf; ++j)
+        for (int32_t a = d.inf_first_seq[j]; a < d.inf_first_seq[j + 1]; ++a) seq_inf[a] = j;
+    std::vector<int32_t> level((size_t)n_inf, 0);
+    int32_t n_levels = 0;
+    for (int32_t j = 0; j < n_inf; ++j) {
+        int32_t par = d.inf_parent[j];
+        level[j] = par == 0 ? 0 : level[seq_inf[par]] + 1;
+        n_levels = std::max(n_levels, level[j] + 1);
+    }
+    pl.n_levels = n_levels;
+    // stable bucket by level
+    std::vector<int32_t> count((size_t)n_levels + 1, 0);
+    for (int32_t j = 0; j < n_inf; ++j) count[level[j] + 1]++;
+    for (int32_t lv = 0; lv < n_levels; ++lv) count[lv + 1] += count[lv];
+    std::vector<int32_t> old_inf_of_new((size_t)n_inf);
+    {
+        std::vector<int32_t> fill(count.begin(), count.end() - 1);
+        for (int32_t j = 0; j < n_inf; ++j) old_inf_of_new[fill[level[j]]++] = j;
+    }
+    pl.new_of_old.assign((size_t)n_seq, 0);
+    pl.old_of_new.assign((size_t)n_seq, 0);
+    pl.inf_first.assign((size_t)n_inf + 1, n_seq);
+    pl.lvl_inf.assign((size_t)n_levels + 1, n_inf);
+    pl.lvl_seq.assign((size_t)n_levels + 1, n_seq);
+    int32_t next = 1;
+    for (int32_t k = 0; k < n_inf; ++k) {
+        int32_t j = old_inf_of_new[k];
+        if (k == count[level[j]]) {
+            pl.lvl_inf[level[j]] = k;
+            pl.lvl_seq[level[j]] = next;
+        }
+        pl.inf_first[k] = next;
+        for (int32_t a = d.inf_first_seq[j]; a < d.inf_first_seq[j + 1]; ++a) {
+            pl.new_of_old[a] = next;
+            pl.old_of_new[next] = a;
+            ++next;
+        }
+    }
+    pl.identity = true;
+    for (int32_t k = 0; k < n_inf; ++k)
+        if (old_inf_of_new[k] != k) {
+            pl.identity = false;
+            break;
+        }
+    // parent sequence of each decision point / of each sequence, new numbering
+    std::vector<int32_t> inf_par((size_t)n_inf);
+    pl.seq_par.assign((size_t)n_seq, 0);
+    for (int32_t k = 0; k < n_inf; ++k) {
+        inf_par[k] = pl.new_of_old[d.inf_parent[old_inf_of_new[k]]];
+        for (int32_t a = pl.inf_first[k]; a < pl.inf_first[k + 1]; ++a) pl.seq_par[a] = inf_par[k];
+    }
+    // decision points below each sequence, ascending
+    pl.child_ptr.assign((size_t)n_seq + 1, 0);
+    for (int32_t k = 0; k < n_inf; ++k) pl.child_ptr[inf_par[k] + 1]++;
+    for (int32_t s = 0; s < n_seq; ++s) pl.child_ptr[s + 1] += pl.child_ptr[s];
+    pl.child_idx.assign((size_t)std::max(n_inf, 1), 0);
+    {
+        std::vector<int32_t> fill(pl.child_ptr.begin(), pl.child_ptr.end() - 1);
+        for (int32_t k = 0; k < n_inf; ++k) pl.child_idx[fill[inf_par[k]]++] = k;
+    }
+    // levels whose decision points fit the fast sweep path (2: and have
+    // nothing below them)
+    pl.lvl_kind.assign((size_t)n_levels, 2);
+    for (int32_t lv = 0; lv < n_levels; ++lv)
+        for (int32_t k = pl.lvl_inf[lv]; k < pl.lvl_inf[lv + 1]; ++k) {
+            if (pl.inf_first[k + 1] - pl.inf_first[k] > kFastActs) pl.lvl_kind[lv] = 0;
+            for (int32_t a = pl.inf_first[k]; a < pl.inf_first[k + 1]; ++a) {
+                const int32_t kids = pl.child_ptr[a + 1] - pl.child_ptr[a];
+                if (kids > kFastKids) pl.lvl_kind[lv] = 0;
+                else if (kids > 0 && pl.lvl_kind[lv] == 2) pl.lvl_kind[lv] = 1;
+            }
+        }
+    // A lone game may run its whole sweep as one launch per root subtree,
+    // when every root decision point's share of every level is at most
+    // kTopMaxGroup decision points (one pass of the block).  The levels of
+    // one sweep form a chain of dependent memory accesses either way, so
+    // this only pays when it removes every per-level launch; otherwise each
+    // level gets a launch over all its decision points.
+    pl.top_levels = 0;
+    pl.n_roots = n_levels > 0 ? pl.lvl_inf[1] - pl.lvl_inf[0] : 0;
+    pl.top_off.clear();
+    pl.top_list.clear();
+    if (n_levels == 0 || !lone) return;
+    std::vector<int32_t> root((size_t)n_inf, 0);
+    std::vector<int32_t> seq_new_inf((size_t)n_seq, 0);
+    for (int32_t k = 0; k < n_inf; ++k)
+        for (int32_t a = pl.inf_first[k]; a < pl.inf_first[k + 1]; ++a) seq_new_inf[a] = k;
+    for (int32_t k = 0; k < n_inf; ++k)
+        root[k] = inf_par[k] == 0 ? k : root[seq_new_inf[inf_par[k]]];
+    const int32_t R = pl.n_roots;
+    std::vector<int32_t> cnt((size_t)R + 1);
+    for (int32_t lv = 0; lv < n_levels; ++lv) {
+        std::fill(cnt.begin(), cnt.end(), 0);
+        for (int32_t k = pl.lvl_inf[lv]; k < pl.lvl_inf[lv + 1]; ++k) cnt[root[k] + 1]++;
+        int32_t mx = *std::max_element(cnt.begin(), cnt.end());
+        if (mx > kTopMaxGroup) break;
+        for (int32_t r = 0; r < R; ++r) cnt[r + 1] += cnt[r];
+        const int32_t base = (int32_t)pl.top_list.size();
+        for (int32_t r = 0; r <= R; ++r) pl.top_off.push_back(base + cnt[r]);
+        pl.top_list.resize((size_t)base + (size_t)cnt[R]);
+        std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+        for (int32_t k = pl.lvl_inf[lv]; k < pl.lvl_inf[lv + 1]; ++k)
+            pl.top_list[(size_t)base + (size_t)fill[root[k]]++] = k;
+        pl.top_levels = lv + 1;
+    }
+    if (pl.top_levels < n_levels && !CFR_TOP_PARTIAL) {
+        pl.top_levels = 0;
+        pl.top_off.clear();
+        pl.top_list.clear();
+    }
+}
+
+// Builds the internal row-sorted matrix of `rows` in level order.
+void permute_rows(int32_t n_rows, const std::vector<int32_t> &old_of_new_row,
+                  const std::vector<int32_t> &new_of_old_col, const int64_t *ptr,
+                  const int32_t *idx, const double *val, std::vector<int64_t> &optr,
+                  std::vector<int32_t> &oidx, std::vector<double> &oval)
+{
+    optr.assign((size_t)n_rows + 1, 0);
+    for (int32_t r = 0; r < n_rows; ++r) {
+        int32_t o = old_of_new_row[r];
+        optr[r + 1] = optr[r] + (ptr[o + 1] - ptr[o]);
+    }
+    oidx.resize((size_t)optr[n_rows]);
+    oval.resize((size_t)optr[n_rows]);
+    std::vector<std::pair<int32_t, double>> row;
+    for (int32_t r = 0; r < n_rows; ++r) {
+        int32_t o = old_of_new_row[r];
+        row.clear();
+        for (int64_t e = ptr[o]; e < ptr[o + 1]; ++e) row.emplace_back(new_of_old_col[idx[e]], val[e]);
+        std::sort(row.begin(), row.end(),
+                  [](const std::pair<int32_t, double> &a, const std::pair<int32_t, double> &b) {
+                      return a.first < b.first;
+                  });
+        int64_t base = optr[r];
+        for (size_t k = 0; k < row.size(); ++k) {
+            oidx[base + k] = row[k].first;
+            oval[base + k] = row[k].second;
+        }
+    }
+}
+
+std::vector<int32_t> narrow_ptr(const int64_t *ptr, size_t n)
+{
+    std::vector<int32_t> out(n);
+    for (size_t i = 0; i < n; ++i) out[i] = (int32_t)ptr[i];
+    return out;
+}
+
+// Row boundaries of product blocks: runs of whole rows with at most
+// cap_nnz nonzeros and cap_rows rows; a longer row gets a block of its own.
+std::vector<int32_t> partition_rows(const std::vector<int32_t> &ptr, int32_t cap_nnz,
+                                    int32_t cap_rows)
+{
+    const int32_t n_rows = (int32_t)ptr.size() - 1;
+    std::vector<int32_t> blk{0};
+    int64_t cur_nnz = 0;
+    int32_t cur_rows = 0;
+    for (int32_t r = 0; r < n_rows; ++r) {
+        int64_t l = ptr[r + 1] - ptr[r];
+        if (l > cap_nnz) {
+            if (cur_rows) blk.push_back(r);
+            blk.push_back(r + 1);
+            cur_nnz = 0;
+            cur_rows = 0;
+            continue;
+        }
+        if (cur_rows && (cur_nnz + l > cap_nnz || cur_rows == cap_rows)) {
+            blk.push_back(r);
+            cur_nnz = 0;
+            cur_rows = 0;
+        }
+        cur_nnz += l;
+        ++cur_rows;
+    }
+    if (cur_rows) blk.push_back(n_rows);
+    return blk;
+}
+
+inline int64_t chunks(int64_t n) { return (n + kRangeBlock - 1) / kRangeBlock; }
+
+// Workspace layout: every buffer 256-byte aligned, carved in a fixed order.
+struct Carver {
+    size_t cur = 0;
+    char *base = nullptr;
+    void *take(size_t bytes)
+    {
+        cur = (cur + 255) & ~(size_t)255;
+        void *p = base ? base + cur : nullptr;
+        cur += bytes;
+        return p;
+    }
+};
+
+// Offsets of the block tables inside one table region.
+struct TableLayout {
+    size_t csr, csc, up[2], down[2], seq[2], root[2], fin, bytes;
+};
+
+TableLayout table_layout(const Capacity &c)
+{
+    TableLayout L{};
+    Carver k;
+    L.csr = (size_t)k.cur;
+    k.take(sizeof(SpmvBlock) * (size_t)std::max<int64_t>(c.t_csr, 1));
+    L.csc = (k.cur + 255) & ~(size_t)255;
+    k.take(sizeof(SpmvBlock) * (size_t)std::max<int64_t>(c.t_csc, 1));
+    for (int p = 0; p < 2; ++p) {
+        L.up[p] = (k.cur + 255) & ~(size_t)255;
+        k.take(sizeof(RangeBlock) * (size_t)std::max<int64_t>(c.t_up[p], 1));
+        L.down[p] = (k.cur + 255) & ~(size_t)255;
+        k.take(sizeof(RangeBlock) * (size_t)std::max<int64_t>(c.t_down[p], 1));
+        L.seq[p] = (k.cur + 255) & ~(size_t)255;
+        k.take(sizeof(RangeBlock) * (size_t)std::max<int64_t>(c.t_seq[p], 1));
+        L.root[p] = (k.cur + 255) & ~(size_t)255;
+        k.take(sizeof(SlotRef) * (size_t)c.slots);
+    }
+    L.fin = (k.cur + 255) & ~(size_t)255;
+    k.take(sizeof(SlotRef) * (size_t)c.slots);
+    L.bytes = (k.cur + 255) & ~(size_t)255;
+    return L;
+}
+
+struct Layout {
+    Scalars *sc;
+    double *partials;
+    DevPlayer dp[2];
+    int32_t *ptr[2], *idx[2];
+    void *val[2];
+    char *tab[2];
+    size_t tab_bytes;
+};
+
+Layout carve(Carver &k, const Capacity &c, int prec)
+{
+    const size_t V = value_bytes(prec), R = accum_bytes(prec), C = compute_bytes(prec);
+    Layout L{};
+    L.sc = (Scalars *)k.take(sizeof(Scalars) * (size_t)c.slots);
+    L.partials = (double *)k.take(sizeof(double) * (size_t)std::max<int64_t>(c.t_seq[0], 1));
+    for (int p = 0; p < 2; ++p) {
+        DevPlayer &d = L.dp[p];
+        const size_t n = (size_t)std::max<int64_t>(c.seq[p], 1);
+        const size_t ni = (size_t)std::max<int64_t>(c.inf[p], 1);
+        d.inf_first = (int32_t *)k.take(4 * ni);
+        d.seq_par = (int32_t *)k.take(4 * n);
+        d.child_ptr = (int32_t *)k.take(4 * n);
+        d.child_idx = (int32_t *)k.take(4 * ni);
+        d.r = k.take(R * n);
+        d.m = k.take(R * n);
+        d.s = k.take(R * n);
+        d.b = k.take(V * n);
+        d.x = k.take(V * n);
+        d.g = k.take(V * n);
+        d.xbar = k.take(V * n);
+        d.vinf = k.take(C * ni);
+        d.top_off = (int32_t *)k.take(4 * (size_t)std::max<int64_t>(c.top_off[p], 1));
+        d.top_list = (int32_t *)k.take(4 * (size_t)std::max<int64_t>(c.top_list[p], 1));
+    }
+    for (int w = 0; w < 2; ++w) {
+        L.ptr[w] = (int32_t *)k.take(4 * (size_t)std::max<int64_t>(c.seq[w], 1));
+        L.idx[w] = (int32_t *)k.take(4 * (size_t)std::max<int64_t>(c.nnz, 1));
+        L.val[w] = k.take(V * (size_t)std::max<int64_t>(c.nnz, 1));
+    }
+    const TableLayout T = table_layout(c);
+    L.tab_bytes = T.bytes;
+    for (int r = 0; r < 2; ++r) L.tab[r] = (char *)k.take(T.bytes);
+    return L;
+}
+
+template <typename V, typename C>
+void initial_strategy_t(const PlayerPlan &pl, std::vector<char> &bb, std::vector<char> &xb)
+{
+    // uniform behaviour at every decision point, then the top-down pass in
+    // ascending sequence order (a parent sequence precedes its children)
+    const size_t n = (size_t)pl.n_seq + 1;
+    bb.assign(n * sizeof(V), 0);
+    xb.assign(n * sizeof(V), 0);
+    V *b = (V *)bb.data();
+    V *x = (V *)xb.data();
+    x[0] = (V)1;
+    for (int32_t k = 0; k < pl.n_inf; ++k) {
+        const int32_t a0 = pl.inf_first[k], a1 = pl.inf_first[k + 1];
+        for (int32_t a = a0; a < a1; ++a) b[a] = (V)((C)1 / (C)(a1 - a0));
+    }
+    for (int32_t a = 1; a < pl.n_seq; ++a) x[a] = x[pl.seq_par[a]] * b[a];
+}
+
+void initial_strategy(int prec, const PlayerPlan &pl, std::vector<char> &b, std::vector<char> &x)
+{
+    if (prec == CFR_FP64) initial_strategy_t<double, double>(pl, b, x);
+    else if (prec == CFR_FP32) initial_strategy_t<float, float>(pl, b, x);
+    else initial_strategy_t<float, double>(pl, b, x);
+}
+
+template <typename T>
+hipError_t h2d(void *dst, const T *src, size_t count, hipStream_t st)
+{
+    if (count == 0) return hipSuccess;
+    return hipMemcpyAsync(dst, src, sizeof(T) * count, hipMemcpyHostToDevice, st);
+}
+
+// Copies `count` doubles to the value type at dst (converting in chunks).
+hipError_t h2d_values(void *dst, const double *src, size_t count, int prec, hipStream_t st)
+{
+    if (count == 0) return hipSuccess;
+    if (value_bytes(prec) == 8) {
+        hipError_t e = h2d(dst, src, count, st);
+        if (e != hipSuccess) return e;
+        return hipStreamSynchronize(st);
+    }
+    const size_t kChunk = (size_t)1 << 24;
+    std::vector<float> tmp(std::min(count, kChunk));
+    for (size_t at = 0; at < count; at += kChunk) {
+        const size_t n = std::min(kChunk, count - at);
+        for (size_t i = 0; i < n; ++i) tmp[i] = (float)src[at + i];
+        hipError_t e = h2d((float *)dst + at, tmp.data(), n, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);  // tmp is reused
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+void transpose(int64_t n_rows, int64_t n_cols, const int64_t *ptr, const int32_t *idx,
+               const double *val, std::vector<int64_t> &tptr, std::vector<int32_t> &tidx,
+               std::vector<double> &tval)
+{
+    int64_t nnz = ptr[n_rows];
+    tptr.assign((size_t)n_cols + 1, 0);
+    for (int64_t e = 0; e < nnz; ++e) tptr[(size_t)idx[e] + 1]++;
+    for (int64_t c = 0; c < n_cols; ++c) tptr[c + 1] += tptr[c];
+    tidx.resize((size_t)nnz);
+    tval.resize((size_t)nnz);
+    std::vector<int64_t> fill(tptr.begin(), tptr.end() - 1);
+    for (int64_t i = 0; i < n_rows; ++i)
+        for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) {
+            int64_t pos = fill[idx[e]]++;
+            tidx[pos] = (int32_t)i;
+            tval[pos] = val[e];
+        }
+}
+
+void prepare_game(const cfr_game_desc *g, bool lone, bool with_matrix, HostGame &hg)
+{
+    for (int p = 0; p < 2; ++p) plan_player(g->player[p], lone, hg.pl[p]);
+    const PlayerPlan &a = hg.pl[0], &b = hg.pl[1];
+    hg.nnz = g->nnz;
+    const bool same = a.identity && b.identity;
+    if (!with_matrix) {
+        // row pointers in level order from the row and column lengths
+        hg.ptr[0].assign((size_t)a.n_seq + 1, 0);
+        for (int32_t r = 0; r < a.n_seq; ++r) {
+            const int32_t o = a.old_of_new[r];
+            hg.ptr[0][r + 1] = hg.ptr[0][r] + (int32_t)(g->row_ptr[o + 1] - g->row_ptr[o]);
+        }
+        std::vector<int32_t> cc((size_t)b.n_seq, 0);
+        for (int64_t e = 0; e < g->nnz; ++e) cc[g->col_idx[e]]++;
+        hg.ptr[1].assign((size_t)b.n_seq + 1, 0);
+        for (int32_t r = 0; r < b.n_seq; ++r) hg.ptr[1][r + 1] = hg.ptr[1][r] + cc[b.old_of_new[r]];
+        return;
+    }
+    const int64_t *rptr = g->row_ptr;
+    std::vector<int64_t> ptr_buf;
+    hg.idx[0] = g->col_idx;
+    hg.val[0] = g->val;
+    if (!same) {
+        permute_rows(a.n_seq, a.old_of_new, b.new_of_old, g->row_ptr, g->col_idx, g->val, ptr_buf,
+                     hg.own_idx[0], hg.own_val[0]);
+        rptr = ptr_buf.data();
+        hg.idx[0] = hg.own_idx[0].data();
+        hg.val[0] = hg.own_val[0].data();
+    }
+    hg.ptr[0] = narrow_ptr(rptr, (size_t)a.n_seq + 1);
+    if (same && g->col_ptr) {
+        // validated to be the exact transpose
+        hg.ptr[1] = narrow_ptr(g->col_ptr, (size_t)b.n_seq + 1);
+        hg.idx[1] = g->row_idx;
+        hg.val[1] = g->val_csc;
+    } else {
+        std::vector<int64_t> tptr;
+        transpose(a.n_seq, b.n_seq, rptr, hg.idx[0], hg.val[0], tptr, hg.own_idx[1],
+                  hg.own_val[1]);
+        hg.ptr[1] = narrow_ptr(tptr.data(), (size_t)b.n_seq + 1);
+        hg.idx[1] = hg.own_idx[1].data();
+        hg.val[1] = hg.own_val[1].data();
+    }
+}
+
+void own_game(HostGame &hg, int prec)
+{
+    for (int w = 0; w < 2; ++w) {
+        const size_t n = (size_t)hg.nnz;
+        if (hg.own_idx[w].empty() && n > 0) {
+            hg.own_idx[w].assign(hg.idx[w], hg.idx[w] + n);
+            hg.idx[w] = hg.own_idx[w].data();
+        }
+        if (value_bytes(prec) == 4) {
+            hg.own_valf[w].resize(n);
+            for (size_t i = 0; i < n; ++i) hg.own_valf[w][i] = (float)hg.val[w][i];
+            std::vector<double>().swap(hg.own_val[w]);
+            hg.val[w] = nullptr;
+        } else if (hg.own_val[w].empty() && n > 0) {
+            hg.own_val[w].assign(hg.val[w], hg.val[w] + n);
+            hg.val[w] = hg.own_val[w].data();
+        }
+    }
+}
+
+Capacity lone_capacity(const HostGame &hg, int items_csr, int rows_csr, int items_csc,
+                       int rows_csc)
+{
+    Capacity c;
+    c.slots = 1;
+    for (int p = 0; p < 2; ++p) {
+        const PlayerPlan &pl = hg.pl[p];
+        c.seq[p] = (int64_t)pl.n_seq + 1;
+        c.inf[p] = (int64_t)pl.n_inf + 1;
+        c.t_up[p] = 0;
+        c.t_down[p] = 0;
+        for (int32_t lv = 0; lv < pl.n_levels; ++lv) {
+            c.t_up[p] += chunks(pl.lvl_inf[lv + 1] - pl.lvl_inf[lv]);
+            if (lv > 0) c.t_down[p] += chunks(pl.lvl_seq[lv + 1] - pl.lvl_seq[lv]);
+        }
+        c.t_seq[p] = chunks(pl.n_seq);
+        c.top_off[p] = (int64_t)pl.top_off.size();
+        c.top_list[p] = (int64_t)pl.top_list.size();
+    }
+    c.nnz = hg.nnz;
+    // product tables large enough for every tiling the tuner may choose
+    // (the most blocks come from the smallest caps)
+    (void)items_csr;
+    (void)rows_csr;
+    (void)items_csc;
+    (void)rows_csc;
+    c.t_csr = (int64_t)partition_rows(hg.ptr[0], kSpmvThreads * 4, 64).size() - 1;
+    c.t_csc = (int64_t)partition_rows(hg.ptr[1], kSpmvThreads * 4, 64).size() - 1;
+    return c;
+}
+
+void bound_tables(Capacity &c)
+{
+    // A game's product blocks: two consecutive blocks together exceed the
+    // nonzero cap unless the row cap closed the first, so a game with z
+    // nonzeros and n rows has at most 2 z / cap + n / row_cap + 2 blocks
+    // (smallest tiling: cap 1024 nonzeros, 64 rows).  Range blocks: one per
+    // kRangeBlock indices plus one partial block per (game, level), and a
+    // game has at most as many levels as decision points.
+    for (int w = 0; w < 2; ++w) {
+        const int64_t t = 2 * c.nnz / (kSpmvThreads * 4) + c.seq[w] / 64 + 2 * c.slots + 1;
+        if (w == 0) c.t_csr = t;
+        else c.t_csc = t;
+    }
+    for (int p = 0; p < 2; ++p) {
+        c.t_up[p] = c.inf[p] / kRangeBlock + c.inf[p] + 1;
+        c.t_down[p] = c.seq[p] / kRangeBlock + c.inf[p] + 1;
+        c.t_seq[p] = c.seq[p] / kRangeBlock + c.slots + 1;
+        c.top_off[p] = 0;
+        c.top_list[p] = 0;
+    }
+}
+
+size_t engine_bytes(const Capacity &c, int prec)
+{
+    Carver k;
+    carve(k, c, prec);
+    return k.cur + 256;
+}
+
+// ---------------------------------------------------------------------------
+// Range allocator
+// ---------------------------------------------------------------------------
+
+void RangeAlloc::init(int64_t c)
+{
+    cap = c;
+    free_.clear();
+    if (c > 0) free_[0] = c;
+}
+
+int64_t RangeAlloc::take(int64_t n)
+{
+    if (n <= 0) return 0;
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+        if (it->second < n) continue;
+        const int64_t at = it->first, len = it->second;
+        free_.erase(it);
+        if (len > n) free_[at + n] = len - n;
+        return at;
+    }
+    return -1;
+}
+
+void RangeAlloc::give(int64_t at, int64_t n)
+{
+    if (n <= 0) return;
+    auto it = free_.emplace(at, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            free_.erase(it);
+        }
+    }
+}
+
+int64_t RangeAlloc::largest() const
+{
+    int64_t m = 0;
+    for (const auto &kv : free_) m = std::max(m, kv.second);
+    return m;
+}
+
+// ---------------------------------------------------------------------------
+// Engine
+// ---------------------------------------------------------------------------
+
+int Engine::init(const Capacity &c, int precision, int dev, hipStream_t stream, void *workspace,
+                 size_t workspace_bytes)
+{
+    cap = c;
+    prec = precision;
+    device = dev;
+    st = stream;
+    const size_t need = engine_bytes(c, prec);
+    if (workspace) {
+        if (workspace_bytes < need)
+            return fail(CFR_ENOMEM, "workspace smaller than the required size");
+        ws = workspace;
+        ws_bytes = workspace_bytes;
+        own_ws = false;
+    } else {
+        hipError_t e = hipMalloc(&ws, need);
+        if (e != hipSuccess) {
+            ws = nullptr;
+            return fail(CFR_ENOMEM, hip_msg("hipMalloc of the workspace", e));
+        }
+        ws_bytes = need;
+        own_ws = true;
+    }
+    Carver k;
+    k.base = (char *)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+    Layout L = carve(k, c, prec);
+    sc = L.sc;
+    partials = L.partials;
+    for (int p = 0; p < 2; ++p) dp[p] = L.dp[p];
+    for (int w = 0; w < 2; ++w) {
+        ptr[w] = L.ptr[w];
+        idx[w] = L.idx[w];
+        val[w] = L.val[w];
+    }
+    tab_region[0] = L.tab[0];
+    tab_region[1] = L.tab[1];
+    tab_bytes = L.tab_bytes;
+    const TableLayout T = table_layout(c);
+    Tables *ts[2] = {&it, &ev};
+    for (int r = 0; r < 2; ++r) {
+        Tables &t = *ts[r];
+        char *base = tab_region[r];
+        t.csr = (SpmvBlock *)(base + T.csr);
+        t.csc = (SpmvBlock *)(base + T.csc);
+        for (int p = 0; p < 2; ++p) {
+            t.up[p] = (RangeBlock *)(base + T.up[p]);
+            t.down[p] = (RangeBlock *)(base + T.down[p]);
+            t.seq[p] = (RangeBlock *)(base + T.seq[p]);
+            t.root[p] = (SlotRef *)(base + T.root[p]);
+        }
+        t.fin = (SlotRef *)(base + T.fin);
+        t.valid = false;
+    }
+    // Every index array starts at zero: the fast sweep path issues clamped
+    // loads that may read child_idx[0] of an unused range.
+    hipError_t e = hipMemsetAsync(sc, 0, sizeof(Scalars) * (size_t)c.slots, st);
+    for (int p = 0; p < 2 && e == hipSuccess; ++p)
+        e = hipMemsetAsync(dp[p].child_idx, 0, 4 * (size_t)std::max<int64_t>(c.inf[p], 1), st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return device_error("workspace initialisation", e);
+    for (int p = 0; p < 2; ++p) {
+        seq_alloc[p].init(c.seq[p]);
+        inf_alloc[p].init(c.inf[p]);
+    }
+    nnz_alloc.init(c.nnz);
+    slots.assign((size_t)c.slots, Slot());
+    return CFR_OK;
+}
+
+void Engine::drop_graph()
+{
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+}
+
+void Engine::release()
+{
+    for (int k = 0; k < 2; ++k) {
+        for (auto &pr : events[k]) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+        events[k].clear();
+    }
+    drop_graph();
+    if (cap_st) (void)hipStreamDestroy(cap_st);
+    cap_st = nullptr;
+    if (own_ws && ws) (void)hipFree(ws);
+    ws = nullptr;
+}
+
+int Engine::device_error(const char *what, hipError_t e)
+{
+    failed = true;
+    return fail(CFR_EDEVICE, hip_msg(what, e));
+}
+
+int Engine::sync(const char *what)
+{
+    hipError_t e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return device_error(what, e);
+    return CFR_OK;
+}
+
+int Engine::sequential() const
+{
+    if (spmv_order == CFR_SPMV_SEQUENTIAL) return 1;
+    if (spmv_order == CFR_SPMV_PARALLEL) return 0;
+    return prec == CFR_FP64 ? 1 : 0;
+}
+
+void Engine::partition(Slot &s, int which)
+{
+    const int k = (int)(&s - slots.data());
+    const std::vector<int32_t> blk =
+        partition_rows(s.ptr[which], kSpmvThreads * items[which], rows[which]);
+    s.blocks[which].clear();
+    s.blocks[which].reserve(blk.size());
+    for (size_t i = 0; i + 1 < blk.size(); ++i) {
+        const int32_t r0 = blk[i], r1 = blk[i + 1];
+        SpmvBlock b{};
+        b.row0 = (int32_t)(s.sb[which] + r0);
+        b.nr = r1 - r0;
+        b.n = s.ptr[which][r1] - s.ptr[which][r0];
+        b.p0 = s.ptr[which][r0];
+        b.e0 = s.nb + s.ptr[which][r0];
+        b.slot = k;
+        b.begin = i == 0 ? 1 : 0;
+        s.blocks[which].push_back(b);
+    }
+}
+
+void Engine::repartition(int which, int items_, int rows_)
+{
+    items[which] = items_;
+    rows[which] = rows_;
+    for (Slot &s : slots)
+        if (s.live) partition(s, which);
+    it.valid = false;
+    ev.valid = false;
+    drop_graph();
+}
+
+int Engine::set_params(int k, const GameParams &gp)
+{
+    Slot &s = slots[(size_t)k];
+    s.gp = gp;
+    struct {
+        double alpha, beta, gamma;
+        int32_t variant, avg_kind;
+    } h{gp.alpha, gp.beta, gp.gamma, gp.variant, gp.avg_kind};
+    static_assert(sizeof(h) == offsetof(Scalars, pad) - offsetof(Scalars, alpha), "layout");
+    hipError_t e = hipMemcpyAsync((char *)(sc + k) + offsetof(Scalars, alpha), &h, sizeof h,
+                                  hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return device_error("game constants", e);
+    it.valid = false;
+    ev.valid = false;
+    drop_graph();
+    return CFR_OK;
+}
+
+int Engine::add(const HostGame &hg, const GameParams &gp, bool join_now, int *slot_out)
+{
+    int k = -1;
+    for (size_t i = 0; i < slots.size(); ++i)
+        if (!slots[i].live) {
+            k = (int)i;
+            break;
+        }
+    if (k < 0) return fail(CFR_ENOMEM, "every game slot is in use");
+    int64_t sb[2] = {-1, -1}, ib[2] = {-1, -1}, nb = -1;
+    bool ok = true;
+    for (int p = 0; p < 2 && ok; ++p) {
+        sb[p] = seq_alloc[p].take((int64_t)hg.pl[p].n_seq + 1);
+        if (sb[p] < 0) ok = false;
+        else {
+            ib[p] = inf_alloc[p].take((int64_t)hg.pl[p].n_inf + 1);
+            if (ib[p] < 0) ok = false;
+        }
+    }
+    if (ok) {
+        nb = hg.nnz > 0 ? nnz_alloc.take(hg.nnz) : 0;
+        if (nb < 0) ok = false;
+    }
+    if (!ok) {
+        for (int p = 0; p < 2; ++p) {
+            if (sb[p] >= 0) seq_alloc[p].give(sb[p], (int64_t)hg.pl[p].n_seq + 1);
+            if (ib[p] >= 0) inf_alloc[p].give(ib[p], (int64_t)hg.pl[p].n_inf + 1);
+        }
+        return fail(CFR_ENOMEM, "the game does not fit the free device capacity");
+    }
+    Slot &s = slots[(size_t)k];
+    s = Slot();
+    s.id = next_id++;
+    s.gp = gp;
+    s.nb = nb;
+    s.nnz = hg.nnz;
+    hipError_t e = hipSuccess;
+#define CHECK(x)                                                 \
+    do {                                                         \
+        e = (x);                                                 \
+        if (e != hipSuccess) return device_error("add game", e); \
+    } while (0)
+    for (int p = 0; p < 2; ++p) {
+        const PlayerPlan &pl = hg.pl[p];
+        s.sb[p] = sb[p];
+        s.ib[p] = ib[p];
+        s.n_seq[p] = pl.n_seq;
+        s.n_inf[p] = pl.n_inf;
+        s.n_levels[p] = pl.n_levels;
+        s.lvl_inf[p] = pl.lvl_inf;
+        s.lvl_seq[p] = pl.lvl_seq;
+        s.lvl_kind[p] = pl.lvl_kind;
+        s.old_of_new[p] = pl.old_of_new;
+        const int32_t S = (int32_t)sb[p], I = (int32_t)ib[p];
+        const size_t n = (size_t)pl.n_seq, ni = (size_t)pl.n_inf;
+        std::vector<int32_t> v(n + 1);
+        for (size_t i = 0; i <= ni; ++i) v[i] = pl.inf_first[i] + S;
+        CHECK(h2d(dp[p].inf_first + I, v.data(), ni + 1, st));
+        CHECK(hipStreamSynchronize(st));
+        for (size_t i = 0; i < n; ++i) v[i] = pl.seq_par[i] + S;
+        v[n] = S;
+        CHECK(h2d(dp[p].seq_par + S, v.data(), n + 1, st));
+        CHECK(hipStreamSynchronize(st));
+        for (size_t i = 0; i <= n; ++i) v[i] = pl.child_ptr[i] + I;
+        CHECK(h2d(dp[p].child_ptr + S, v.data(), n + 1, st));
+        CHECK(hipStreamSynchronize(st));
+        for (size_t i = 0; i < ni; ++i) v[i] = pl.child_idx[i] + I;
+        CHECK(h2d(dp[p].child_idx + I, v.data(), ni, st));
+        CHECK(hipStreamSynchronize(st));
+        if (lone) {
+            CHECK(h2d(dp[p].top_off, pl.top_off.data(), pl.top_off.size(), st));
+            CHECK(h2d(dp[p].top_list, pl.top_list.data(), pl.top_list.size(), st));
+            dp[p].top_levels = pl.top_levels;
+            dp[p].n_roots = pl.n_roots;
+            dp[p].top_fast = 1;
+            for (int32_t lv = 0; lv < pl.top_levels; ++lv) dp[p].top_fast &= pl.lvl_kind[lv] != 0;
+        }
+        // state: zero regrets, predictions and averages; uniform strategy
+        const size_t R = accum_bytes(prec), V = value_bytes(prec);
+        CHECK(hipMemsetAsync((char *)dp[p].r + R * (size_t)S, 0, R * (n + 1), st));
+        CHECK(hipMemsetAsync((char *)dp[p].m + R * (size_t)S, 0, R * (n + 1), st));
+        CHECK(hipMemsetAsync((char *)dp[p].s + R * (size_t)S, 0, R * (n + 1), st));
+        std::vector<char> hb, hx;
+        initial_strategy(prec, pl, hb, hx);
+        CHECK(hipMemcpyAsync((char *)dp[p].b + V * (size_t)S, hb.data(), hb.size(),
+                             hipMemcpyHostToDevice, st));
+        CHECK(hipMemcpyAsync((char *)dp[p].x + V * (size_t)S, hx.data(), hx.size(),
+                             hipMemcpyHostToDevice, st));
+        CHECK(hipStreamSynchronize(st));
+    }
+    // payoff matrix: row pointers at the row player's sequences, indices
+    // shifted to the column player's global sequences
+    for (int w = 0; w < 2; ++w) {
+        s.ptr[w] = hg.ptr[w];
+        CHECK(h2d(ptr[w] + sb[w], hg.ptr[w].data(), hg.ptr[w].size(), st));
+        CHECK(h2d(idx[w] + nb, hg.idx[w], (size_t)hg.nnz, st));
+        const int32_t col_base = (int32_t)sb[1 - w];
+        if (col_base != 0) CHECK(launch_add_offset(idx[w] + nb, hg.nnz, col_base, st));
+        CHECK(hipStreamSynchronize(st));
+        if (!hg.own_valf[w].empty() && value_bytes(prec) == 4) {
+            CHECK(h2d((float *)val[w] + nb, hg.own_valf[w].data(), (size_t)hg.nnz, st));
+            CHECK(hipStreamSynchronize(st));
+        } else {
+            CHECK(h2d_values((char *)val[w] + value_bytes(prec) * (size_t)nb, hg.val[w],
+                             (size_t)hg.nnz, prec, st));
+        }
+    }
+    // the game's scalars: t = 0, its constants
+    {
+        Scalars h{};
+        h.alpha = gp.alpha;
+        h.beta = gp.beta;
+        h.gamma = gp.gamma;
+        h.variant = gp.variant;
+        h.avg_kind = gp.avg_kind;
+        CHECK(hipMemcpyAsync(sc + k, &h, sizeof h, hipMemcpyHostToDevice, st));
+        CHECK(hipStreamSynchronize(st));
+    }
+#undef CHECK
+    s.live = true;
+    partition(s, 0);
+    partition(s, 1);
+    s.active = join_now;
+    s.pending = !join_now;
+    if (join_now) {
+        it.valid = false;
+        drop_graph();
+    }
+    *slot_out = k;
+    return CFR_OK;
+}
+
+void Engine::remove(int k)
+{
+    Slot &s = slots[(size_t)k];
+    if (!s.live) return;
+    for (int p = 0; p < 2; ++p) {
+        seq_alloc[p].give(s.sb[p], (int64_t)s.n_seq[p] + 1);
+        inf_alloc[p].give(s.ib[p], (int64_t)s.n_inf[p] + 1);
+    }
+    if (s.nnz > 0) nnz_alloc.give(s.nb, s.nnz);
+    const bool was_active = s.active;
+    s = Slot();
+    if (was_active) {
+        it.valid = false;
+        drop_graph();
+    }
+    ev.valid = false;
+}
+
+std::vector<int> Engine::active_set() const
+{
+    std::vector<int> out;
+    for (size_t i = 0; i < slots.size(); ++i)
+        if (slots[i].live && slots[i].active) out.push_back((int)i);
+    return out;
+}
+
+// Every entry stays inside its own game's ranges (what the kernels index).
+bool Engine::tables_in_bounds(const Tables &T) const
+{
+    auto live = [&](int k) { return k >= 0 && k < (int)slots.size() && slots[(size_t)k].live; };
+    for (int w = 0; w < 2; ++w) {
+        const std::vector<SpmvBlock> &v = w == 0 ? T.h_csr : T.h_csc;
+        const int cap_nnz = kSpmvThreads * items[w];
+        for (const SpmvBlock &b : v) {
+            if (!live(b.slot)) return false;
+            const Slot &s = slots[(size_t)b.slot];
+            if (b.nr < 1 || b.nr > kSpmvRowCap || b.n < 0 || (b.n > cap_nnz && b.nr != 1))
+                return false;
+            if (b.row0 < s.sb[w] || (int64_t)b.row0 + b.nr > s.sb[w] + s.n_seq[w]) return false;
+            if (b.e0 < s.nb || b.e0 + b.n > s.nb + s.nnz) return false;
+            if (b.e0 - s.nb != b.p0) return false;
+        }
+    }
+    for (int p = 0; p < 2; ++p) {
+        for (const RangeBlock &r : T.h_up[p]) {
+            if (!live(r.slot)) return false;
+            const Slot &s = slots[(size_t)r.slot];
+            if (r.hi - r.lo < 1 || r.hi - r.lo > kRangeBlock || r.lo < s.ib[p] ||
+                r.hi > s.ib[p] + s.n_inf[p])
+                return false;
+        }
+        for (const std::vector<RangeBlock> *v : {&T.h_down[p], &T.h_seq[p]})
+            for (const RangeBlock &r : *v) {
+                if (!live(r.slot)) return false;
+                const Slot &s = slots[(size_t)r.slot];
+                if (r.hi - r.lo < 1 || r.hi - r.lo > kRangeBlock || r.lo < s.sb[p] ||
+                    r.hi > s.sb[p] + s.n_seq[p])
+                    return false;
+            }
+        for (const SlotRef &r : T.h_root[p]) {
+            if (!live(r.slot)) return false;
+            const Slot &s = slots[(size_t)r.slot];
+            if (r.root != s.sb[p] || r.a < s.ib[p] || r.b < r.a || r.b > s.ib[p] + s.n_inf[p])
+                return false;
+        }
+    }
+    for (const SlotRef &r : T.h_fin)
+        if (!live(r.slot) || r.a < 0 || r.b < r.a || r.b > (int32_t)T.h_seq[0].size()) return false;
+    return true;
+}
+
+int Engine::build_tables(Tables &T, char *region, const std::vector<int> &set)
+{
+    (void)region;
+    // the previous upload may still be in flight
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return device_error("table upload", e);
+    const double V = (double)value_bytes(prec);
+    T.h_csr.clear();
+    T.h_csc.clear();
+    T.h_fin.clear();
+    T.bytes[0] = T.bytes[1] = 0;
+    for (int k : set) {
+        const Slot &s = slots[(size_t)k];
+        T.h_csr.insert(T.h_csr.end(), s.blocks[0].begin(), s.blocks[0].end());
+        T.h_csc.insert(T.h_csc.end(), s.blocks[1].begin(), s.blocks[1].end());
+        for (int w = 0; w < 2; ++w)
+            T.bytes[w] += (double)s.nnz * (4.0 + V) + 4.0 * (s.n_seq[w] + 1) +
+                          V * s.n_seq[1 - w] + V * s.n_seq[w];
+    }
+    std::vector<int> classes;
+    for (int k : set) classes.push_back(slots[(size_t)k].gp.variant);
+    std::sort(classes.begin(), classes.end());
+    classes.erase(std::unique(classes.begin(), classes.end()), classes.end());
+    auto push_chunks = [](std::vector<RangeBlock> &v, int64_t lo, int64_t hi, int k, int32_t aux) {
+        for (int64_t a = lo; a < hi; a += kRangeBlock)
+            v.push_back(RangeBlock{(int32_t)a, (int32_t)std::min<int64_t>(hi, a + kRangeBlock), k,
+                                   aux});
+    };
+    for (int p = 0; p < 2; ++p) {
+        int maxL = 0;
+        for (int k : set) maxL = std::max(maxL, (int)slots[(size_t)k].n_levels[p]);
+        T.h_up[p].clear();
+        T.h_down[p].clear();
+        T.h_seq[p].clear();
+        T.h_root[p].clear();
+        T.up_l[p].assign((size_t)maxL, {});
+        T.up_level[p].assign((size_t)maxL, {0, 0});
+        T.down_l[p].assign((size_t)maxL, {0, 0});
+        for (int L = 0; L < maxL; ++L) {
+            const int32_t lvl_start = (int32_t)T.h_up[p].size();
+            for (int c : classes) {
+                const int32_t off = (int32_t)T.h_up[p].size();
+                int kind = 2;
+                for (int k : set) {
+                    const Slot &s = slots[(size_t)k];
+                    if (s.gp.variant != c || L >= s.n_levels[p]) continue;
+                    push_chunks(T.h_up[p], s.ib[p] + s.lvl_inf[p][L], s.ib[p] + s.lvl_inf[p][L + 1],
+                                k, 0);
+                    kind = std::min(kind, (int)s.lvl_kind[p][L]);
+                }
+                const int32_t n = (int32_t)T.h_up[p].size() - off;
+                if (n > 0) T.up_l[p][L].push_back(Tables::Up{off, n, c, kind});
+            }
+            T.up_level[p][L] = {lvl_start, (int32_t)T.h_up[p].size() - lvl_start};
+            if (L > 0) {
+                const int32_t off = (int32_t)T.h_down[p].size();
+                for (int k : set) {
+                    const Slot &s = slots[(size_t)k];
+                    if (L >= s.n_levels[p]) continue;
+                    push_chunks(T.h_down[p], s.sb[p] + s.lvl_seq[p][L], s.sb[p] + s.lvl_seq[p][L + 1],
+                                k, 0);
+                }
+                T.down_l[p][L] = {off, (int32_t)T.h_down[p].size() - off};
+            }
+        }
+        for (int k : set) {
+            const Slot &s = slots[(size_t)k];
+            const int32_t first = (int32_t)T.h_seq[p].size();
+            push_chunks(T.h_seq[p], s.sb[p], s.sb[p] + s.n_seq[p], k, (int32_t)s.sb[p]);
+            if (p == 0) T.h_fin.push_back(SlotRef{k, 0, first, (int32_t)T.h_seq[p].size()});
+            const int32_t j0 = s.n_levels[p] > 0 ? s.lvl_inf[p][0] : 0;
+            const int32_t j1 = s.n_levels[p] > 0 ? s.lvl_inf[p][1] : 0;
+            T.h_root[p].push_back(
+                SlotRef{k, (int32_t)s.sb[p], (int32_t)(s.ib[p] + j0), (int32_t)(s.ib[p] + j1)});
+        }
+        if ((int64_t)T.h_up[p].size() > cap.t_up[p] || (int64_t)T.h_down[p].size() > cap.t_down[p] ||
+            (int64_t)T.h_seq[p].size() > cap.t_seq[p])
+            return fail(CFR_EINVAL, "internal: sweep tables exceed their capacity");
+        T.n_seq[p] = (int32_t)T.h_seq[p].size();
+        T.n_root[p] = (int32_t)T.h_root[p].size();
+    }
+    if ((int64_t)T.h_csr.size() > cap.t_csr || (int64_t)T.h_csc.size() > cap.t_csc)
+        return fail(CFR_EINVAL, "internal: product tables exceed their capacity");
+    T.n_csr = (int32_t)T.h_csr.size();
+    T.n_csc = (int32_t)T.h_csc.size();
+    T.n_fin = (int32_t)T.h_fin.size();
+    if (!tables_in_bounds(T)) return fail(CFR_EINVAL, "internal: a table entry leaves its game");
+    e = h2d(T.csr, T.h_csr.data(), T.h_csr.size(), st);
+    if (e == hipSuccess) e = h2d(T.csc, T.h_csc.data(), T.h_csc.size(), st);
+    for (int p = 0; p < 2 && e == hipSuccess; ++p) {
+        e = h2d(T.up[p], T.h_up[p].data(), T.h_up[p].size(), st);
+        if (e == hipSuccess) e = h2d(T.down[p], T.h_down[p].data(), T.h_down[p].size(), st);
+        if (e == hipSuccess) e = h2d(T.seq[p], T.h_seq[p].data(), T.h_seq[p].size(), st);
+        if (e == hipSuccess) e = h2d(T.root[p], T.h_root[p].data(), T.h_root[p].size(), st);
+    }
+    if (e == hipSuccess) e = h2d(T.fin, T.h_fin.data(), T.h_fin.size(), st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return device_error("table upload", e);
+    T.valid = true;
+    return CFR_OK;
+}
+
+int Engine::rebuild()
+{
+    drop_graph();
+    int rc = build_tables(it, tab_region[0], active_set());
+    if (rc) it.valid = false;
+    return rc;
+}
+
+hipError_t Engine::spmv(const Tables &T, int which, const void *xin, void *yout, bool begin,
+                        hipStream_t s, bool timed)
+{
+    const SpmvBlock *tab = which == 0 ? T.csr : T.csc;
+    const int32_t n = which == 0 ? T.n_csr : T.n_csc;
+    if (timed) {
+        hipEvent_t a, b;
+        hipError_t e = hipEventCreate(&a);
+        if (e == hipSuccess) e = hipEventCreate(&b);
+        if (e != hipSuccess) return e;
+        (void)hipEventRecord(a, s);
+        e = launch_spmv(prec, items[which], tab, n, ptr[which], idx[which], val[which], xin, yout,
+                        xcd_remap, sequential(), begin ? 1 : 0, sc, s);
+        (void)hipEventRecord(b, s);
+        events[which].emplace_back(a, b);
+        launches[which]++;
+        return e;
+    }
+    return launch_spmv(prec, items[which], tab, n, ptr[which], idx[which], val[which], xin, yout,
+                       xcd_remap, sequential(), begin ? 1 : 0, sc, s);
+}
+
+hipError_t Engine::sweeps(const Tables &T, int p, double usign, hipStream_t s)
+{
+    const DevPlayer &d = dp[p];
+    const int maxL = (int)T.up_l[p].size();
+    hipError_t e;
+    const bool top = lone && d.top_levels > 0;
+    const int low = top ? d.top_levels : 0;
+    // ObserveUtility, deepest level first (level 0's launch also does its
+    // top-down step)
+    for (int L = maxL - 1; L >= low; --L)
+        for (const Tables::Up &u : T.up_l[p][(size_t)L])
+            if ((e = launch_up(prec, u.variant, u.kind, L == 0 ? 1 : 0, T.up[p] + u.off, u.n, d,
+                               usign, sc, s)) != hipSuccess)
+                return e;
+    if (top) {
+        // the shallow levels of the lone game, both directions, one launch
+        if ((e = launch_top(prec, slots[0].gp.variant, d, usign, 1, sc, s)) != hipSuccess) return e;
+    }
+    for (int L = std::max(low, 1); L < maxL; ++L) {
+        const auto &dl = T.down_l[p][(size_t)L];
+        if ((e = launch_down(prec, T.down[p] + dl.first, dl.second, d, 1, sc, s)) != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t Engine::enqueue_iteration(hipStream_t s)
+{
+    hipError_t e;
+    const bool timed = timing && s == st;
+    if (mode == CFR_SIMULTANEOUS) {
+        // both products read the strategies of iteration t before either
+        // player moves on
+        if ((e = spmv(it, 0, dp[1].x, dp[0].g, true, s, timed)) != hipSuccess) return e;
+        if ((e = spmv(it, 1, dp[0].x, dp[1].g, false, s, timed)) != hipSuccess) return e;
+        if ((e = sweeps(it, 0, 1.0, s)) != hipSuccess) return e;
+        return sweeps(it, 1, -1.0, s);
+    }
+    if ((e = spmv(it, 0, dp[1].x, dp[0].g, true, s, timed)) != hipSuccess) return e;
+    if ((e = sweeps(it, 0, 1.0, s)) != hipSuccess) return e;
+    if ((e = spmv(it, 1, dp[0].x, dp[1].g, false, s, timed)) != hipSuccess) return e;
+    return sweeps(it, 1, -1.0, s);
+}
+
+hipError_t Engine::build_graph()
+{
+    hipError_t e = hipSuccess;
+    if (!cap_st) {
+        e = hipStreamCreateWithFlags(&cap_st, hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+    }
+    e = hipStreamBeginCapture(cap_st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t e2 = enqueue_iteration(cap_st);
+    e = hipStreamEndCapture(cap_st, &graph);
+    if (e2 != hipSuccess) return e2;
+    if (e != hipSuccess) return e;
+    return hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+}
+
+int Engine::iterate(int64_t n)
+{
+    if (n <= 0) return CFR_OK;
+    if (mode != CFR_SIMULTANEOUS && mode != CFR_ALTERNATING)
+        return fail(CFR_ESTATE, "update mode not set");
+    if (!it.valid) {
+        int rc = rebuild();
+        if (rc) return rc;
+    }
+    const std::vector<int> act = active_set();
+    if (act.empty()) return CFR_OK;
+    for (int k : act)
+        if (slots[(size_t)k].gp.variant < CFR_VANILLA)
+            return fail(CFR_ESTATE, "a game has no regret minimiser set");
+    hipError_t e = hipSuccess;
+    if (use_graph && !timing) {
+        if (!gexec) {
+            e = build_graph();
+            if (e != hipSuccess) {
+                drop_graph();
+                return device_error("graph capture of one iteration", e);
+            }
+        }
+        for (int64_t i = 0; i < n && e == hipSuccess; ++i) e = hipGraphLaunch(gexec, st);
+    } else {
+        for (int64_t i = 0; i < n && e == hipSuccess; ++i) e = enqueue_iteration(st);
+    }
+    if (e != hipSuccess) return device_error("iteration launch", e);
+    for (int k : act) slots[(size_t)k].t += n;
+    return CFR_OK;
+}
+
+int Engine::evaluate(const std::vector<int> &set, int kind)
+{
+    if (set.empty()) return CFR_OK;
+    const Tables *T = nullptr;
+    if (it.valid && set == active_set()) {
+        T = &it;
+    } else {
+        if (!(ev.valid && ev_set == set)) {
+            ev.valid = false;
+            int rc = build_tables(ev, tab_region[1], set);
+            if (rc) return rc;
+            ev_set = set;
+        }
+        T = &ev;
+    }
+    hipError_t e = hipSuccess;
+#define CHECK(x)                                                     \
+    do {                                                             \
+        e = (x);                                                     \
+        if (e != hipSuccess) return device_error("evaluation", e);   \
+    } while (0)
+    const void *src[2] = {dp[0].x, dp[1].x};
+    if (kind == CFR_AVERAGE) {
+        for (int p = 0; p < 2; ++p) {
+            CHECK(launch_normalize(prec, T->seq[p], T->n_seq[p], dp[p], sc, st));
+            src[p] = dp[p].xbar;
+        }
+    }
+    CHECK(spmv(*T, 0, src[1], dp[0].g, false, st, false));
+    CHECK(spmv(*T, 1, src[0], dp[1].g, false, st, false));
+    for (int p = 0; p < 2; ++p) {
+        const double usign = p == 0 ? 1.0 : -1.0;
+        for (int L = (int)T->up_level[p].size() - 1; L >= 0; --L) {
+            const auto &ul = T->up_level[p][(size_t)L];
+            CHECK(launch_br(prec, T->up[p] + ul.first, ul.second, dp[p], usign, st));
+        }
+        CHECK(launch_root_value(prec, T->root[p], T->n_root[p], dp[p], usign, sc, p, st));
+    }
+    CHECK(launch_dot(prec, T->seq[0], T->n_seq[0], src[0], dp[0].g, partials, T->fin, T->n_fin,
+                     sc, 2, st));
+    std::vector<Scalars> h(slots.size());
+    CHECK(hipMemcpyAsync(h.data(), sc, sizeof(Scalars) * h.size(), hipMemcpyDeviceToHost, st));
+#undef CHECK
+    int rc = sync("evaluation");
+    if (rc) return rc;
+    for (int k : set) {
+        Slot &s = slots[(size_t)k];
+        const double br1 = h[(size_t)k].out[0], br2 = h[(size_t)k].out[1];
+        s.last[0] = (br1 + br2) / 2.0;
+        s.last[1] = br1 + br2;
+        s.last[2] = br1;
+        s.last[3] = br2;
+        s.last[4] = h[(size_t)k].out[2];
+        s.last_t = s.t;
+    }
+    return CFR_OK;
+}
+
+int Engine::run(int64_t n)
+{
+    int64_t done = 0;
+    while (done < n) {
+        if (phase == 0) {
+            // games admitted since the last check join now
+            bool joined = false;
+            for (Slot &s : slots)
+                if (s.live && s.pending) {
+                    s.pending = false;
+                    s.active = true;
+                    joined = true;
+                }
+            if (joined) {
+                it.valid = false;
+                drop_graph();
+            }
+        }
+        const std::vector<int> act = active_set();
+        if (act.empty()) break;
+        const int64_t chunk =
+            check_every > 0 ? std::min(check_every - phase, n - done) : n - done;
+        int rc = iterate(chunk);
+        if (rc) return rc;
+        done += chunk;
+        if (check_every <= 0) continue;
+        phase += chunk;
+        if (phase < check_every) continue;
+        phase = 0;
+        rc = evaluate(act, CFR_AVERAGE);
+        if (rc) return rc;
+        bool changed = false;
+        for (int k : act) {
+            Slot &s = slots[(size_t)k];
+            const bool hit = s.gp.target > 0 && s.last[0] <= s.gp.target;
+            if (hit) s.reached = true;
+            if (hit || (s.gp.max_it > 0 && s.t >= s.gp.max_it)) {
+                s.active = false;
+                changed = true;
+            }
+        }
+        if (changed) {
+            it.valid = false;
+            drop_graph();
+        }
+    }
+    return CFR_OK;
+}
+
+int Engine::time_spmv(int which, int reps, double *ms)
+{
+    if (!it.valid) {
+        int rc = rebuild();
+        if (rc) return rc;
+    }
+    hipEvent_t a, b;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e != hipSuccess) return device_error("event", e);
+    const void *xin = which == 0 ? dp[1].x : dp[0].x;
+    void *yout = which == 0 ? dp[0].g : dp[1].g;
+    // one untimed launch, then `reps` timed ones
+    e = spmv(it, which, xin, yout, false, st, false);
+    if (e == hipSuccess) e = hipEventRecord(a, st);
+    for (int i = 0; i < reps && e == hipSuccess; ++i) e = spmv(it, which, xin, yout, false, st, false);
+    if (e == hipSuccess) e = hipEventRecord(b, st);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float t = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (e != hipSuccess) return device_error("product timing", e);
+    *ms = (double)t / std::max(reps, 1);
+    return CFR_OK;
+}
+
+int Engine::fetch_vector(int k, int player, int what, std::vector<double> &out)
+{
+    const Slot &s = slots[(size_t)k];
+    const size_t n = (size_t)s.n_seq[player];
+    const int64_t S = s.sb[player];
+    out.assign(n, 0.0);
+    const bool acc = what != 0;  // regrets and averages live in the accumulator type
+    const size_t el = acc ? accum_bytes(prec) : value_bytes(prec);
+    const void *src = what == 0 ? dp[player].x : what == 1 ? dp[player].s : dp[player].r;
+    std::vector<char> h(n * el);
+    Scalars hs{};
+    hipError_t e = hipMemcpyAsync(h.data(), (const char *)src + el * (size_t)S, n * el,
+                                  hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && what == 1)
+        e = hipMemcpyAsync(&hs, sc + k, sizeof hs, hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return device_error("device-to-host copy", e);
+    int rc = sync("device-to-host copy");
+    if (rc) return rc;
+    auto load = [&](size_t i) -> double {
+        if (el == 8) {
+            double v;
+            std::memcpy(&v, h.data() + i * 8, 8);
+            return v;
+        }
+        float v;
+        std::memcpy(&v, h.data() + i * 4, 4);
+        return (double)v;
+    };
+    if (what == 1 && hs.W <= 0) return fetch_vector(k, player, 0, out);  // no iteration yet
+    for (size_t i = 0; i < n; ++i) {
+        double v = load(i);
+        if (what == 1) v = i == 0 ? 1.0 : v / hs.W;
+        if (what == 2 && i == 0) v = 0.0;
+        out[(size_t)s.old_of_new[player][i]] = v;
+    }
+    return CFR_OK;
+}
+
+}  // namespace cfr

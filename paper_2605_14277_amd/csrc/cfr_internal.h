@@ -1,5 +1,15 @@
-// Internal declarations shared by the host runtime (cfr_api.hip) and the
-// kernel launchers (cfr_kernels.hip).  Not part of the public ABI.
+// Internal declarations shared by the host runtime (cfr_engine.hip,
+// cfr_api.hip) and the kernel launchers (cfr_kernels.hip).  Not part of the
+// public ABI.
+//
+// Device layout.  Every game held by an engine owns, per player, a block of
+// consecutive sequence indices (its empty sequence first, then its other
+// sequences in level order, then one sentinel) and a block of consecutive
+// decision-point indices (in level order, then one sentinel).  All index
+// arrays hold these global indices, so one launch can cover any set of
+// games: it walks a table of blocks, each naming a game ("slot") and an
+// index range, and reads the game's own iteration scalars.  A single game
+// is the case of one slot at offset 0.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -9,102 +19,119 @@
 
 namespace cfr {
 
-// Per-iteration scalars kept in device memory, so that every kernel reads
-// the iteration index and its derived factors at run time and a captured
-// graph of one iteration can be replayed unchanged.
+// Per-game iteration scalars kept in device memory, so that every kernel
+// reads the iteration index and its derived factors at run time and a
+// captured graph of one iteration can be replayed unchanged.
 struct Scalars {
     double t;      // iterations completed (incremented first thing each iteration)
     double w;      // averaging weight of the current iteration
     double W;      // sum of weights so far
     double dpos;   // DCFR factor for positive regrets, t^a/(t^a+1)
     double dneg;   // DCFR factor for negative regrets, t^b/(t^b+1)
-    double pad[3];
-    double out[8]; // scalar results of the evaluation kernels
+    double alpha, beta, gamma;  // DCFR exponents of this game
+    int32_t variant;            // CFR_VANILLA .. CFR_PCFR
+    int32_t avg_kind;           // CFR_AVG_*
+    int32_t pad[2];
+    double out[8];  // evaluation results (BR1, BR2, value)
 };
 
-// Constants of the iteration that the first product launch uses to advance
-// the device-side scalars.
-struct IterParams {
-    int variant = 0;
-    int avg_kind = 0;
-    double alpha = 1.5, beta = 0.0, gamma = 2.0;
+// One block of a payoff product: a run of whole rows of one game.
+struct SpmvBlock {
+    int32_t row0;   // first row (global sequence index of the row player)
+    int32_t nr;     // rows in the block
+    int32_t n;      // nonzeros in the block
+    int32_t p0;     // row pointer of row0 (offset inside the game's matrix)
+    int64_t e0;     // position of the block's first nonzero in the index/value arrays
+    int32_t slot;   // game
+    int32_t begin;  // 1 on the game's first block: advances the game's scalars
+};
+static_assert(sizeof(SpmvBlock) == 32, "one scalar load per block");
+
+// A range [lo, hi) of at most one block's worth of decision points or
+// sequences of one game.  aux: the game's empty sequence (normalisation).
+struct RangeBlock {
+    int32_t lo, hi, slot, aux;
 };
 
-// Payoff matrix sorted along one player's sequences: CSR of A (player 1
-// rows) or CSR of A^T (player 2 rows), with the row-block partition the
-// product kernel walks.
-struct DevMatrix {
-    int32_t n_rows = 0;
-    int32_t n_cols = 0;
-    int64_t nnz = 0;
-    int32_t n_blk = 0;
-    const int32_t *ptr = nullptr;  // [n_rows+1]
-    const int32_t *idx = nullptr;  // [nnz]
-    const void *val = nullptr;     // [nnz] value type
-    const int32_t *blk = nullptr;  // [2*(n_blk+1)] (first row, first nonzero) of each block
+// Per-game entry of the evaluation reductions: value at the empty sequence
+// (root = empty sequence, [a, b) = decision points under it) or the final
+// stage of a dot product ([a, b) = the game's partial sums).
+struct SlotRef {
+    int32_t slot, root, a, b;
 };
 
-// One player's treeplex in level order (see the runtime for the layout).
+// Device arrays of one player, covering every slot (global indices).
 struct DevPlayer {
-    int32_t n_seq = 0;
-    int32_t n_inf = 0;
-    int32_t n_levels = 0;
-    const int32_t *lvl_inf = nullptr;  // host array [n_levels+1]
-    const int32_t *lvl_seq = nullptr;  // host array [n_levels+1]
-    const uint8_t *lvl_kind = nullptr; // host array [n_levels]: 1 if every decision point of
-                                       // the level has <= kFastActs actions, each with
-                                       // <= kFastKids decision points below it; 2 if in
-                                       // addition nothing lies below the level; else 0
-    int32_t *inf_first = nullptr;      // [n_inf+1]
-    int32_t *seq_par = nullptr;        // [n_seq] parent sequence of each sequence's decision point
-    int32_t *child_ptr = nullptr;      // [n_seq+1] decision points below each sequence:
-    int32_t *child_idx = nullptr;      //   child_idx[child_ptr[s] .. child_ptr[s+1])
-    void *r = nullptr;                 // [n_seq] accumulator type
-    void *m = nullptr;                 // [n_seq] accumulator type
-    void *s = nullptr;                 // [n_seq] accumulator type
-    void *b = nullptr;                 // [n_seq] value type
-    void *x = nullptr;                 // [n_seq] value type
-    void *g = nullptr;                 // [n_seq] value type
-    void *xbar = nullptr;              // [n_seq] value type
-    void *vinf = nullptr;              // [n_inf] compute type
-    // shallow levels 0 .. top_levels-1 run in one launch (k_top), one block
-    // per root decision point (n_roots of them)
+    int32_t *inf_first = nullptr;  // [decision points + sentinel] first sequence of each
+    int32_t *seq_par = nullptr;    // [sequences] parent sequence of each sequence's decision point
+    int32_t *child_ptr = nullptr;  // [sequences] decision points below each sequence:
+    int32_t *child_idx = nullptr;  //   child_idx[child_ptr[s] .. child_ptr[s+1])
+    void *r = nullptr;             // accumulator type
+    void *m = nullptr;             // accumulator type
+    void *s = nullptr;             // accumulator type
+    void *b = nullptr;             // value type
+    void *x = nullptr;             // value type
+    void *g = nullptr;             // value type
+    void *xbar = nullptr;          // value type
+    void *vinf = nullptr;          // [decision points] compute type
+    // shallow levels 0 .. top_levels-1 of a lone game in one launch (k_top),
+    // one block per root decision point (n_roots of them)
     int32_t top_levels = 0;
     int32_t n_roots = 0;
-    int32_t *top_off = nullptr;        // [top_levels*(n_roots+1)]
-    int32_t *top_list = nullptr;       // decision points grouped by level, then root
-    int top_fast = 0;                  // every level in k_top is a fast level
+    int32_t *top_off = nullptr;    // [top_levels*(n_roots+1)]
+    int32_t *top_list = nullptr;   // decision points grouped by level, then root
+    int top_fast = 0;              // every level in k_top is a fast level
 };
 
 // Kernel launchers (cfr_kernels.hip).  All enqueue on `st` and return the
-// launch status.
-hipError_t launch_uniform_b(int prec, const DevPlayer &p, hipStream_t st);
-// begin_sc != nullptr: the first block also advances the iteration scalars.
-hipError_t launch_spmv(int prec, const DevMatrix &A, const void *xin, void *yout,
-                       int xcd_remap, int sequential, Scalars *begin_sc, const IterParams &ip,
+// launch status.  Tables and the arrays they index live in device memory.
+//
+// Payoff product yout = M xin over the blocks of `tab`; with `begin`, the
+// first block of each game advances that game's scalars.  items: nonzeros
+// per thread of the kernel instance (the block partition must hold at most
+// kSpmvThreads*items nonzeros per block, or one row).
+hipError_t launch_spmv(int prec, int items, const SpmvBlock *tab, int32_t n_tab,
+                       const int32_t *ptr, const int32_t *idx, const void *val, const void *xin,
+                       void *yout, int xcd_remap, int sequential, int begin, Scalars *sc,
                        hipStream_t st);
-hipError_t launch_up_level(int prec, int variant, const DevPlayer &p, int level, double usign,
-                           const void *g, const Scalars *sc, hipStream_t st);
-hipError_t launch_down_level(int prec, const DevPlayer &p, int level, int average,
-                             const Scalars *sc, hipStream_t st);
-// launch_up_level on level 0 also runs that level's top-down step.
+// ObserveUtility on the decision points of `tab` (one level), fused with the
+// variant's post-step and regret matching; kind 0 generic, 1 fast, 2 fast
+// without children; root: the level under the empty sequence, whose
+// top-down step (with averaging) is done in the same launch.
+hipError_t launch_up(int prec, int variant, int kind, int root, const RangeBlock *tab,
+                     int32_t n_tab, const DevPlayer &p, double usign, const Scalars *sc,
+                     hipStream_t st);
+// Top-down pass over the sequences of `tab` (one level).
+hipError_t launch_down(int prec, const RangeBlock *tab, int32_t n_tab, const DevPlayer &p,
+                       int average, const Scalars *sc, hipStream_t st);
 // ObserveUtility on levels top_levels-1..0, then the top-down pass on levels
-// 0..top_levels-1 (with averaging when `average`).
+// 0..top_levels-1 (with averaging when `average`) of the game in slot 0.
 hipError_t launch_top(int prec, int variant, const DevPlayer &p, double usign, int average,
                       const Scalars *sc, hipStream_t st);
-hipError_t launch_normalize(int prec, const DevPlayer &p, const Scalars *sc, hipStream_t st);
-hipError_t launch_br_level(int prec, const DevPlayer &p, int level, double usign,
-                           const void *g, hipStream_t st);
-hipError_t launch_root_value(int prec, const DevPlayer &p, double usign, const void *g,
-                             double *out, hipStream_t st);
-hipError_t launch_dot(int prec, int32_t n, const void *a, const void *b, double *partials,
-                      int n_partials, double *out, hipStream_t st);
+// xbar = s / W per game (x where W = 0), 1 at each game's empty sequence.
+hipError_t launch_normalize(int prec, const RangeBlock *tab, int32_t n_tab, const DevPlayer &p,
+                            const Scalars *sc, hipStream_t st);
+// One level of the best-response max-sweep (values in vinf).
+hipError_t launch_br(int prec, const RangeBlock *tab, int32_t n_tab, const DevPlayer &p,
+                     double usign, hipStream_t st);
+// Per game: usign*g[root] + sum of vinf over the root decision points,
+// into sc[slot].out[out_index].
+hipError_t launch_root_value(int prec, const SlotRef *tab, int32_t n_tab, const DevPlayer &p,
+                             double usign, Scalars *sc, int out_index, hipStream_t st);
+// Per game: sum over its sequences of a[i]*b[i] in double, into
+// sc[slot].out[out_index] (partials: one double per entry of `tab`).
+hipError_t launch_dot(int prec, const RangeBlock *tab, int32_t n_tab, const void *a,
+                      const void *b, double *partials, const SlotRef *fin, int32_t n_fin,
+                      Scalars *sc, int out_index, hipStream_t st);
+// a[i] += base for i < n.
+hipError_t launch_add_offset(int32_t *a, int64_t n, int32_t base, hipStream_t st);
 
 size_t value_bytes(int prec);
 size_t accum_bytes(int prec);
 size_t compute_bytes(int prec);
 
-// Payoff-product tiling (overridable at build time for tuning sweeps).
+// Payoff-product tiling.  The kernel is instantiated for these
+// nonzeros-per-thread counts; the runtime picks one per matrix.
 #ifndef CFR_SPMV_ITEMS
 #define CFR_SPMV_ITEMS 16
 #endif
@@ -116,11 +143,12 @@ size_t compute_bytes(int prec);
 #define CFR_SPMV_LDS_VALUE 1
 #endif
 constexpr int kSpmvThreads = 256;
-constexpr int kSpmvItems = CFR_SPMV_ITEMS;
-constexpr int kSpmvCap = kSpmvThreads * kSpmvItems;  // nonzeros staged per block
-constexpr int kSpmvRowCap = 256;                     // rows per block
+constexpr int kSpmvItemsDefault = CFR_SPMV_ITEMS;
+constexpr int kSpmvItemsMax = 16;
+constexpr int kSpmvRowCap = 256;  // rows per block at most
 static_assert(kSpmvRowCap <= kSpmvThreads, "a block's row pointers are one per thread");
-constexpr int kDotPartials = 512;
+inline bool spmv_items_supported(int items) { return items == 4 || items == 8 || items == 16; }
+constexpr int kRangeBlock = 256;  // decision points or sequences per sweep block
 // 1: run the shallow levels in one launch (k_top) even when deeper levels
 // remain as per-level launches
 #ifndef CFR_TOP_PARTIAL

@@ -1,14 +1,16 @@
 // HIP kernels for one iteration of sequence-form CFR on gfx950.
 //
 // The path is sparse and bandwidth-bound (about 0.25 flop per byte), so
-// nothing here uses MFMA.  Kernels:
+// nothing here uses MFMA.  Every launch walks a table of blocks; each entry
+// names a game and a range of it, so one launch serves one game or a whole
+// batch of games (global indices, per-game scalars).  Kernels:
 //   k_spmv      payoff product over a row-sorted matrix (A y over the CSR,
 //               A^T x over the CSC): each 256-thread block owns a run of
-//               whole rows holding at most 2048 nonzeros, streams their
-//               index/value pairs with coalesced loads, gathers the input
-//               vector, stages the products in LDS, and sums every row in
-//               ascending column order.  A row longer than one block's
-//               capacity gets a block of its own and a tree reduction.
+//               whole rows of one game, streams their index/value pairs with
+//               coalesced loads, gathers the input vector, stages the
+//               products in LDS, and sums every row.  A row longer than one
+//               block's capacity gets a block of its own and a tree
+//               reduction.
 //   k_up        one treeplex level of ObserveUtility (Algorithm 2, bottom-up
 //               part and regret update) fused with the variant's post-step
 //               and with regret matching for the next strategy: one thread
@@ -16,17 +18,19 @@
 //   k_down      one treeplex level of NextStrategy's top-down pass, fused
 //               with the average-strategy accumulation of the strategy it
 //               overwrites: one thread per sequence.
-//   k_top       the shallow levels of a player, bottom-up then top-down, in
-//               one launch: one block per root decision point's subtree.
+//   k_top       the shallow levels of a lone game, bottom-up then top-down,
+//               in one launch: one block per root decision point's subtree.
 //   k_br        one level of the best-response max-sweep.
 //   k_normalize / k_root / k_dot   average normalisation and deterministic
-//               scalar reductions.  The per-iteration scalars (t, the
-//               averaging weight, the DCFR factors) are advanced by the first
-//               block of the iteration's first payoff product.
+//               per-game scalar reductions.  The per-iteration scalars (t,
+//               the averaging weight, the DCFR factors) of each game are
+//               advanced by that game's first block of the iteration's first
+//               payoff product.
 // Precision modes select the value type (payoffs, strategies, utilities),
 // the accumulator type (regrets, predictions, averages) and the compute
 // type (in-register arithmetic).  No kernel uses atomics, so every result
-// is run-to-run reproducible.
+// is run-to-run reproducible, and no reduction mixes two games, so a game's
+// iterates do not depend on which other games share its launches.
 #include "cfr_internal.h"
 
 #include <cfloat>
@@ -72,24 +76,25 @@ inline unsigned grid_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kTh
 // Per-iteration scalars
 // ---------------------------------------------------------------------------
 
-__device__ void begin_iteration(Scalars *sc, const IterParams &ip)
+__device__ void begin_iteration(Scalars *sc)
 {
     double t = sc->t + 1.0;
     sc->t = t;
-    int kind = ip.avg_kind;
+    int kind = sc->avg_kind;
+    const int variant = sc->variant;
     if (kind == CFR_AVG_DEFAULT) {
-        kind = ip.variant == CFR_PLUS        ? CFR_AVG_LINEAR
-               : ip.variant == CFR_DCFR      ? CFR_AVG_POW_GAMMA
-               : ip.variant == CFR_PCFR_PLUS ? CFR_AVG_QUADRATIC
-                                             : CFR_AVG_UNIFORM;
+        kind = variant == CFR_PLUS        ? CFR_AVG_LINEAR
+               : variant == CFR_DCFR      ? CFR_AVG_POW_GAMMA
+               : variant == CFR_PCFR_PLUS ? CFR_AVG_QUADRATIC
+                                          : CFR_AVG_UNIFORM;
     }
     double w = 1.0;
     if (kind == CFR_AVG_LINEAR) w = t;
     else if (kind == CFR_AVG_QUADRATIC) w = t * t;
-    else if (kind == CFR_AVG_POW_GAMMA) w = pow(t, ip.gamma);
+    else if (kind == CFR_AVG_POW_GAMMA) w = pow(t, sc->gamma);
     sc->w = w;
     sc->W = sc->W + w;
-    double ta = pow(t, ip.alpha), tb = pow(t, ip.beta);
+    double ta = pow(t, sc->alpha), tb = pow(t, sc->beta);
     sc->dpos = ta / (ta + 1.0);
     sc->dneg = tb / (tb + 1.0);
 }
@@ -103,28 +108,28 @@ __device__ void begin_iteration(Scalars *sc, const IterParams &ip)
 // evaluation bit for bit; otherwise a power-of-two group of lanes shares
 // each row and combines its partial sums with cross-lane shuffles.
 //
-// blk holds (first row, first nonzero) of every row block, so one load
-// gives the block's extent.  The loads of a block are all issued
+// Each table entry gives a block's rows, nonzeros and game in one scalar
+// load.  The loads of a block are all issued
 // unconditionally (lanes past the end read the block's first entry and
 // ignore it): index/value stream and row pointers in one round, gathers in
 // the next; the reduction then reads only LDS.
-template <int P, bool SEQ>
+template <int P, bool SEQ, int ITEMS>
 __global__ __launch_bounds__(kSpmvThreads) void k_spmv(
-    int32_t n_blk, const int32_t *__restrict__ blk, const int32_t *__restrict__ ptr,
+    int32_t n_blk, const SpmvBlock *__restrict__ tab, const int32_t *__restrict__ ptr,
     const int32_t *__restrict__ idx, const typename Types<P>::V *__restrict__ val,
     const typename Types<P>::V *__restrict__ xin, typename Types<P>::V *__restrict__ yout,
-    int xcd_remap, Scalars *begin_sc, IterParams ip)
+    int xcd_remap, int begin, Scalars *sc)
 {
     using V = typename Types<P>::V;
     using C = typename Types<P>::C;
     // products staged in LDS: the compute type, or the value type when the
     // FP32 modes are built to stage them compactly
     using L = typename std::conditional<(CFR_SPMV_LDS_VALUE != 0) && P != CFR_FP64, V, C>::type;
-    __shared__ L prod[kSpmvCap];
+    constexpr int kCap = kSpmvThreads * ITEMS;  // nonzeros staged per block
+    __shared__ L prod[kCap];
     __shared__ int32_t s_ptr[kSpmvRowCap + 1];
     __shared__ C red[kSpmvThreads];
 
-    if (begin_sc && blockIdx.x == 0 && threadIdx.x == 0) begin_iteration(begin_sc, ip);
     int32_t bid = (int32_t)blockIdx.x;
     if (xcd_remap) {
         // Workgroups are dealt round-robin over the 8 XCDs; give each XCD a
@@ -135,10 +140,12 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(
     }
     if (bid >= n_blk) return;
     const int tid = threadIdx.x;
-    const int32_t rb = blk[2 * bid], e0 = blk[2 * bid + 1];
-    const int32_t nr = blk[2 * bid + 2] - rb, n = blk[2 * bid + 3] - e0;
+    const SpmvBlock bk = tab[bid];
+    if (begin && bk.begin && tid == 0) begin_iteration(sc + bk.slot);
+    const int32_t rb = bk.row0, nr = bk.nr, n = bk.n, p0 = bk.p0;
+    const int64_t e0 = bk.e0;
 
-    if (n > kSpmvCap) {
+    if (n > kCap) {
         // a single long row: strided partial sums, then a fixed-order tree
         C acc = 0;
         for (int32_t i = tid; i < n; i += kSpmvThreads)
@@ -153,17 +160,17 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(
         return;
     }
 
-    int32_t c[kSpmvItems];
-    V v[kSpmvItems];
-    V gx[kSpmvItems];
+    int32_t c[ITEMS];
+    V v[ITEMS];
+    V gx[ITEMS];
     // this block's row pointers: one per thread (a block has at most
     // kSpmvRowCap = kSpmvThreads rows)
     const int32_t pr = ptr[rb + (tid < nr ? tid : 0)];
     if (n > 0) {
 #pragma unroll
-        for (int k = 0; k < kSpmvItems; ++k) {
+        for (int k = 0; k < ITEMS; ++k) {
             const int32_t i = k * kSpmvThreads + tid;
-            const int32_t at = e0 + (i < n ? i : 0);
+            const int64_t at = e0 + (i < n ? i : 0);
 #if CFR_SPMV_NONTEMPORAL
             c[k] = __builtin_nontemporal_load(idx + at);
             v[k] = __builtin_nontemporal_load(val + at);
@@ -173,14 +180,14 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(
 #endif
         }
 #pragma unroll
-        for (int k = 0; k < kSpmvItems; ++k) gx[k] = xin[c[k]];
+        for (int k = 0; k < ITEMS; ++k) gx[k] = xin[c[k]];
 #pragma unroll
-        for (int k = 0; k < kSpmvItems; ++k) {
+        for (int k = 0; k < ITEMS; ++k) {
             const int32_t i = k * kSpmvThreads + tid;
             if (i < n) prod[i] = (L)((C)v[k] * (C)gx[k]);
         }
     }
-    if (tid < nr) s_ptr[tid] = pr - e0;
+    if (tid < nr) s_ptr[tid] = pr - p0;
     if (tid == 0) s_ptr[nr] = n;
     __syncthreads();
     if (SEQ) {
@@ -189,11 +196,11 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(
             const int32_t z = s_ptr[tid + 1];
             C acc = 0;
             for (; i + 4 <= z; i += 4) {
-                C p0 = prod[i], p1 = prod[i + 1], p2 = prod[i + 2], p3 = prod[i + 3];
-                acc = acc + p0;
-                acc = acc + p1;
-                acc = acc + p2;
-                acc = acc + p3;
+                C q0 = prod[i], q1 = prod[i + 1], q2 = prod[i + 2], q3 = prod[i + 3];
+                acc = acc + q0;
+                acc = acc + q1;
+                acc = acc + q2;
+                acc = acc + q3;
             }
             for (; i < z; ++i) acc = acc + (C)prod[i];
             yout[rb + tid] = (V)acc;
@@ -452,13 +459,14 @@ __device__ __forceinline__ void down_infoset(int32_t j, const int32_t *__restric
     }
 }
 
-// One level of ObserveUtility.  KIND 0: any shape; 1: fast path; 2: fast
-// path for a level with no decision points below it.  ROOT: the level under
-// the empty sequence, whose top-down step (x = 1 * b, averaging the old x)
-// needs nothing but this thread's own new strategy, so it is done here too.
+// One level of ObserveUtility over the decision points of the table's
+// ranges.  KIND 0: any shape; 1: fast path; 2: fast path for a level with
+// no decision points below it.  ROOT: the level under the empty sequence,
+// whose top-down step (x = 1 * b, averaging the old x) needs nothing but
+// this thread's own new strategy, so it is done here too.
 template <int P, int VAR, int KIND, bool ROOT>
 __global__ __launch_bounds__(kThreads) void k_up(
-    int32_t j0, int32_t j1, const int32_t *__restrict__ inf_first,
+    const RangeBlock *__restrict__ tab, const int32_t *__restrict__ inf_first,
     const int32_t *__restrict__ child_ptr, const int32_t *__restrict__ child_idx,
     const typename Types<P>::V *__restrict__ g, typename Types<P>::C usign,
     typename Types<P>::C *__restrict__ vinf, typename Types<P>::V *__restrict__ b,
@@ -468,12 +476,14 @@ __global__ __launch_bounds__(kThreads) void k_up(
 {
     using R = typename Types<P>::R;
     using C = typename Types<P>::C;
-    int32_t j = j0 + (int32_t)(blockIdx.x * kThreads + threadIdx.x);
-    if (j >= j1) return;
+    const RangeBlock rb = tab[blockIdx.x];
+    const int32_t j = rb.lo + (int32_t)threadIdx.x;
+    if (j >= rb.hi) return;
+    const Scalars *gs = sc + rb.slot;
     C dpos = 1, dneg = 1;
     if (VAR == CFR_DCFR) {
-        dpos = (C)sc->dpos;
-        dneg = (C)sc->dneg;
+        dpos = (C)gs->dpos;
+        dneg = (C)gs->dneg;
     }
     if (KIND == 1)
         up_infoset_fast<P, VAR, kFastKids>(j, inf_first, child_ptr, child_idx, g, usign, vinf, b,
@@ -484,7 +494,7 @@ __global__ __launch_bounds__(kThreads) void k_up(
     else
         up_infoset<P, VAR>(j, inf_first, child_ptr, child_idx, g, usign, vinf, b, r, m, dpos,
                            dneg);
-    if (ROOT) down_infoset<P>(j, inf_first, seq_par, b, x, s, (R)sc->w, 1);
+    if (ROOT) down_infoset<P>(j, inf_first, seq_par, b, x, s, (R)gs->w, 1);
 }
 
 // The shallow levels of one player in one launch: block `root` owns the
@@ -535,34 +545,24 @@ __global__ __launch_bounds__(kTopThreads) void k_top(
     }
 }
 
-template <int P>
-__global__ __launch_bounds__(kThreads) void k_uniform_b(int32_t n_inf,
-                                                        const int32_t *__restrict__ inf_first,
-                                                        typename Types<P>::V *__restrict__ b)
-{
-    using V = typename Types<P>::V;
-    using C = typename Types<P>::C;
-    int32_t j = (int32_t)(blockIdx.x * kThreads + threadIdx.x);
-    if (j >= n_inf) return;
-    const int32_t a0 = inf_first[j], a1 = inf_first[j + 1];
-    for (int32_t a = a0; a < a1; ++a) b[a] = (V)((C)1 / (C)(a1 - a0));
-}
-
 // ---------------------------------------------------------------------------
 // NextStrategy top-down pass for one level, fused with averaging
 // ---------------------------------------------------------------------------
 
 template <int P>
-__global__ __launch_bounds__(kThreads) void k_down(
-    int32_t s0, int32_t s1, const int32_t *__restrict__ seq_par,
-    const typename Types<P>::V *__restrict__ b, typename Types<P>::V *__restrict__ x,
-    typename Types<P>::R *__restrict__ s, const Scalars *__restrict__ sc, int average)
+__global__ __launch_bounds__(kThreads) void k_down(const RangeBlock *__restrict__ tab,
+                                                   const int32_t *__restrict__ seq_par,
+                                                   const typename Types<P>::V *__restrict__ b,
+                                                   typename Types<P>::V *__restrict__ x,
+                                                   typename Types<P>::R *__restrict__ s,
+                                                   const Scalars *__restrict__ sc, int average)
 {
     using R = typename Types<P>::R;
-    int32_t i = s0 + (int32_t)(blockIdx.x * kThreads + threadIdx.x);
-    if (i >= s1) return;
+    const RangeBlock rb = tab[blockIdx.x];
+    const int32_t i = rb.lo + (int32_t)threadIdx.x;
+    if (i >= rb.hi) return;
     if (average) {
-        R w = (R)sc->w;
+        R w = (R)sc[rb.slot].w;
         s[i] = s[i] + w * (R)x[i];
     }
     x[i] = x[seq_par[i]] * b[i];
@@ -572,20 +572,25 @@ __global__ __launch_bounds__(kThreads) void k_down(
 // Evaluation: average normalisation, best-response sweep, reductions
 // ---------------------------------------------------------------------------
 
+// xbar = s / W of the sequence's game, 1 at the game's empty sequence (the
+// table's aux); the current strategy for a game with no iteration yet.
 template <int P>
-__global__ __launch_bounds__(kThreads) void k_normalize(int32_t n, const typename Types<P>::R *s,
+__global__ __launch_bounds__(kThreads) void k_normalize(const RangeBlock *__restrict__ tab,
+                                                        const typename Types<P>::R *s,
+                                                        const typename Types<P>::V *x,
                                                         const Scalars *__restrict__ sc,
                                                         typename Types<P>::V *__restrict__ xbar)
 {
     using V = typename Types<P>::V;
-    int32_t i = (int32_t)(blockIdx.x * kThreads + threadIdx.x);
-    if (i >= n) return;
-    double W = sc->W;
-    xbar[i] = i == 0 ? (V)1 : (V)((double)s[i] / W);
+    const RangeBlock rb = tab[blockIdx.x];
+    const int32_t i = rb.lo + (int32_t)threadIdx.x;
+    if (i >= rb.hi) return;
+    const double W = sc[rb.slot].W;
+    xbar[i] = i == rb.aux ? (V)1 : W > 0 ? (V)((double)s[i] / W) : x[i];
 }
 
 template <int P>
-__global__ __launch_bounds__(kThreads) void k_br(int32_t j0, int32_t j1,
+__global__ __launch_bounds__(kThreads) void k_br(const RangeBlock *__restrict__ tab,
                                                  const int32_t *__restrict__ inf_first,
                                                  const int32_t *__restrict__ child_ptr,
                                                  const int32_t *__restrict__ child_idx,
@@ -594,8 +599,9 @@ __global__ __launch_bounds__(kThreads) void k_br(int32_t j0, int32_t j1,
                                                  typename Types<P>::C *__restrict__ vmax)
 {
     using C = typename Types<P>::C;
-    int32_t j = j0 + (int32_t)(blockIdx.x * kThreads + threadIdx.x);
-    if (j >= j1) return;
+    const RangeBlock rb = tab[blockIdx.x];
+    const int32_t j = rb.lo + (int32_t)threadIdx.x;
+    if (j >= rb.hi) return;
     const int32_t a0 = inf_first[j], a1 = inf_first[j + 1];
     C best = 0;
     for (int32_t a = a0; a < a1; ++a) {
@@ -606,33 +612,37 @@ __global__ __launch_bounds__(kThreads) void k_br(int32_t j0, int32_t j1,
     vmax[j] = best;
 }
 
-// value at the empty sequence: own utility there plus the values of the
-// decision points directly below it, summed in ascending order
+// value at each game's empty sequence: own utility there plus the values of
+// the decision points directly below it, summed in ascending order
 template <int P>
-__global__ void k_root(int32_t n_root, const typename Types<P>::V *__restrict__ g,
-                       typename Types<P>::C usign, const typename Types<P>::C *__restrict__ v,
-                       double *out)
+__global__ __launch_bounds__(kThreads) void k_root(int32_t n_tab, const SlotRef *__restrict__ tab,
+                                                   const typename Types<P>::V *__restrict__ g,
+                                                   typename Types<P>::C usign,
+                                                   const typename Types<P>::C *__restrict__ v,
+                                                   Scalars *sc, int out_index)
 {
     using C = typename Types<P>::C;
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double acc = (double)(usign * (C)g[0]);
-    for (int32_t j = 0; j < n_root; ++j) acc = acc + (double)v[j];
-    *out = acc;
+    const int32_t k = (int32_t)(blockIdx.x * kThreads + threadIdx.x);
+    if (k >= n_tab) return;
+    const SlotRef e = tab[k];
+    double acc = (double)(usign * (C)g[e.root]);
+    for (int32_t j = e.a; j < e.b; ++j) acc = acc + (double)v[j];
+    sc[e.slot].out[out_index] = acc;
 }
 
-// deterministic two-stage dot product in double
+// deterministic two-stage dot product in double: one partial per table
+// entry (a fixed tree over its at most kThreads terms), then one block per
+// game adding its partials in a fixed order
 template <int P>
-__global__ __launch_bounds__(kThreads) void k_dot_partial(int32_t n,
+__global__ __launch_bounds__(kThreads) void k_dot_partial(const RangeBlock *__restrict__ tab,
                                                           const typename Types<P>::V *__restrict__ a,
                                                           const typename Types<P>::V *__restrict__ b,
                                                           double *partials)
 {
     __shared__ double red[kThreads];
-    double acc = 0;
-    for (int32_t i = (int32_t)(blockIdx.x * kThreads + threadIdx.x); i < n;
-         i += (int32_t)(gridDim.x * kThreads))
-        acc = acc + (double)a[i] * (double)b[i];
-    red[threadIdx.x] = acc;
+    const RangeBlock rb = tab[blockIdx.x];
+    const int32_t i = rb.lo + (int32_t)threadIdx.x;
+    red[threadIdx.x] = i < rb.hi ? (double)a[i] * (double)b[i] : 0.0;
     __syncthreads();
     for (int w = kThreads / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + w];
@@ -641,50 +651,82 @@ __global__ __launch_bounds__(kThreads) void k_dot_partial(int32_t n,
     if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
 }
 
-__global__ __launch_bounds__(kThreads) void k_dot_final(int n_partials, const double *partials,
-                                                        double *out)
+__global__ __launch_bounds__(kThreads) void k_dot_final(const SlotRef *__restrict__ fin,
+                                                        const double *partials, Scalars *sc,
+                                                        int out_index)
 {
     __shared__ double red[kThreads];
+    const SlotRef e = fin[blockIdx.x];
     double acc = 0;
-    for (int i = threadIdx.x; i < n_partials; i += kThreads) acc = acc + partials[i];
+    for (int32_t i = e.a + (int32_t)threadIdx.x; i < e.b; i += kThreads) acc = acc + partials[i];
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int w = kThreads / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out = red[0];
+    if (threadIdx.x == 0) sc[e.slot].out[out_index] = red[0];
+}
+
+__global__ __launch_bounds__(kThreads) void k_add_offset(int32_t *a, int64_t n, int32_t base)
+{
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) a[i] += base;
 }
 
 // ---------------------------------------------------------------------------
 // Launch helpers
 // ---------------------------------------------------------------------------
 
-template <int P>
-hipError_t spmv_t(const DevMatrix &A, const void *xin, void *yout, int xcd_remap, int sequential,
-                  Scalars *begin_sc, const IterParams &ip, hipStream_t st)
+template <int P, bool SEQ, int ITEMS>
+hipError_t spmv_launch(const SpmvBlock *tab, int32_t n_tab, const int32_t *ptr, const int32_t *idx,
+                       const void *val, const void *xin, void *yout, int xcd_remap, int begin,
+                       Scalars *sc, hipStream_t st)
 {
     using V = typename Types<P>::V;
-    if (A.n_blk == 0) return hipSuccess;
-    unsigned grid = xcd_remap ? (unsigned)(((A.n_blk + 7) / 8) * 8) : (unsigned)A.n_blk;
-    if (sequential)
-        hipLaunchKernelGGL((k_spmv<P, true>), dim3(grid), dim3(kSpmvThreads), 0, st, A.n_blk,
-                           A.blk, A.ptr, A.idx, (const V *)A.val, (const V *)xin, (V *)yout,
-                           xcd_remap, begin_sc, ip);
-    else
-        hipLaunchKernelGGL((k_spmv<P, false>), dim3(grid), dim3(kSpmvThreads), 0, st, A.n_blk,
-                           A.blk, A.ptr, A.idx, (const V *)A.val, (const V *)xin, (V *)yout,
-                           xcd_remap, begin_sc, ip);
+    unsigned grid = xcd_remap ? (unsigned)(((n_tab + 7) / 8) * 8) : (unsigned)n_tab;
+    hipLaunchKernelGGL((k_spmv<P, SEQ, ITEMS>), dim3(grid), dim3(kSpmvThreads), 0, st, n_tab, tab,
+                       ptr, idx, (const V *)val, (const V *)xin, (V *)yout, xcd_remap, begin, sc);
     return hipGetLastError();
 }
 
+template <int P, bool SEQ>
+hipError_t spmv_items(int items, const SpmvBlock *tab, int32_t n_tab, const int32_t *ptr,
+                      const int32_t *idx, const void *val, const void *xin, void *yout,
+                      int xcd_remap, int begin, Scalars *sc, hipStream_t st)
+{
+    switch (items) {
+    case 4:
+        return spmv_launch<P, SEQ, 4>(tab, n_tab, ptr, idx, val, xin, yout, xcd_remap, begin, sc, st);
+    case 8:
+        return spmv_launch<P, SEQ, 8>(tab, n_tab, ptr, idx, val, xin, yout, xcd_remap, begin, sc, st);
+    case 16:
+        return spmv_launch<P, SEQ, 16>(tab, n_tab, ptr, idx, val, xin, yout, xcd_remap, begin, sc,
+                                       st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int P>
+hipError_t spmv_t(int items, const SpmvBlock *tab, int32_t n_tab, const int32_t *ptr,
+                  const int32_t *idx, const void *val, const void *xin, void *yout, int xcd_remap,
+                  int sequential, int begin, Scalars *sc, hipStream_t st)
+{
+    if (n_tab <= 0) return hipSuccess;
+    if (sequential)
+        return spmv_items<P, true>(items, tab, n_tab, ptr, idx, val, xin, yout, xcd_remap, begin,
+                                   sc, st);
+    return spmv_items<P, false>(items, tab, n_tab, ptr, idx, val, xin, yout, xcd_remap, begin, sc,
+                                st);
+}
+
 template <int P, int VAR, int KIND, bool ROOT>
-hipError_t up_launch(const DevPlayer &p, int32_t j0, int32_t j1, double usign, const void *g,
+hipError_t up_launch(const RangeBlock *tab, int32_t n_tab, const DevPlayer &p, double usign,
                      const Scalars *sc, hipStream_t st)
 {
     using T = Types<P>;
-    hipLaunchKernelGGL((k_up<P, VAR, KIND, ROOT>), dim3(grid_for(j1 - j0)), dim3(kThreads), 0, st,
-                       j0, j1, p.inf_first, p.child_ptr, p.child_idx, (const typename T::V *)g,
+    hipLaunchKernelGGL((k_up<P, VAR, KIND, ROOT>), dim3((unsigned)n_tab), dim3(kThreads), 0, st,
+                       tab, p.inf_first, p.child_ptr, p.child_idx, (const typename T::V *)p.g,
                        (typename T::C)usign, (typename T::C *)p.vinf, (typename T::V *)p.b,
                        (typename T::R *)p.r, (typename T::R *)p.m, sc, p.seq_par,
                        (typename T::V *)p.x, (typename T::R *)p.s);
@@ -692,32 +734,30 @@ hipError_t up_launch(const DevPlayer &p, int32_t j0, int32_t j1, double usign, c
 }
 
 template <int P, int VAR>
-hipError_t up_t(const DevPlayer &p, int level, double usign, const void *g, const Scalars *sc,
-                hipStream_t st)
+hipError_t up_t(int kind, int root, const RangeBlock *tab, int32_t n_tab, const DevPlayer &p,
+                double usign, const Scalars *sc, hipStream_t st)
 {
-    int32_t j0 = p.lvl_inf[level], j1 = p.lvl_inf[level + 1];
-    if (j1 <= j0) return hipSuccess;
-    const int kind = p.lvl_kind[level];
-    if (level == 0) {
-        if (kind == 1) return up_launch<P, VAR, 1, true>(p, j0, j1, usign, g, sc, st);
-        if (kind == 2) return up_launch<P, VAR, 2, true>(p, j0, j1, usign, g, sc, st);
-        return up_launch<P, VAR, 0, true>(p, j0, j1, usign, g, sc, st);
+    if (n_tab <= 0) return hipSuccess;
+    if (root) {
+        if (kind == 1) return up_launch<P, VAR, 1, true>(tab, n_tab, p, usign, sc, st);
+        if (kind == 2) return up_launch<P, VAR, 2, true>(tab, n_tab, p, usign, sc, st);
+        return up_launch<P, VAR, 0, true>(tab, n_tab, p, usign, sc, st);
     }
-    if (kind == 1) return up_launch<P, VAR, 1, false>(p, j0, j1, usign, g, sc, st);
-    if (kind == 2) return up_launch<P, VAR, 2, false>(p, j0, j1, usign, g, sc, st);
-    return up_launch<P, VAR, 0, false>(p, j0, j1, usign, g, sc, st);
+    if (kind == 1) return up_launch<P, VAR, 1, false>(tab, n_tab, p, usign, sc, st);
+    if (kind == 2) return up_launch<P, VAR, 2, false>(tab, n_tab, p, usign, sc, st);
+    return up_launch<P, VAR, 0, false>(tab, n_tab, p, usign, sc, st);
 }
 
 template <int P>
-hipError_t up_dispatch(int variant, const DevPlayer &p, int level, double usign, const void *g,
-                       const Scalars *sc, hipStream_t st)
+hipError_t up_dispatch(int variant, int kind, int root, const RangeBlock *tab, int32_t n_tab,
+                       const DevPlayer &p, double usign, const Scalars *sc, hipStream_t st)
 {
     switch (variant) {
-    case CFR_VANILLA: return up_t<P, CFR_VANILLA>(p, level, usign, g, sc, st);
-    case CFR_PLUS: return up_t<P, CFR_PLUS>(p, level, usign, g, sc, st);
-    case CFR_DCFR: return up_t<P, CFR_DCFR>(p, level, usign, g, sc, st);
-    case CFR_PCFR_PLUS: return up_t<P, CFR_PCFR_PLUS>(p, level, usign, g, sc, st);
-    case CFR_PCFR: return up_t<P, CFR_PCFR>(p, level, usign, g, sc, st);
+    case CFR_VANILLA: return up_t<P, CFR_VANILLA>(kind, root, tab, n_tab, p, usign, sc, st);
+    case CFR_PLUS: return up_t<P, CFR_PLUS>(kind, root, tab, n_tab, p, usign, sc, st);
+    case CFR_DCFR: return up_t<P, CFR_DCFR>(kind, root, tab, n_tab, p, usign, sc, st);
+    case CFR_PCFR_PLUS: return up_t<P, CFR_PCFR_PLUS>(kind, root, tab, n_tab, p, usign, sc, st);
+    case CFR_PCFR: return up_t<P, CFR_PCFR>(kind, root, tab, n_tab, p, usign, sc, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -751,70 +791,64 @@ hipError_t top_dispatch(int variant, const DevPlayer &p, double usign, int avera
 }
 
 template <int P>
-hipError_t down_t(const DevPlayer &p, int level, int average, const Scalars *sc, hipStream_t st)
+hipError_t down_t(const RangeBlock *tab, int32_t n_tab, const DevPlayer &p, int average,
+                  const Scalars *sc, hipStream_t st)
 {
     using T = Types<P>;
-    int32_t s0 = p.lvl_seq[level], s1 = p.lvl_seq[level + 1];
-    if (s1 <= s0) return hipSuccess;
-    hipLaunchKernelGGL((k_down<P>), dim3(grid_for(s1 - s0)), dim3(kThreads), 0, st, s0, s1,
-                       p.seq_par, (const typename T::V *)p.b, (typename T::V *)p.x,
-                       (typename T::R *)p.s, sc, average);
+    if (n_tab <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_down<P>), dim3((unsigned)n_tab), dim3(kThreads), 0, st, tab, p.seq_par,
+                       (const typename T::V *)p.b, (typename T::V *)p.x, (typename T::R *)p.s, sc,
+                       average);
     return hipGetLastError();
 }
 
 template <int P>
-hipError_t uniform_t(const DevPlayer &p, hipStream_t st)
+hipError_t normalize_t(const RangeBlock *tab, int32_t n_tab, const DevPlayer &p, const Scalars *sc,
+                       hipStream_t st)
 {
     using T = Types<P>;
-    if (p.n_inf == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_uniform_b<P>), dim3(grid_for(p.n_inf)), dim3(kThreads), 0, st, p.n_inf,
-                       p.inf_first, (typename T::V *)p.b);
+    if (n_tab <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_normalize<P>), dim3((unsigned)n_tab), dim3(kThreads), 0, st, tab,
+                       (const typename T::R *)p.s, (const typename T::V *)p.x, sc,
+                       (typename T::V *)p.xbar);
     return hipGetLastError();
 }
 
 template <int P>
-hipError_t normalize_t(const DevPlayer &p, const Scalars *sc, hipStream_t st)
+hipError_t br_t(const RangeBlock *tab, int32_t n_tab, const DevPlayer &p, double usign,
+                hipStream_t st)
 {
     using T = Types<P>;
-    hipLaunchKernelGGL((k_normalize<P>), dim3(grid_for(p.n_seq)), dim3(kThreads), 0, st, p.n_seq,
-                       (const typename T::R *)p.s, sc, (typename T::V *)p.xbar);
+    if (n_tab <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_br<P>), dim3((unsigned)n_tab), dim3(kThreads), 0, st, tab, p.inf_first,
+                       p.child_ptr, p.child_idx, (const typename T::V *)p.g, (typename T::C)usign,
+                       (typename T::C *)p.vinf);
     return hipGetLastError();
 }
 
 template <int P>
-hipError_t br_t(const DevPlayer &p, int level, double usign, const void *g, hipStream_t st)
+hipError_t root_t(const SlotRef *tab, int32_t n_tab, const DevPlayer &p, double usign,
+                  Scalars *sc, int out_index, hipStream_t st)
 {
     using T = Types<P>;
-    int32_t j0 = p.lvl_inf[level], j1 = p.lvl_inf[level + 1];
-    if (j1 <= j0) return hipSuccess;
-    hipLaunchKernelGGL((k_br<P>), dim3(grid_for(j1 - j0)), dim3(kThreads), 0, st, j0, j1,
-                       p.inf_first, p.child_ptr, p.child_idx, (const typename T::V *)g,
-                       (typename T::C)usign, (typename T::C *)p.vinf);
+    if (n_tab <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_root<P>), dim3(grid_for(n_tab)), dim3(kThreads), 0, st, n_tab, tab,
+                       (const typename T::V *)p.g, (typename T::C)usign,
+                       (const typename T::C *)p.vinf, sc, out_index);
     return hipGetLastError();
 }
 
 template <int P>
-hipError_t root_t(const DevPlayer &p, double usign, const void *g, double *out, hipStream_t st)
+hipError_t dot_t(const RangeBlock *tab, int32_t n_tab, const void *a, const void *b,
+                 double *partials, const SlotRef *fin, int32_t n_fin, Scalars *sc, int out_index,
+                 hipStream_t st)
 {
     using T = Types<P>;
-    int32_t n_root = p.n_levels > 0 ? p.lvl_inf[1] - p.lvl_inf[0] : 0;
-    hipLaunchKernelGGL((k_root<P>), dim3(1), dim3(64), 0, st, n_root,
-                       (const typename T::V *)g, (typename T::C)usign,
-                       (const typename T::C *)p.vinf, out);
-    return hipGetLastError();
-}
-
-template <int P>
-hipError_t dot_t(int32_t n, const void *a, const void *b, double *partials, int n_partials,
-                 double *out, hipStream_t st)
-{
-    using T = Types<P>;
-    int blocks = (int)grid_for(n);
-    if (blocks > n_partials) blocks = n_partials;
-    if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL((k_dot_partial<P>), dim3(blocks), dim3(kThreads), 0, st, n,
+    if (n_tab <= 0 || n_fin <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_dot_partial<P>), dim3((unsigned)n_tab), dim3(kThreads), 0, st, tab,
                        (const typename T::V *)a, (const typename T::V *)b, partials);
-    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(kThreads), 0, st, blocks, partials, out);
+    hipLaunchKernelGGL(k_dot_final, dim3((unsigned)n_fin), dim3(kThreads), 0, st, fin, partials,
+                       sc, out_index);
     return hipGetLastError();
 }
 
@@ -828,21 +862,20 @@ hipError_t dot_t(int32_t n, const void *a, const void *b, double *partials, int 
     default: return hipErrorInvalidValue;                          \
     }
 
-hipError_t launch_uniform_b(int prec, const DevPlayer &p, hipStream_t st)
+hipError_t launch_spmv(int prec, int items, const SpmvBlock *tab, int32_t n_tab,
+                       const int32_t *ptr, const int32_t *idx, const void *val, const void *xin,
+                       void *yout, int xcd_remap, int sequential, int begin, Scalars *sc,
+                       hipStream_t st)
 {
-    CFR_DISPATCH(prec, uniform_t<P>(p, st));
+    CFR_DISPATCH(prec, spmv_t<P>(items, tab, n_tab, ptr, idx, val, xin, yout, xcd_remap,
+                                 sequential, begin, sc, st));
 }
 
-hipError_t launch_spmv(int prec, const DevMatrix &A, const void *xin, void *yout, int xcd_remap,
-                       int sequential, Scalars *begin_sc, const IterParams &ip, hipStream_t st)
+hipError_t launch_up(int prec, int variant, int kind, int root, const RangeBlock *tab,
+                     int32_t n_tab, const DevPlayer &p, double usign, const Scalars *sc,
+                     hipStream_t st)
 {
-    CFR_DISPATCH(prec, spmv_t<P>(A, xin, yout, xcd_remap, sequential, begin_sc, ip, st));
-}
-
-hipError_t launch_up_level(int prec, int variant, const DevPlayer &p, int level, double usign,
-                           const void *g, const Scalars *sc, hipStream_t st)
-{
-    CFR_DISPATCH(prec, up_dispatch<P>(variant, p, level, usign, g, sc, st));
+    CFR_DISPATCH(prec, up_dispatch<P>(variant, kind, root, tab, n_tab, p, usign, sc, st));
 }
 
 hipError_t launch_top(int prec, int variant, const DevPlayer &p, double usign, int average,
@@ -851,33 +884,43 @@ hipError_t launch_top(int prec, int variant, const DevPlayer &p, double usign, i
     CFR_DISPATCH(prec, top_dispatch<P>(variant, p, usign, average, sc, st));
 }
 
-hipError_t launch_down_level(int prec, const DevPlayer &p, int level, int average,
-                             const Scalars *sc, hipStream_t st)
+hipError_t launch_down(int prec, const RangeBlock *tab, int32_t n_tab, const DevPlayer &p,
+                       int average, const Scalars *sc, hipStream_t st)
 {
-    CFR_DISPATCH(prec, down_t<P>(p, level, average, sc, st));
+    CFR_DISPATCH(prec, down_t<P>(tab, n_tab, p, average, sc, st));
 }
 
-hipError_t launch_normalize(int prec, const DevPlayer &p, const Scalars *sc, hipStream_t st)
+hipError_t launch_normalize(int prec, const RangeBlock *tab, int32_t n_tab, const DevPlayer &p,
+                            const Scalars *sc, hipStream_t st)
 {
-    CFR_DISPATCH(prec, normalize_t<P>(p, sc, st));
+    CFR_DISPATCH(prec, normalize_t<P>(tab, n_tab, p, sc, st));
 }
 
-hipError_t launch_br_level(int prec, const DevPlayer &p, int level, double usign, const void *g,
-                           hipStream_t st)
+hipError_t launch_br(int prec, const RangeBlock *tab, int32_t n_tab, const DevPlayer &p,
+                     double usign, hipStream_t st)
 {
-    CFR_DISPATCH(prec, br_t<P>(p, level, usign, g, st));
+    CFR_DISPATCH(prec, br_t<P>(tab, n_tab, p, usign, st));
 }
 
-hipError_t launch_root_value(int prec, const DevPlayer &p, double usign, const void *g,
-                             double *out, hipStream_t st)
+hipError_t launch_root_value(int prec, const SlotRef *tab, int32_t n_tab, const DevPlayer &p,
+                             double usign, Scalars *sc, int out_index, hipStream_t st)
 {
-    CFR_DISPATCH(prec, root_t<P>(p, usign, g, out, st));
+    CFR_DISPATCH(prec, root_t<P>(tab, n_tab, p, usign, sc, out_index, st));
 }
 
-hipError_t launch_dot(int prec, int32_t n, const void *a, const void *b, double *partials,
-                      int n_partials, double *out, hipStream_t st)
+hipError_t launch_dot(int prec, const RangeBlock *tab, int32_t n_tab, const void *a,
+                      const void *b, double *partials, const SlotRef *fin, int32_t n_fin,
+                      Scalars *sc, int out_index, hipStream_t st)
 {
-    CFR_DISPATCH(prec, dot_t<P>(n, a, b, partials, n_partials, out, st));
+    CFR_DISPATCH(prec, dot_t<P>(tab, n_tab, a, b, partials, fin, n_fin, sc, out_index, st));
+}
+
+hipError_t launch_add_offset(int32_t *a, int64_t n, int32_t base, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_add_offset, dim3((unsigned)((n + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, st, a, n, base);
+    return hipGetLastError();
 }
 
 }  // namespace cfr

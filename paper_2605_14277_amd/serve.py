@@ -1,0 +1,204 @@
+"""Serving loop with continuous batching on one GPU.
+
+Requests (a game, a regret minimiser, an exploitability target, an
+iteration limit) arrive over time.  Arriving games are prepared on worker
+threads (``cfr_prepare``: validation, level order, float conversion; no
+device work, and ctypes releases the GIL), so preparation overlaps the
+device's iterations.  At each check boundary the loop admits waiting
+requests in arrival order while they fit the batch's free slots and device
+ranges (``cfr_batch_add_prepared`` returns CFR_ENOMEM otherwise), runs one
+check period of every game in the batch (``cfr_batch_run``), and frees the
+games that met their stopping rule.  Admission at check boundaries keeps
+every game's iterates and checks identical to the game solved alone.
+
+The device capacity is sized from a byte budget (``capacities_for_bytes``)
+with the index-unit proportions of the expected request mix.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import time
+from collections import deque
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+from . import (AVG, CFR_ENOMEM, PRECISIONS, VARIANTS, Batch, CfrError, GameArrays, _check, _lib,
+               cfr_batch_options_default, cfr_batch_workspace_size, cfr_game_params_default)
+
+
+class Prepared:
+    """A game prepared on the host for batches of one precision."""
+
+    def __init__(self, game, precision: str = "fp32_acc64"):
+        arrays = GameArrays(game)
+        self.precision = precision
+        self.n_seq = list(arrays.n_seq)
+        h = C.c_void_p()
+        _check(_lib.cfr_prepare(C.byref(arrays.desc), PRECISIONS[precision], C.byref(h)),
+               "cfr_prepare")
+        self.h = h
+        units = np.zeros(5, dtype=np.int64)
+        _check(_lib.cfr_prepared_size(h, units.ctypes.data_as(C.POINTER(C.c_int64))),
+               "cfr_prepared_size")
+        self.units = units
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.cfr_prepared_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def add_prepared(batch: Batch, prep: Prepared, variant: str, target: float = 0.0,
+                 max_iterations: int = 0, avg: str = "default", alpha: float = 1.5,
+                 beta: float = 0.0, gamma: float = 2.0) -> int:
+    gp = cfr_game_params_default()
+    gp.variant = VARIANTS[variant]
+    gp.avg_weight = AVG[avg]
+    gp.dcfr_alpha, gp.dcfr_beta, gp.dcfr_gamma = float(alpha), float(beta), float(gamma)
+    gp.target_exploitability = float(target)
+    gp.max_iterations = int(max_iterations)
+    gid = C.c_int64(-1)
+    _check(_lib.cfr_batch_add_prepared(batch.h, prep.h, C.byref(gp), C.byref(gid)),
+           "cfr_batch_add_prepared")
+    batch.n_seq[int(gid.value)] = list(prep.n_seq)
+    return int(gid.value)
+
+
+def capacities_for_bytes(budget: int, mix_units, max_games: int, precision: str = "fp32_acc64"):
+    """Largest capacities in the proportions of `mix_units` (the summed
+    index units of a representative set of games) whose batch workspace
+    fits `budget` bytes.  Returns (seq[2], inf[2], nnz)."""
+    mix = np.asarray(mix_units, dtype=np.float64)
+
+    def caps(scale):
+        u = np.maximum(np.ceil(mix * scale), [2, 2, 1, 1, 0]).astype(np.int64)
+        return [int(u[0]), int(u[1])], [int(u[2]), int(u[3])], int(u[4])
+
+    def size(scale):
+        o = cfr_batch_options_default()
+        o.precision = PRECISIONS[precision]
+        o.max_games = int(max_games)
+        seq, inf, nnz = caps(scale)
+        for p in range(2):
+            o.seq_capacity[p] = seq[p]
+            o.inf_capacity[p] = inf[p]
+        o.nnz_capacity = nnz
+        return cfr_batch_workspace_size(o)
+
+    lo, hi = 0.0, 1.0
+    while size(hi) <= budget:
+        lo, hi = hi, hi * 2
+    for _ in range(50):
+        mid = (lo + hi) / 2
+        if size(mid) <= budget:
+            lo = mid
+        else:
+            hi = mid
+    return caps(lo)
+
+
+class Server:
+    """Continuous batching over one Batch."""
+
+    def __init__(self, seq_capacity, inf_capacity, nnz_capacity, max_games: int = 256,
+                 precision: str = "fp32_acc64", check_every: int = 10, workers: int = 8,
+                 device: int = 0):
+        self.batch = Batch(seq_capacity, inf_capacity, nnz_capacity, max_games=max_games,
+                           precision=precision, mode="alternating", check_every=check_every,
+                           device=device)
+        self.precision = precision
+        self.check_every = check_every
+        self.workers = workers
+
+    def serve(self, requests, keep_strategies: bool = False, prepared=None) -> list:
+        """Serves `requests` in real time: a list of dicts with "arrival"
+        (seconds from the start, ascending), "game" (or an index into
+        `prepared`, a list of Prepared games: "prepared"), "variant",
+        "target" and "max_iterations".  Returns one record per request:
+        arrival, admitted, finished, latency, iterations, expl,
+        reached_target (and the average strategies with keep_strategies)."""
+        n = len(requests)
+        out = [None] * n
+        futures = [None] * n
+        pool = ThreadPoolExecutor(max_workers=self.workers)
+        clock = time.perf_counter
+        t0 = clock()
+        next_arrival = 0
+        waiting = deque()
+        inflight = {}
+        try:
+            while any(r is None for r in out):
+                now = clock() - t0
+                while next_arrival < n and requests[next_arrival]["arrival"] <= now:
+                    k = next_arrival
+                    r = requests[k]
+                    if "prepared" in r:
+                        futures[k] = prepared[r["prepared"]]
+                    else:
+                        futures[k] = pool.submit(Prepared, r["game"], self.precision)
+                    waiting.append(k)
+                    next_arrival += 1
+                # admit in arrival order while the head fits
+                while waiting:
+                    k = waiting[0]
+                    f = futures[k]
+                    prep = f if isinstance(f, Prepared) else (f.result() if f.done() else None)
+                    if prep is None:
+                        break
+                    r = requests[k]
+                    try:
+                        gid = add_prepared(self.batch, prep, r["variant"], r["target"],
+                                           r["max_iterations"])
+                    except CfrError as e:
+                        if e.code == CFR_ENOMEM and inflight:
+                            break
+                        raise
+                    waiting.popleft()
+                    inflight[gid] = (k, clock() - t0)
+                if inflight:
+                    self.batch.run(self.check_every)
+                    now = clock() - t0
+                    for gid in list(inflight):
+                        st = self.batch.status(gid)
+                        if st["state"] != "done":
+                            continue
+                        k, admitted = inflight.pop(gid)
+                        rec = {"arrival": requests[k]["arrival"], "admitted": admitted,
+                               "finished": now, "latency": now - requests[k]["arrival"],
+                               "iterations": st["iterations"], "expl": st["expl"],
+                               "reached_target": st["reached_target"]}
+                        if keep_strategies:
+                            rec["strategy"] = [self.batch.strategy(gid, p, "average")
+                                               for p in range(2)]
+                        self.batch.remove(gid)
+                        out[k] = rec
+                elif waiting:
+                    time.sleep(0.0005)  # the head is still being prepared
+                elif next_arrival < n:
+                    time.sleep(max(0.0, requests[next_arrival]["arrival"] - (clock() - t0)))
+        finally:
+            pool.shutdown(wait=True)
+        return out
+
+    def close(self):
+        self.batch.close()
+
+
+def sequential_latencies(arrivals, service_times):
+    """Latencies of one-at-a-time FIFO service with the given per-request
+    service times (a single server: each request starts when it has arrived
+    and the previous one has finished)."""
+    free = 0.0
+    lat = []
+    for a, s in zip(arrivals, service_times):
+        start = max(a, free)
+        free = start + s
+        lat.append(free - a)
+    return np.array(lat)

@@ -168,3 +168,71 @@ def test_null_solver_calls(cfr):
     assert lib.cfr_step(None, 1, 0, 0) == cfr.CFR_EINVAL
     lib.cfr_destroy.argtypes = [C.c_void_p]
     assert lib.cfr_destroy(None) == cfr.CFR_OK
+
+
+# ---- batches (host side only) ------------------------------------------------
+
+def test_batch_defaults_and_game_size(cfr, games):
+    o = cfr.cfr_batch_options_default()
+    assert o.precision == cfr.PRECISIONS["fp32_acc64"] and o.mode == cfr.MODES["alternating"]
+    assert o.max_games == 256 and o.check_every == 10 and o.use_graph == 1
+    gp = cfr.cfr_game_params_default()
+    assert gp.variant == cfr.VARIANTS["pcfr+"] and gp.target_exploitability == 0
+    g = games["stops"]
+    u = cfr.cfr_batch_game_size(cfr.GameArrays(g))
+    assert list(u) == [g.n_seq[0] + 1, g.n_seq[1] + 1, g.n_inf[0] + 1, g.n_inf[1] + 1, g.nnz]
+
+
+def _batch_opts(cfr, seq, inf, nnz, **kw):
+    o = cfr.cfr_batch_options_default()
+    for p in range(2):
+        o.seq_capacity[p] = seq[p]
+        o.inf_capacity[p] = inf[p]
+    o.nnz_capacity = nnz
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def test_batch_workspace_linear_in_capacity(cfr):
+    """A batch's bytes grow linearly with its index and nonzero capacities:
+    the per-unit cost of a capacity ten times larger stays within a few
+    percent of the smaller one."""
+    small = cfr.cfr_batch_workspace_size(_batch_opts(cfr, [10**5, 3 * 10**5], [4 * 10**4, 10**5],
+                                                     10**7))
+    large = cfr.cfr_batch_workspace_size(_batch_opts(cfr, [10**6, 3 * 10**6], [4 * 10**5, 10**6],
+                                                     10**8))
+    assert 9.5 < large / small < 10.5
+    # nonzeros dominate: two index/value copies (CSR and CSC) of 8 bytes each
+    per_nnz = (cfr.cfr_batch_workspace_size(_batch_opts(cfr, [10**5, 10**5], [10**4, 10**4], 2 * 10**7))
+               - cfr.cfr_batch_workspace_size(_batch_opts(cfr, [10**5, 10**5], [10**4, 10**4], 10**7))) / 10**7
+    assert 16 <= per_nnz < 17
+
+
+@pytest.mark.parametrize("field,value", [("precision", 9), ("mode", 3), ("max_games", 0),
+                                         ("check_every", 0), ("nnz_capacity", -1),
+                                         ("spmv_order", 5)])
+def test_batch_bad_options_rejected(cfr, field, value):
+    o = _batch_opts(cfr, [100, 100], [10, 10], 1000, **{field: value})
+    with pytest.raises(cfr.CfrError) as ei:
+        cfr.cfr_batch_workspace_size(o)
+    assert ei.value.code == cfr.CFR_EINVAL
+
+
+def test_batch_create_without_device_fails_cleanly(cfr):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(cfr.CfrError) as ei:
+        cfr.cfr_batch_create(_batch_opts(cfr, [100, 100], [10, 10], 1000))
+    assert ei.value.code == cfr.CFR_EDEVICE
+
+
+def test_null_batch_calls(cfr):
+    lib = C.CDLL(cfr.LIB_PATH)
+    lib.cfr_batch_run.argtypes = [C.c_void_p, C.c_int64, C.c_void_p]
+    assert lib.cfr_batch_run(None, 1, None) == cfr.CFR_EINVAL
+    lib.cfr_batch_destroy.argtypes = [C.c_void_p]
+    assert lib.cfr_batch_destroy(None) == cfr.CFR_OK
+    lib.cfr_tune.argtypes = [C.c_void_p, C.c_int, C.c_void_p]
+    assert lib.cfr_tune(None, 3, None) == cfr.CFR_EINVAL

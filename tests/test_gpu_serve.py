@@ -1,0 +1,96 @@
+"""Serving with continuous batching, through the C ABI.
+
+Requests arrive while others are iterating; they are prepared on worker
+threads, admitted at check boundaries as slots and device ranges free up,
+and freed when they meet their stopping rule.  Each result must be the same
+as the game solved alone (bit for bit: same iterates, same checks), and the
+requests must really share the device (admitted while others are in
+flight).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import gamegen as gg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cfr():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    import paper_2605_14277_amd as m
+    return m
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _requests(pool, n, mean_gap, seed):
+    rng = np.random.default_rng(seed)
+    t, out = 0.0, []
+    for k in range(n):
+        t += rng.exponential(mean_gap)
+        i = int(rng.integers(0, len(pool)))
+        rel = [1e-2, 1e-3][int(rng.integers(0, 2))]
+        out.append({"arrival": t, "game": pool[i], "variant": ["cfr+", "dcfr"][k % 2],
+                    "target": rel * gg.payoff_range(pool[i]), "max_iterations": 150})
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_acc64"])
+def test_served_results_equal_alone(cfr, games, precision):
+    from paper_2605_14277_amd import serve
+    pool = [games["cfg1"], games["stops"], games["s2d3"], games["perfect"], gg.cfg2_literal()]
+    reqs = _requests(pool, 20, 0.004, seed=3)
+    # room for about three games at once, so requests also wait for space
+    units = sorted((cfr.Batch.game_size(g) for g in pool), key=lambda u: -u[4])
+    cap = np.sum(units[:3], axis=0)
+    srv = serve.Server([cap[0], cap[1]], [cap[2], cap[3]], int(cap[4]), max_games=4,
+                       precision=precision, check_every=10, workers=4)
+    out = srv.serve(reqs, keep_strategies=True)
+    srv.close()
+    overlaps = sum(1 for i in range(len(out)) for j in range(i + 1, len(out))
+                   if out[i]["admitted"] < out[j]["finished"] and
+                   out[j]["admitted"] < out[i]["finished"])
+    say(f"  {precision}: {len(out)} requests, {overlaps} overlapping pairs, latency p50 "
+        f"{np.percentile([o['latency'] for o in out], 50) * 1e3:.1f} ms")
+    assert overlaps > 0
+    for k, (r, o) in enumerate(zip(reqs, out)):
+        assert o["iterations"] % 10 == 0 and o["latency"] >= 0
+        assert o["admitted"] >= r["arrival"] and o["finished"] >= o["admitted"]
+        if o["reached_target"]:
+            assert o["expl"] <= r["target"]
+        else:
+            assert o["iterations"] == 150
+        solo = cfr.Solver(r["game"], precision=precision)
+        solo.step(o["iterations"], r["variant"], "alternating")
+        for p in range(2):
+            assert np.array_equal(o["strategy"][p], solo.strategy(p, "average")), (k, p)
+        assert solo.exploitability("average")["expl"] == o["expl"], k
+        solo.close()
+
+
+def test_prepared_game_reuse_and_precision_check(cfr, games):
+    from paper_2605_14277_amd import serve
+    g = games["stops"]
+    prep = serve.Prepared(g, "fp64")
+    assert list(prep.units) == list(cfr.Batch.game_size(g))
+    u = prep.units
+    b = cfr.Batch([2 * u[0], 2 * u[1]], [2 * u[2], 2 * u[3]], int(2 * u[4]), max_games=2,
+                  precision="fp64")
+    a = serve.add_prepared(b, prep, "cfr+")
+    c = serve.add_prepared(b, prep, "cfr+")  # the same prepared game twice
+    b.run(30)
+    assert np.array_equal(b.strategy(a, 0, "average"), b.strategy(c, 0, "average"))
+    other = cfr.Batch([u[0], u[1]], [u[2], u[3]], int(u[4]), max_games=1, precision="fp32")
+    with pytest.raises(cfr.CfrError) as ei:
+        serve.add_prepared(other, prep, "cfr+")
+    assert ei.value.code == cfr.CFR_EINVAL
+    other.close()
+    b.close()
+    prep.close()
