@@ -296,6 +296,7 @@ def bench_serving(args, torch):
                            check_every=K)
         t0 = time.perf_counter()
         out = srv.serve(reqs, prepared=prepared)
+        host = srv.batch.host_stats()
         srv.close()
         lat = np.array([o["latency"] for o in out])
         span = max(o["finished"] for o in out) - float(arrivals[0])
@@ -307,11 +308,13 @@ def bench_serving(args, torch):
             "served": {"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
                        "solves_per_s": n / span, "reached_target": int(sum(o["reached_target"]
                                                                            for o in out)),
-                       "same_iterations_as_alone": bool(same)},
+                       "same_iterations_as_alone": bool(same), "host": host},
             "one_at_a_time": {"p50_s": float(np.percentile(seq_lat, 50)),
                               "p99_s": float(np.percentile(seq_lat, 99)),
                               "solves_per_s": n / seq_span},
         }
+        log("[bench]   host " + ", ".join(f"{k} {v['seconds'] * 1e3:.0f} ms/{v['calls']}"
+                                        for k, v in host.items()))
         log(f"[bench] {rate:g} req/s: served p50 {np.percentile(lat, 50) * 1e3:.0f} ms, p99 "
             f"{np.percentile(lat, 99) * 1e3:.0f} ms, {n / span:.1f} solves/s; one at a time p50 "
             f"{np.percentile(seq_lat, 50) * 1e3:.0f} ms, p99 {np.percentile(seq_lat, 99) * 1e3:.0f} ms, "
@@ -372,10 +375,12 @@ def main():
     ap.add_argument("--precision", default=None)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--spmv-order", default="default", choices=["default", "sequential", "parallel"])
+    ap.add_argument("--sweep", action="store_true",
+                    help="time both products under every tiling (stderr table, 'sweep' field)")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default product tiling instead of running the autotuner")
     ap.add_argument("--tiling", default=None,
-                    help="fixed product tiling 'items_Ay,items_ATx:rows_Ay,rows_ATx' "
+                    help="fixed product tiling 'items_Ay,items_ATx:rows_Ay,rows_ATx:vec_Ay,vec_ATx' "
                          "(skips the autotuner)")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle time for the CPU baseline sample")
@@ -422,11 +427,31 @@ def main():
                    spmv_order=args.spmv_order)
     torch.cuda.synchronize()
     log(f"[bench] cfr_create {time.perf_counter() - t0:.1f}s, workspace {s.workspace_bytes / 1e9:.2f} GB")
+    sweep = None
+    if args.sweep:
+        sweep = []
+        s.step(3, variant, mode)
+        for vec in (0, 1):
+            for items in (4, 8, 16):
+                for rows in (64, 128, 256):
+                    s.tiling = {"items": [items, items], "rows": [rows, rows], "vec": [vec, vec]}
+                    s.kernel_timing(True)
+                    s.step(20, variant, mode)
+                    us = []
+                    for k in (0, 1):
+                        n, tot, _ = s.kernel_stats(k)
+                        us.append(tot / n * 1e3)
+                    s.kernel_timing(False)
+                    sweep.append({"vec": vec, "items": items, "rows": rows, "csr_us": us[0],
+                                  "csc_us": us[1]})
+                    log(f"[sweep] vec {vec} items {items:2d} rows {rows:3d}: A y {us[0]:7.1f} us, "
+                        f"A^T x {us[1]:7.1f} us")
     tune_s = None
     if args.tiling:
-        it_s, rows_s = args.tiling.split(":")
-        s.tiling = {"items": [int(v) for v in it_s.split(",")],
-                    "rows": [int(v) for v in rows_s.split(",")]}
+        parts = args.tiling.split(":")
+        s.tiling = {"items": [int(v) for v in parts[0].split(",")],
+                    "rows": [int(v) for v in parts[1].split(",")],
+                    "vec": [int(v) for v in parts[2].split(",")] if len(parts) > 2 else [1, 1]}
     elif not args.no_tune:
         t0 = time.perf_counter()
         s.tune(reps=10)
@@ -512,6 +537,8 @@ def main():
         "cpu_baseline": cpu,
         "expl_average": e["expl"],
     }
+    if sweep is not None:
+        out["sweep"] = sweep
     print(json.dumps(out), flush=True)
     s.close()
 

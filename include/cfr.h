@@ -212,13 +212,16 @@ int cfr_kernel_timing(cfr_solver *s, int enable);
 int cfr_kernel_stats(cfr_solver *s, int kernel, int64_t *launches, double *total_ms,
                      double *bytes_per_launch);
 
-/* Payoff-product tiling: nonzeros per thread (4, 8 or 16; a block stages
- * 256 times that many) and rows per block (64..256) of the A y product
- * (index 0) and of the A^T x product (index 1).  Rows longer than one
- * block's capacity are summed by a tree in every order.                    */
+/* Payoff-product tiling of the A y product (index 0) and of the A^T x
+ * product (index 1): nonzeros per thread (4, 8 or 16; a block holds up to
+ * 256 times that many less 3), rows per block (64..256), and vec (1: the
+ * index and value streams are read with 16-byte loads, four elements per
+ * lane; 0: one 4-byte load per element).  Rows longer than one block's
+ * capacity are summed by a tree in every order.                           */
 typedef struct cfr_spmv_tiling {
     int items[2];
     int rows[2];
+    int vec[2];
 } cfr_spmv_tiling;
 
 /* Reads / sets the solver's tiling (CFR_EINVAL outside the ranges above).  */
@@ -354,6 +357,12 @@ int cfr_batch_tune(cfr_batch *b, int reps, cfr_spmv_tiling *chosen);
 int cfr_batch_kernel_timing(cfr_batch *b, int enable);
 int cfr_batch_kernel_stats(cfr_batch *b, int kernel, int64_t *launches, double *total_ms,
                            double *bytes_per_launch);
+
+/* Host seconds and calls spent so far by the batch's runtime: out[0..5]
+ * seconds in table builds, graph captures, evaluations (including their
+ * wait for the stream), iteration enqueues, game additions and removals;
+ * out[6..11] the matching call counts.  For reports.                     */
+int cfr_batch_host_stats(cfr_batch *b, double *out);
 
 int cfr_batch_destroy(cfr_batch *b);
 

@@ -56,7 +56,7 @@ class cfr_options(C.Structure):
 
 
 class cfr_spmv_tiling(C.Structure):
-    _fields_ = [("items", C.c_int * 2), ("rows", C.c_int * 2)]
+    _fields_ = [("items", C.c_int * 2), ("rows", C.c_int * 2), ("vec", C.c_int * 2)]
 
 
 class cfr_batch_options(C.Structure):
@@ -117,6 +117,7 @@ _lib.cfr_batch_kernel_stats.argtypes = [C.c_void_p, C.c_int, _P(C.c_int64), _P(C
                                         _P(C.c_double)]
 _lib.cfr_batch_destroy.argtypes = [C.c_void_p]
 _lib.cfr_prepare.argtypes = [_P(cfr_game_desc), C.c_int, _P(C.c_void_p)]
+_lib.cfr_batch_host_stats.argtypes = [C.c_void_p, _P(C.c_double)]
 _lib.cfr_prepared_size.argtypes = [C.c_void_p, _P(C.c_int64)]
 _lib.cfr_batch_add_prepared.argtypes = [C.c_void_p, C.c_void_p, _P(cfr_game_params),
                                         _P(C.c_int64)]
@@ -130,7 +131,7 @@ for _f in ("cfr_options_default", "cfr_validate", "cfr_workspace_size", "cfr_cre
            "cfr_batch_exploitability", "cfr_batch_remove", "cfr_batch_get_tiling",
            "cfr_batch_set_tiling", "cfr_batch_tune", "cfr_batch_kernel_timing",
            "cfr_batch_kernel_stats", "cfr_batch_destroy", "cfr_prepare", "cfr_prepared_size",
-           "cfr_batch_add_prepared", "cfr_prepared_destroy"):
+           "cfr_batch_add_prepared", "cfr_prepared_destroy", "cfr_batch_host_stats"):
     getattr(_lib, _f).restype = C.c_int
 
 
@@ -255,7 +256,8 @@ def cfr_kernel_stats(h, kernel: int):
 
 
 def _tiling_dict(t: cfr_spmv_tiling) -> dict:
-    return {"items": [int(t.items[0]), int(t.items[1])], "rows": [int(t.rows[0]), int(t.rows[1])]}
+    return {"items": [int(t.items[0]), int(t.items[1])], "rows": [int(t.rows[0]), int(t.rows[1])],
+            "vec": [int(t.vec[0]), int(t.vec[1])]}
 
 
 def _tiling_struct(d: dict) -> cfr_spmv_tiling:
@@ -263,6 +265,7 @@ def _tiling_struct(d: dict) -> cfr_spmv_tiling:
     for w in range(2):
         t.items[w] = int(d["items"][w])
         t.rows[w] = int(d["rows"][w])
+        t.vec[w] = int(d.get("vec", [1, 1])[w])
     return t
 
 
@@ -386,6 +389,16 @@ def cfr_batch_kernel_stats(h, kernel: int):
     _check(_lib.cfr_batch_kernel_stats(h, kernel, C.byref(n), C.byref(ms), C.byref(by)),
            "cfr_batch_kernel_stats")
     return int(n.value), float(ms.value), float(by.value)
+
+
+HOST_STATS = ("tables", "graph", "evaluate", "enqueue", "add", "remove")
+
+
+def cfr_batch_host_stats(h) -> dict:
+    out = np.zeros(12)
+    _check(_lib.cfr_batch_host_stats(h, _dptr(out)), "cfr_batch_host_stats")
+    return {k: {"seconds": float(out[i]), "calls": int(out[6 + i])}
+            for i, k in enumerate(HOST_STATS)}
 
 
 def cfr_batch_destroy(h):
@@ -556,6 +569,9 @@ class Batch:
 
     def kernel_timing(self, enable: bool):
         cfr_batch_kernel_timing(self.h, enable)
+
+    def host_stats(self) -> dict:
+        return cfr_batch_host_stats(self.h)
 
     def kernel_stats(self, kernel: int):
         return cfr_batch_kernel_stats(self.h, kernel)

@@ -174,6 +174,7 @@ int check_tiling(const cfr_spmv_tiling *t)
             return fail(CFR_EINVAL, "nonzeros per thread must be 4, 8 or 16");
         if (t->rows[w] < 64 || t->rows[w] > cfr::kSpmvRowCap)
             return fail(CFR_EINVAL, "rows per block must be in [64, 256]");
+        if (t->vec[w] != 0 && t->vec[w] != 1) return fail(CFR_EINVAL, "vec must be 0 or 1");
     }
     return CFR_OK;
 }
@@ -208,12 +209,13 @@ void get_tiling(const cfr::Engine &e, cfr_spmv_tiling *t)
     for (int w = 0; w < 2; ++w) {
         t->items[w] = e.items[w];
         t->rows[w] = e.rows[w];
+        t->vec[w] = e.vec[w];
     }
 }
 
 int set_tiling(cfr::Engine &e, const cfr_spmv_tiling *t)
 {
-    for (int w = 0; w < 2; ++w) e.repartition(w, t->items[w], t->rows[w]);
+    for (int w = 0; w < 2; ++w) e.repartition(w, t->items[w], t->rows[w], t->vec[w]);
     return CFR_OK;
 }
 
@@ -226,20 +228,22 @@ int tune(cfr::Engine &e, int reps, cfr_spmv_tiling *chosen)
     static const int kRows[] = {64, 128, 256};
     for (int w = 0; w < 2; ++w) {
         double best = -1;
-        int bi = e.items[w], br = e.rows[w];
-        for (int items : kItems)
-            for (int rows : kRows) {
-                e.repartition(w, items, rows);
-                double ms = 0;
-                int rc = e.time_spmv(w, reps, &ms);
-                if (rc) return rc;
-                if (best < 0 || ms < best) {
-                    best = ms;
-                    bi = items;
-                    br = rows;
+        int bi = e.items[w], br = e.rows[w], bv = e.vec[w];
+        for (int vec = 0; vec < 2; ++vec)
+            for (int items : kItems)
+                for (int rows : kRows) {
+                    e.repartition(w, items, rows, vec);
+                    double ms = 0;
+                    int rc = e.time_spmv(w, reps, &ms);
+                    if (rc) return rc;
+                    if (best < 0 || ms < best) {
+                        best = ms;
+                        bi = items;
+                        br = rows;
+                        bv = vec;
+                    }
                 }
-            }
-        e.repartition(w, bi, br);
+        e.repartition(w, bi, br, bv);
     }
     if (chosen) get_tiling(e, chosen);
     return CFR_OK;
@@ -902,6 +906,16 @@ int cfr_batch_kernel_stats(cfr_batch *b, int kernel, int64_t *launches, double *
     if (!b || kernel < 0 || kernel > 1) return fail(CFR_EINVAL, "bad batch or kernel");
     DeviceGuard guard(b->eng.device);
     return kernel_stats(b->eng, kernel, launches, total_ms, bytes_per_launch);
+}
+
+int cfr_batch_host_stats(cfr_batch *b, double *out)
+{
+    if (!b || !out) return fail(CFR_EINVAL, "null argument");
+    for (int i = 0; i < cfr::Engine::kHostN; ++i) {
+        out[i] = b->eng.host_s[i];
+        out[cfr::Engine::kHostN + i] = (double)b->eng.host_n[i];
+    }
+    return CFR_OK;
 }
 
 int cfr_batch_destroy(cfr_batch *b)

@@ -160,12 +160,22 @@ struct Tables {
     bool valid = false;
 };
 
+// Adds the wall time of its scope to a host-time counter.
+struct HostTimer {
+    double *acc;
+    int64_t *cnt;
+    double t0;
+    HostTimer(double *a, int64_t *c);
+    ~HostTimer();
+};
+
 struct Engine {
     int prec = CFR_FP64;
     int mode = -1;  // CFR_SIMULTANEOUS / CFR_ALTERNATING, fixed by the first step
     int spmv_order = CFR_SPMV_DEFAULT;
     int items[2] = {kSpmvItemsDefault, kSpmvItemsDefault};
     int rows[2] = {kSpmvRowCap, kSpmvRowCap};
+    int vec[2] = {1, 1};  // 16-byte stream loads in the products
     int xcd_remap = 1;
     int device = 0;
     bool use_graph = true;
@@ -197,6 +207,11 @@ struct Engine {
     int64_t check_every = 0;  // 0: no checks (single-game solver)
     int64_t phase = 0;        // iterations since the last check
 
+    // host-side time and calls per activity (kHost* below), for reports
+    enum { kHostTables = 0, kHostGraph, kHostEval, kHostEnqueue, kHostAdd, kHostRemove, kHostN };
+    double host_s[kHostN] = {0, 0, 0, 0, 0, 0};
+    int64_t host_n[kHostN] = {0, 0, 0, 0, 0, 0};
+
     // per-launch timing of the payoff products (HIP events on st)
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events[2];
@@ -217,7 +232,7 @@ struct Engine {
     void remove(int slot);
     int set_params(int slot, const GameParams &gp);  // writes the game's constants to the device
     // Re-partitions every game's product blocks for a new tiling.
-    void repartition(int which, int items_, int rows_);
+    void repartition(int which, int items_, int rows_, int vec_);
     void partition(Slot &s, int which);
 
     std::vector<int> active_set() const;

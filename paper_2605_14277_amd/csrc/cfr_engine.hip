@@ -12,6 +12,7 @@
 #include "cfr_engine.h"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -308,8 +309,9 @@ Layout carve(Carver &k, const Capacity &c, int prec)
     }
     for (int w = 0; w < 2; ++w) {
         L.ptr[w] = (int32_t *)k.take(4 * (size_t)std::max<int64_t>(c.seq[w], 1));
-        L.idx[w] = (int32_t *)k.take(4 * (size_t)std::max<int64_t>(c.nnz, 1));
-        L.val[w] = k.take(V * (size_t)std::max<int64_t>(c.nnz, 1));
+        // kStreamPad readable elements past the last nonzero (16-byte stream loads)
+        L.idx[w] = (int32_t *)k.take(4 * (size_t)(c.nnz + kStreamPad));
+        L.val[w] = k.take(V * (size_t)(c.nnz + kStreamPad));
     }
     const TableLayout T = table_layout(c);
     L.tab_bytes = T.bytes;
@@ -483,8 +485,8 @@ Capacity lone_capacity(const HostGame &hg, int items_csr, int rows_csr, int item
     (void)rows_csr;
     (void)items_csc;
     (void)rows_csc;
-    c.t_csr = (int64_t)partition_rows(hg.ptr[0], kSpmvThreads * 4, 64).size() - 1;
-    c.t_csc = (int64_t)partition_rows(hg.ptr[1], kSpmvThreads * 4, 64).size() - 1;
+    c.t_csr = (int64_t)partition_rows(hg.ptr[0], spmv_block_cap(4), 64).size() - 1;
+    c.t_csc = (int64_t)partition_rows(hg.ptr[1], spmv_block_cap(4), 64).size() - 1;
     return c;
 }
 
@@ -497,7 +499,7 @@ void bound_tables(Capacity &c)
     // kRangeBlock indices plus one partial block per (game, level), and a
     // game has at most as many levels as decision points.
     for (int w = 0; w < 2; ++w) {
-        const int64_t t = 2 * c.nnz / (kSpmvThreads * 4) + c.seq[w] / 64 + 2 * c.slots + 1;
+        const int64_t t = 2 * c.nnz / spmv_block_cap(4) + c.seq[w] / 64 + 2 * c.slots + 1;
         if (w == 0) c.t_csr = t;
         else c.t_csc = t;
     }
@@ -515,6 +517,19 @@ size_t engine_bytes(const Capacity &c, int prec)
     Carver k;
     carve(k, c, prec);
     return k.cur + 256;
+}
+
+static double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+HostTimer::HostTimer(double *a, int64_t *c) : acc(a), cnt(c), t0(now_s()) {}
+HostTimer::~HostTimer()
+{
+    *acc += now_s() - t0;
+    ++*cnt;
 }
 
 // ---------------------------------------------------------------------------
@@ -688,7 +703,7 @@ void Engine::partition(Slot &s, int which)
 {
     const int k = (int)(&s - slots.data());
     const std::vector<int32_t> blk =
-        partition_rows(s.ptr[which], kSpmvThreads * items[which], rows[which]);
+        partition_rows(s.ptr[which], spmv_block_cap(items[which]), rows[which]);
     s.blocks[which].clear();
     s.blocks[which].reserve(blk.size());
     for (size_t i = 0; i + 1 < blk.size(); ++i) {
@@ -705,10 +720,11 @@ void Engine::partition(Slot &s, int which)
     }
 }
 
-void Engine::repartition(int which, int items_, int rows_)
+void Engine::repartition(int which, int items_, int rows_, int vec_)
 {
     items[which] = items_;
     rows[which] = rows_;
+    vec[which] = vec_;
     for (Slot &s : slots)
         if (s.live) partition(s, which);
     it.valid = false;
@@ -737,6 +753,7 @@ int Engine::set_params(int k, const GameParams &gp)
 
 int Engine::add(const HostGame &hg, const GameParams &gp, bool join_now, int *slot_out)
 {
+    HostTimer timer(&host_s[kHostAdd], &host_n[kHostAdd]);
     int k = -1;
     for (size_t i = 0; i < slots.size(); ++i)
         if (!slots[i].live) {
@@ -869,6 +886,7 @@ int Engine::add(const HostGame &hg, const GameParams &gp, bool join_now, int *sl
 
 void Engine::remove(int k)
 {
+    HostTimer timer(&host_s[kHostRemove], &host_n[kHostRemove]);
     Slot &s = slots[(size_t)k];
     if (!s.live) return;
     for (int p = 0; p < 2; ++p) {
@@ -899,7 +917,7 @@ bool Engine::tables_in_bounds(const Tables &T) const
     auto live = [&](int k) { return k >= 0 && k < (int)slots.size() && slots[(size_t)k].live; };
     for (int w = 0; w < 2; ++w) {
         const std::vector<SpmvBlock> &v = w == 0 ? T.h_csr : T.h_csc;
-        const int cap_nnz = kSpmvThreads * items[w];
+        const int cap_nnz = spmv_block_cap(items[w]);
         for (const SpmvBlock &b : v) {
             if (!live(b.slot)) return false;
             const Slot &s = slots[(size_t)b.slot];
@@ -940,6 +958,7 @@ bool Engine::tables_in_bounds(const Tables &T) const
 
 int Engine::build_tables(Tables &T, char *region, const std::vector<int> &set)
 {
+    HostTimer timer(&host_s[kHostTables], &host_n[kHostTables]);
     (void)region;
     // the previous upload may still be in flight
     hipError_t e = hipStreamSynchronize(st);
@@ -1059,14 +1078,16 @@ hipError_t Engine::spmv(const Tables &T, int which, const void *xin, void *yout,
         if (e == hipSuccess) e = hipEventCreate(&b);
         if (e != hipSuccess) return e;
         (void)hipEventRecord(a, s);
-        e = launch_spmv(prec, items[which], tab, n, ptr[which], idx[which], val[which], xin, yout,
+        e = launch_spmv(prec, items[which], vec[which], tab, n, ptr[which], idx[which], val[which],
+                        xin, yout,
                         xcd_remap, sequential(), begin ? 1 : 0, sc, s);
         (void)hipEventRecord(b, s);
         events[which].emplace_back(a, b);
         launches[which]++;
         return e;
     }
-    return launch_spmv(prec, items[which], tab, n, ptr[which], idx[which], val[which], xin, yout,
+    return launch_spmv(prec, items[which], vec[which], tab, n, ptr[which], idx[which], val[which],
+                       xin, yout,
                        xcd_remap, sequential(), begin ? 1 : 0, sc, s);
 }
 
@@ -1116,6 +1137,7 @@ hipError_t Engine::enqueue_iteration(hipStream_t s)
 
 hipError_t Engine::build_graph()
 {
+    HostTimer timer(&host_s[kHostGraph], &host_n[kHostGraph]);
     hipError_t e = hipSuccess;
     if (!cap_st) {
         e = hipStreamCreateWithFlags(&cap_st, hipStreamNonBlocking);
@@ -1153,6 +1175,7 @@ int Engine::iterate(int64_t n)
                 return device_error("graph capture of one iteration", e);
             }
         }
+        HostTimer timer(&host_s[kHostEnqueue], &host_n[kHostEnqueue]);
         for (int64_t i = 0; i < n && e == hipSuccess; ++i) e = hipGraphLaunch(gexec, st);
     } else {
         for (int64_t i = 0; i < n && e == hipSuccess; ++i) e = enqueue_iteration(st);
@@ -1165,6 +1188,7 @@ int Engine::iterate(int64_t n)
 int Engine::evaluate(const std::vector<int> &set, int kind)
 {
     if (set.empty()) return CFR_OK;
+    HostTimer timer(&host_s[kHostEval], &host_n[kHostEval]);
     const Tables *T = nullptr;
     if (it.valid && set == active_set()) {
         T = &it;

@@ -89,8 +89,10 @@ struct DevPlayer {
 // Payoff product yout = M xin over the blocks of `tab`; with `begin`, the
 // first block of each game advances that game's scalars.  items: nonzeros
 // per thread of the kernel instance (the block partition must hold at most
-// kSpmvThreads*items nonzeros per block, or one row).
-hipError_t launch_spmv(int prec, int items, const SpmvBlock *tab, int32_t n_tab,
+// spmv_block_cap(items) nonzeros per block, or one row); vec: 16-byte
+// stream loads.  The index and value arrays must be readable three elements
+// past the last nonzero.
+hipError_t launch_spmv(int prec, int items, int vec, const SpmvBlock *tab, int32_t n_tab,
                        const int32_t *ptr, const int32_t *idx, const void *val, const void *xin,
                        void *yout, int xcd_remap, int sequential, int begin, Scalars *sc,
                        hipStream_t st);
@@ -148,6 +150,10 @@ constexpr int kSpmvItemsMax = 16;
 constexpr int kSpmvRowCap = 256;  // rows per block at most
 static_assert(kSpmvRowCap <= kSpmvThreads, "a block's row pointers are one per thread");
 inline bool spmv_items_supported(int items) { return items == 4 || items == 8 || items == 16; }
+// Nonzeros one block of the product may hold: the staging area less the up
+// to three elements the 16-byte stream loads start before the block.
+__host__ __device__ constexpr int spmv_block_cap(int items) { return kSpmvThreads * items - 3; }
+constexpr int kStreamPad = 4;  // readable elements past the end of the index/value arrays
 constexpr int kRangeBlock = 256;  // decision points or sequences per sweep block
 // 1: run the shallow levels in one launch (k_top) even when deeper levels
 // remain as per-level launches

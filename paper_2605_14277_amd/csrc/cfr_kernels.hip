@@ -72,6 +72,55 @@ constexpr int kMaxActs = 8;  // decision points up to this size keep their actio
 
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
+typedef int32_t v4i __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
+
+// Four consecutive stream elements with 16-byte loads (the address is a
+// multiple of four elements).
+__device__ __forceinline__ v4i load4(const int32_t *p)
+{
+#if CFR_SPMV_NONTEMPORAL
+    return __builtin_nontemporal_load((const v4i *)p);
+#else
+    return *(const v4i *)p;
+#endif
+}
+__device__ __forceinline__ void load4(const float *p, float (&o)[4])
+{
+#if CFR_SPMV_NONTEMPORAL
+    const v4f t = __builtin_nontemporal_load((const v4f *)p);
+#else
+    const v4f t = *(const v4f *)p;
+#endif
+    o[0] = t.x;
+    o[1] = t.y;
+    o[2] = t.z;
+    o[3] = t.w;
+}
+__device__ __forceinline__ void load4(const double *p, double (&o)[4])
+{
+#if CFR_SPMV_NONTEMPORAL
+    const v2d a = __builtin_nontemporal_load((const v2d *)p);
+    const v2d b = __builtin_nontemporal_load((const v2d *)p + 1);
+#else
+    const v2d a = *(const v2d *)p, b = *((const v2d *)p + 1);
+#endif
+    o[0] = a.x;
+    o[1] = a.y;
+    o[2] = b.x;
+    o[3] = b.y;
+}
+__device__ __forceinline__ void store4(float *p, const float (&o)[4])
+{
+    *(v4f *)p = v4f{o[0], o[1], o[2], o[3]};
+}
+__device__ __forceinline__ void store4(double *p, const double (&o)[4])
+{
+    *(v2d *)p = v2d{o[0], o[1]};
+    *((v2d *)p + 1) = v2d{o[2], o[3]};
+}
+
 // ---------------------------------------------------------------------------
 // Per-iteration scalars
 // ---------------------------------------------------------------------------
@@ -108,12 +157,19 @@ __device__ void begin_iteration(Scalars *sc)
 // evaluation bit for bit; otherwise a power-of-two group of lanes shares
 // each row and combines its partial sums with cross-lane shuffles.
 //
+// VEC: the index and value streams are read four elements per lane with
+// 16-byte loads from the block's first element rounded down to a multiple
+// of four (the block partition leaves room for the up to three elements
+// before it); products are staged at their offset from that aligned start.
+// Elements outside the block gather entry 0 and stage a zero that no row
+// reads.  Otherwise every element is its own 4-byte load.
+//
 // Each table entry gives a block's rows, nonzeros and game in one scalar
 // load.  The loads of a block are all issued
 // unconditionally (lanes past the end read the block's first entry and
 // ignore it): index/value stream and row pointers in one round, gathers in
 // the next; the reduction then reads only LDS.
-template <int P, bool SEQ, int ITEMS>
+template <int P, bool SEQ, int ITEMS, bool VEC>
 __global__ __launch_bounds__(kSpmvThreads) void k_spmv(
     int32_t n_blk, const SpmvBlock *__restrict__ tab, const int32_t *__restrict__ ptr,
     const int32_t *__restrict__ idx, const typename Types<P>::V *__restrict__ val,
@@ -125,7 +181,7 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(
     // products staged in LDS: the compute type, or the value type when the
     // FP32 modes are built to stage them compactly
     using L = typename std::conditional<(CFR_SPMV_LDS_VALUE != 0) && P != CFR_FP64, V, C>::type;
-    constexpr int kCap = kSpmvThreads * ITEMS;  // nonzeros staged per block
+    constexpr int kCap = kSpmvThreads * ITEMS;  // staged products per block
     __shared__ L prod[kCap];
     __shared__ int32_t s_ptr[kSpmvRowCap + 1];
     __shared__ C red[kSpmvThreads];
@@ -145,7 +201,7 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(
     const int32_t rb = bk.row0, nr = bk.nr, n = bk.n, p0 = bk.p0;
     const int64_t e0 = bk.e0;
 
-    if (n > kCap) {
+    if (n > spmv_block_cap(ITEMS)) {
         // a single long row: strided partial sums, then a fixed-order tree
         C acc = 0;
         for (int32_t i = tid; i < n; i += kSpmvThreads)
@@ -160,13 +216,51 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(
         return;
     }
 
-    int32_t c[ITEMS];
-    V v[ITEMS];
-    V gx[ITEMS];
     // this block's row pointers: one per thread (a block has at most
     // kSpmvRowCap = kSpmvThreads rows)
     const int32_t pr = ptr[rb + (tid < nr ? tid : 0)];
-    if (n > 0) {
+    int32_t sh = 0;  // staging offset of the block's first element
+    if (VEC) {
+        constexpr int NV = ITEMS / 4;
+        const int64_t e_al = e0 & ~(int64_t)3;
+        sh = (int32_t)(e0 - e_al);
+        const int32_t n_al = n + sh;
+        if (n > 0) {
+            v4i c4[NV];
+            V v4[NV][4];
+#pragma unroll
+            for (int j = 0; j < NV; ++j) {
+                const int32_t vi = j * kSpmvThreads + tid;
+                const int64_t at = e_al + 4 * (int64_t)(4 * vi < n_al ? vi : 0);
+                c4[j] = load4(idx + at);
+                load4(val + at, v4[j]);
+            }
+            V gx[NV][4];
+#pragma unroll
+            for (int j = 0; j < NV; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int32_t q = 4 * (j * kSpmvThreads + tid) + e - sh;
+                    gx[j][e] = xin[(q >= 0 && q < n) ? c4[j][e] : 0];
+                }
+            // every lane stores its four slots (zeros outside the block):
+            // no branch the loads above could be moved into
+#pragma unroll
+            for (int j = 0; j < NV; ++j) {
+                const int32_t vi = j * kSpmvThreads + tid;
+                L o[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int32_t q = 4 * vi + e - sh;
+                    o[e] = (q >= 0 && q < n) ? (L)((C)v4[j][e] * (C)gx[j][e]) : (L)0;
+                }
+                store4(&prod[4 * vi], o);
+            }
+        }
+    } else if (n > 0) {
+        int32_t c[ITEMS];
+        V v[ITEMS];
+        V gx[ITEMS];
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
             const int32_t i = k * kSpmvThreads + tid;
@@ -187,8 +281,8 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(
             if (i < n) prod[i] = (L)((C)v[k] * (C)gx[k]);
         }
     }
-    if (tid < nr) s_ptr[tid] = pr - p0;
-    if (tid == 0) s_ptr[nr] = n;
+    if (tid < nr) s_ptr[tid] = pr - p0 + sh;
+    if (tid == 0) s_ptr[nr] = n + sh;
     __syncthreads();
     if (SEQ) {
         if (tid < nr) {
@@ -678,46 +772,56 @@ __global__ __launch_bounds__(kThreads) void k_add_offset(int32_t *a, int64_t n, 
 // Launch helpers
 // ---------------------------------------------------------------------------
 
-template <int P, bool SEQ, int ITEMS>
+template <int P, bool SEQ, int ITEMS, bool VEC>
 hipError_t spmv_launch(const SpmvBlock *tab, int32_t n_tab, const int32_t *ptr, const int32_t *idx,
                        const void *val, const void *xin, void *yout, int xcd_remap, int begin,
                        Scalars *sc, hipStream_t st)
 {
     using V = typename Types<P>::V;
     unsigned grid = xcd_remap ? (unsigned)(((n_tab + 7) / 8) * 8) : (unsigned)n_tab;
-    hipLaunchKernelGGL((k_spmv<P, SEQ, ITEMS>), dim3(grid), dim3(kSpmvThreads), 0, st, n_tab, tab,
-                       ptr, idx, (const V *)val, (const V *)xin, (V *)yout, xcd_remap, begin, sc);
+    hipLaunchKernelGGL((k_spmv<P, SEQ, ITEMS, VEC>), dim3(grid), dim3(kSpmvThreads), 0, st, n_tab,
+                       tab, ptr, idx, (const V *)val, (const V *)xin, (V *)yout, xcd_remap, begin,
+                       sc);
     return hipGetLastError();
 }
 
-template <int P, bool SEQ>
+template <int P, bool SEQ, bool VEC>
 hipError_t spmv_items(int items, const SpmvBlock *tab, int32_t n_tab, const int32_t *ptr,
                       const int32_t *idx, const void *val, const void *xin, void *yout,
                       int xcd_remap, int begin, Scalars *sc, hipStream_t st)
 {
     switch (items) {
     case 4:
-        return spmv_launch<P, SEQ, 4>(tab, n_tab, ptr, idx, val, xin, yout, xcd_remap, begin, sc, st);
+        return spmv_launch<P, SEQ, 4, VEC>(tab, n_tab, ptr, idx, val, xin, yout, xcd_remap, begin,
+                                           sc, st);
     case 8:
-        return spmv_launch<P, SEQ, 8>(tab, n_tab, ptr, idx, val, xin, yout, xcd_remap, begin, sc, st);
+        return spmv_launch<P, SEQ, 8, VEC>(tab, n_tab, ptr, idx, val, xin, yout, xcd_remap, begin,
+                                           sc, st);
     case 16:
-        return spmv_launch<P, SEQ, 16>(tab, n_tab, ptr, idx, val, xin, yout, xcd_remap, begin, sc,
-                                       st);
+        return spmv_launch<P, SEQ, 16, VEC>(tab, n_tab, ptr, idx, val, xin, yout, xcd_remap, begin,
+                                            sc, st);
     default: return hipErrorInvalidValue;
     }
 }
 
 template <int P>
-hipError_t spmv_t(int items, const SpmvBlock *tab, int32_t n_tab, const int32_t *ptr,
+hipError_t spmv_t(int items, int vec, const SpmvBlock *tab, int32_t n_tab, const int32_t *ptr,
                   const int32_t *idx, const void *val, const void *xin, void *yout, int xcd_remap,
                   int sequential, int begin, Scalars *sc, hipStream_t st)
 {
     if (n_tab <= 0) return hipSuccess;
-    if (sequential)
-        return spmv_items<P, true>(items, tab, n_tab, ptr, idx, val, xin, yout, xcd_remap, begin,
-                                   sc, st);
-    return spmv_items<P, false>(items, tab, n_tab, ptr, idx, val, xin, yout, xcd_remap, begin, sc,
-                                st);
+    if (sequential) {
+        if (vec)
+            return spmv_items<P, true, true>(items, tab, n_tab, ptr, idx, val, xin, yout,
+                                             xcd_remap, begin, sc, st);
+        return spmv_items<P, true, false>(items, tab, n_tab, ptr, idx, val, xin, yout, xcd_remap,
+                                          begin, sc, st);
+    }
+    if (vec)
+        return spmv_items<P, false, true>(items, tab, n_tab, ptr, idx, val, xin, yout, xcd_remap,
+                                          begin, sc, st);
+    return spmv_items<P, false, false>(items, tab, n_tab, ptr, idx, val, xin, yout, xcd_remap,
+                                       begin, sc, st);
 }
 
 template <int P, int VAR, int KIND, bool ROOT>
@@ -862,12 +966,12 @@ hipError_t dot_t(const RangeBlock *tab, int32_t n_tab, const void *a, const void
     default: return hipErrorInvalidValue;                          \
     }
 
-hipError_t launch_spmv(int prec, int items, const SpmvBlock *tab, int32_t n_tab,
+hipError_t launch_spmv(int prec, int items, int vec, const SpmvBlock *tab, int32_t n_tab,
                        const int32_t *ptr, const int32_t *idx, const void *val, const void *xin,
                        void *yout, int xcd_remap, int sequential, int begin, Scalars *sc,
                        hipStream_t st)
 {
-    CFR_DISPATCH(prec, spmv_t<P>(items, tab, n_tab, ptr, idx, val, xin, yout, xcd_remap,
+    CFR_DISPATCH(prec, spmv_t<P>(items, vec, tab, n_tab, ptr, idx, val, xin, yout, xcd_remap,
                                  sequential, begin, sc, st));
 }
 

@@ -198,7 +198,8 @@ def test_tiling_and_tuner(cfr, mix):
     here exceeds the smallest block capacity)."""
     games = [g for _, g, _ in mix]
     out = []
-    for tiling in (None, {"items": [4, 8], "rows": [64, 128]}, "tune"):
+    for tiling in (None, {"items": [4, 8], "rows": [64, 128], "vec": [0, 1]},
+                   {"items": [16, 4], "rows": [256, 64], "vec": [1, 0]}, "tune"):
         b = make_batch(cfr, games, max_games=len(mix), precision="fp64")
         ids = [b.add(g, v) for _, g, v in mix]
         if tiling == "tune":
@@ -206,6 +207,7 @@ def test_tiling_and_tuner(cfr, mix):
             say(f"  tuner chose {chosen}")
             assert all(i in (4, 8, 16) for i in chosen["items"])
             assert all(64 <= r <= 256 for r in chosen["rows"])
+            assert all(v in (0, 1) for v in chosen["vec"])
         elif tiling is not None:
             b.tiling = tiling
             assert b.tiling == tiling
