@@ -380,8 +380,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default product tiling instead of running the autotuner")
     ap.add_argument("--tiling", default=None,
-                    help="fixed product tiling 'items_Ay,items_ATx:rows_Ay,rows_ATx:vec_Ay,vec_ATx' "
-                         "(skips the autotuner)")
+                    help="fixed product tiling 'items_Ay,items_ATx:rows_Ay,rows_ATx:vec_Ay,vec_ATx:"
+                         "perm_Ay,perm_ATx' (skips the autotuner)")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle time for the CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -451,7 +451,8 @@ def main():
         parts = args.tiling.split(":")
         s.tiling = {"items": [int(v) for v in parts[0].split(",")],
                     "rows": [int(v) for v in parts[1].split(",")],
-                    "vec": [int(v) for v in parts[2].split(",")] if len(parts) > 2 else [1, 1]}
+                    "vec": [int(v) for v in parts[2].split(",")] if len(parts) > 2 else [1, 1],
+                    "perm": [int(v) for v in parts[3].split(",")] if len(parts) > 3 else [0, 0]}
     elif not args.no_tune:
         t0 = time.perf_counter()
         s.tune(reps=10)

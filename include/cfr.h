@@ -89,6 +89,13 @@ enum { CFR_CURRENT = 0, CFR_AVERAGE = 1 };
  * CFR_FP64, PARALLEL otherwise.                                            */
 enum { CFR_SPMV_DEFAULT = 0, CFR_SPMV_SEQUENTIAL = 1, CFR_SPMV_PARALLEL = 2 };
 
+/* Top-down pass of NextStrategy.  DEFAULT: below level 0, one launch in
+ * which each sequence multiplies the behavioural strategies along its
+ * parent chain from the root down (the same products in the same order as
+ * the level-by-level pass, so identical results), when no chain is longer
+ * than 16; otherwise, and with LEVELS, one launch per level.             */
+enum { CFR_DOWN_DEFAULT = 0, CFR_DOWN_LEVELS = 1 };
+
 /* Averaging weight w_t.  DEFAULT: 1 (vanilla, PCFR), t (CFR+), t^gamma
  * (DCFR; the paper's quadratic weighting with gamma = 2), t^2 (PCFR+).   */
 enum { CFR_AVG_DEFAULT = 0, CFR_AVG_UNIFORM = 1, CFR_AVG_LINEAR = 2,
@@ -142,6 +149,7 @@ typedef struct cfr_options {
     size_t workspace_bytes;
     int use_graph;          /* 1: replay a captured HIP graph per iteration  */
     int spmv_order;         /* CFR_SPMV_*                                    */
+    int down_pass;          /* CFR_DOWN_*                                    */
 } cfr_options;
 
 typedef struct cfr_solver cfr_solver;
@@ -214,14 +222,20 @@ int cfr_kernel_stats(cfr_solver *s, int kernel, int64_t *launches, double *total
 
 /* Payoff-product tiling of the A y product (index 0) and of the A^T x
  * product (index 1): nonzeros per thread (4, 8 or 16; a block holds up to
- * 256 times that many less 3), rows per block (64..256), and vec (1: the
- * index and value streams are read with 16-byte loads, four elements per
- * lane; 0: one 4-byte load per element).  Rows longer than one block's
- * capacity are summed by a tree in every order.                           */
+ * 256 times that many less 3), rows per block (64..256), vec (1: the index
+ * and value streams are read with 16-byte loads, four elements per lane;
+ * 0: one 4-byte load per element) and perm (1: before the product, the
+ * gathered strategy is copied into the order in which the rows first use
+ * its entries, and the product gathers from that copy, so each row's
+ * gathers touch consecutive entries; the index stream is renumbered once
+ * when the flag changes).  Rows longer than one block's capacity are
+ * summed by a tree in every order; every other row keeps its summation
+ * order under every choice.                                              */
 typedef struct cfr_spmv_tiling {
     int items[2];
     int rows[2];
     int vec[2];
+    int perm[2];
 } cfr_spmv_tiling;
 
 /* Reads / sets the solver's tiling (CFR_EINVAL outside the ranges above).  */
@@ -273,6 +287,14 @@ typedef struct cfr_batch_options {
     void *stream;              /* hipStream_t; NULL = null stream                */
     int device;                /* HIP device ordinal                             */
     int use_graph;             /* 1: replay a captured graph per iteration       */
+    int down_pass;             /* CFR_DOWN_*                                     */
+    int async_admission;       /* 1: cfr_batch_add_prepared only enqueues its
+                                  copies (on a stream of its own) and returns;
+                                  the prepared game must then stay alive until
+                                  the game has run or been removed.  A game
+                                  added while others iterate joins at the
+                                  next check, so its copies overlap one check
+                                  period of the others.                     */
 } cfr_batch_options;
 
 typedef struct cfr_game_params {
@@ -316,10 +338,13 @@ int cfr_batch_add(cfr_batch *b, const cfr_game_desc *game, const cfr_game_params
 
 /* A game validated, laid out in level order and converted to one
  * precision's value type on the host, ready to be added to batches of that
- * precision: cfr_prepare touches no device and may run on worker threads
- * while a batch iterates (the serving path prepares arriving requests this
- * way, so that admission is only the copy to the device).  A prepared game
- * owns copies of everything it needs and may be added any number of times. */
+ * precision: cfr_prepare launches no device work and may run on worker
+ * threads while a batch iterates (the serving path prepares arriving
+ * requests this way, so that admission is only the copy to the device).
+ * Its index and value streams are held in page-locked host memory
+ * (hipHostMalloc; ordinary memory if that fails), so those copies are DMA
+ * transfers that do not hold up the host.  A prepared game owns copies of
+ * everything it needs and may be added any number of times.               */
 typedef struct cfr_prepared cfr_prepared;
 int cfr_prepare(const cfr_game_desc *game, int precision, cfr_prepared **out);
 /* Index units of a prepared game, as cfr_batch_game_size.                 */

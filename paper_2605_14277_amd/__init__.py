@@ -26,6 +26,7 @@ MODES = {"simultaneous": 0, "alternating": 1}
 KINDS = {"current": 0, "average": 1}
 AVG = {"default": 0, "uniform": 1, "linear": 2, "quadratic": 3, "pow_gamma": 4}
 SPMV_ORDER = {"default": 0, "sequential": 1, "parallel": 2}
+DOWN_PASS = {"default": 0, "levels": 1}
 GAME_STATES = {0: "active", 1: "waiting", 2: "done"}
 ERRORS = {CFR_EINVAL: "EINVAL", CFR_ENOMEM: "ENOMEM", CFR_EDEVICE: "EDEVICE",
           CFR_ESTATE: "ESTATE", CFR_EUNSUPPORTED: "EUNSUPPORTED"}
@@ -52,11 +53,12 @@ class cfr_options(C.Structure):
     _fields_ = [("precision", C.c_int), ("dcfr_alpha", C.c_double), ("dcfr_beta", C.c_double),
                 ("dcfr_gamma", C.c_double), ("avg_weight", C.c_int), ("stream", C.c_void_p),
                 ("device", C.c_int), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
-                ("use_graph", C.c_int), ("spmv_order", C.c_int)]
+                ("use_graph", C.c_int), ("spmv_order", C.c_int), ("down_pass", C.c_int)]
 
 
 class cfr_spmv_tiling(C.Structure):
-    _fields_ = [("items", C.c_int * 2), ("rows", C.c_int * 2), ("vec", C.c_int * 2)]
+    _fields_ = [("items", C.c_int * 2), ("rows", C.c_int * 2), ("vec", C.c_int * 2),
+                ("perm", C.c_int * 2)]
 
 
 class cfr_batch_options(C.Structure):
@@ -64,7 +66,7 @@ class cfr_batch_options(C.Structure):
                 ("max_games", C.c_int64), ("seq_capacity", C.c_int64 * 2),
                 ("inf_capacity", C.c_int64 * 2), ("nnz_capacity", C.c_int64),
                 ("check_every", C.c_int64), ("stream", C.c_void_p), ("device", C.c_int),
-                ("use_graph", C.c_int)]
+                ("use_graph", C.c_int), ("down_pass", C.c_int), ("async_admission", C.c_int)]
 
 
 class cfr_game_params(C.Structure):
@@ -257,7 +259,7 @@ def cfr_kernel_stats(h, kernel: int):
 
 def _tiling_dict(t: cfr_spmv_tiling) -> dict:
     return {"items": [int(t.items[0]), int(t.items[1])], "rows": [int(t.rows[0]), int(t.rows[1])],
-            "vec": [int(t.vec[0]), int(t.vec[1])]}
+            "vec": [int(t.vec[0]), int(t.vec[1])], "perm": [int(t.perm[0]), int(t.perm[1])]}
 
 
 def _tiling_struct(d: dict) -> cfr_spmv_tiling:
@@ -266,6 +268,7 @@ def _tiling_struct(d: dict) -> cfr_spmv_tiling:
         t.items[w] = int(d["items"][w])
         t.rows[w] = int(d["rows"][w])
         t.vec[w] = int(d.get("vec", [1, 1])[w])
+        t.perm[w] = int(d.get("perm", [0, 0])[w])
     return t
 
 
@@ -414,7 +417,7 @@ class Solver:
     def __init__(self, game, precision: str = "fp64", device: int = 0, alpha: float = 1.5,
                  beta: float = 0.0, gamma: float = 2.0, avg: str = "default",
                  use_graph: bool = True, stream=None, with_csc: bool = True,
-                 spmv_order: str = "default"):
+                 spmv_order: str = "default", down_pass: str = "default"):
         import torch
         self.torch = torch
         self.arrays = GameArrays(game, with_csc=with_csc)
@@ -426,6 +429,7 @@ class Solver:
         o.device = int(device)
         o.use_graph = int(bool(use_graph))
         o.spmv_order = SPMV_ORDER[spmv_order]
+        o.down_pass = DOWN_PASS[down_pass]
         dev = torch.device("cuda", int(device))
         if stream is None:
             stream = torch.cuda.current_stream(dev)
@@ -496,7 +500,8 @@ class Batch:
     def __init__(self, seq_capacity, inf_capacity, nnz_capacity: int, max_games: int = 256,
                  precision: str = "fp32_acc64", mode: str = "alternating",
                  check_every: int = 10, device: int = 0, use_graph: bool = True, stream=None,
-                 spmv_order: str = "default"):
+                 spmv_order: str = "default", down_pass: str = "default",
+                 async_admission: bool = False):
         import torch
         o = cfr_batch_options_default()
         o.precision = PRECISIONS[precision]
@@ -510,6 +515,8 @@ class Batch:
         o.check_every = int(check_every)
         o.device = int(device)
         o.use_graph = int(bool(use_graph))
+        o.down_pass = DOWN_PASS[down_pass]
+        o.async_admission = int(bool(async_admission))
         dev = torch.device("cuda", int(device))
         if stream is None:
             stream = torch.cuda.current_stream(dev)

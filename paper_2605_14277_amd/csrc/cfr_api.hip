@@ -146,6 +146,8 @@ int check_options(const cfr_options *o)
         return fail(CFR_EINVAL, "unknown averaging weight");
     if (o->spmv_order < CFR_SPMV_DEFAULT || o->spmv_order > CFR_SPMV_PARALLEL)
         return fail(CFR_EINVAL, "unknown summation order");
+    if (o->down_pass != CFR_DOWN_DEFAULT && o->down_pass != CFR_DOWN_LEVELS)
+        return fail(CFR_EINVAL, "unknown top-down pass");
     if (!std::isfinite(o->dcfr_alpha) || !std::isfinite(o->dcfr_beta) ||
         !std::isfinite(o->dcfr_gamma))
         return fail(CFR_EINVAL, "DCFR exponents must be finite");
@@ -175,6 +177,7 @@ int check_tiling(const cfr_spmv_tiling *t)
         if (t->rows[w] < 64 || t->rows[w] > cfr::kSpmvRowCap)
             return fail(CFR_EINVAL, "rows per block must be in [64, 256]");
         if (t->vec[w] != 0 && t->vec[w] != 1) return fail(CFR_EINVAL, "vec must be 0 or 1");
+        if (t->perm[w] != 0 && t->perm[w] != 1) return fail(CFR_EINVAL, "perm must be 0 or 1");
     }
     return CFR_OK;
 }
@@ -210,12 +213,17 @@ void get_tiling(const cfr::Engine &e, cfr_spmv_tiling *t)
         t->items[w] = e.items[w];
         t->rows[w] = e.rows[w];
         t->vec[w] = e.vec[w];
+        t->perm[w] = e.perm_on[w];
     }
 }
 
 int set_tiling(cfr::Engine &e, const cfr_spmv_tiling *t)
 {
-    for (int w = 0; w < 2; ++w) e.repartition(w, t->items[w], t->rows[w], t->vec[w]);
+    for (int w = 0; w < 2; ++w) {
+        int rc = e.set_perm(w, t->perm[w]);
+        if (rc) return rc;
+        e.repartition(w, t->items[w], t->rows[w], t->vec[w]);
+    }
     return CFR_OK;
 }
 
@@ -228,21 +236,28 @@ int tune(cfr::Engine &e, int reps, cfr_spmv_tiling *chosen)
     static const int kRows[] = {64, 128, 256};
     for (int w = 0; w < 2; ++w) {
         double best = -1;
-        int bi = e.items[w], br = e.rows[w], bv = e.vec[w];
-        for (int vec = 0; vec < 2; ++vec)
-            for (int items : kItems)
-                for (int rows : kRows) {
-                    e.repartition(w, items, rows, vec);
-                    double ms = 0;
-                    int rc = e.time_spmv(w, reps, &ms);
-                    if (rc) return rc;
-                    if (best < 0 || ms < best) {
-                        best = ms;
-                        bi = items;
-                        br = rows;
-                        bv = vec;
+        int bi = e.items[w], br = e.rows[w], bv = e.vec[w], bp = e.perm_on[w];
+        for (int perm = 0; perm < 2; ++perm) {
+            int rc = e.set_perm(w, perm);
+            if (rc) return rc;
+            for (int vec = 0; vec < 2; ++vec)
+                for (int items : kItems)
+                    for (int rows : kRows) {
+                        e.repartition(w, items, rows, vec);
+                        double ms = 0;
+                        rc = e.time_spmv(w, reps, &ms);
+                        if (rc) return rc;
+                        if (best < 0 || ms < best) {
+                            best = ms;
+                            bi = items;
+                            br = rows;
+                            bv = vec;
+                            bp = perm;
+                        }
                     }
-                }
+        }
+        int rc = e.set_perm(w, bp);
+        if (rc) return rc;
         e.repartition(w, bi, br, bv);
     }
     if (chosen) get_tiling(e, chosen);
@@ -298,7 +313,8 @@ struct cfr_solver {
 };
 
 struct cfr_prepared {
-    cfr::HostGame hg;
+    cfr::HostGame hg;  // plans and row pointers (the streams live in the image)
+    cfr::GameImage img;
     int precision = CFR_FP64;
     int64_t units[5] = {0, 0, 0, 0, 0};
 };
@@ -373,10 +389,13 @@ int cfr_create(const cfr_game_desc *game, const cfr_options *opt, cfr_solver **o
         cfr::Engine &e = s->eng;
         e.spmv_order = opt->spmv_order;
         e.use_graph = opt->use_graph != 0;
+        e.down_pass = opt->down_pass;
         e.lone = true;
         {
             cfr::HostGame hg;
             cfr::prepare_game(game, true, true, hg);
+            cfr::GameImage img;
+            cfr::build_image(hg, opt->precision, false, true, img);
             const cfr::Capacity c = cfr::lone_capacity(hg, e.items[0], e.rows[0], e.items[1],
                                                        e.rows[1]);
             rc = e.init(c, opt->precision, opt->device, (hipStream_t)opt->stream, opt->workspace,
@@ -389,7 +408,7 @@ int cfr_create(const cfr_game_desc *game, const cfr_options *opt, cfr_solver **o
                 gp.beta = opt->dcfr_beta;
                 gp.gamma = opt->dcfr_gamma;
                 int slot = -1;
-                rc = e.add(hg, gp, true, &slot);
+                rc = e.add(hg, img, gp, true, false, &slot);
             }
         }
         if (rc) {
@@ -619,6 +638,8 @@ static int batch_capacity(const cfr_batch_options *opt, cfr::Capacity &c)
             return fail(CFR_EINVAL, "index capacities out of range");
     if (opt->nnz_capacity < 0) return fail(CFR_EINVAL, "negative nonzero capacity");
     if (opt->check_every < 1) return fail(CFR_EINVAL, "check_every must be >= 1");
+    if (opt->down_pass != CFR_DOWN_DEFAULT && opt->down_pass != CFR_DOWN_LEVELS)
+        return fail(CFR_EINVAL, "unknown top-down pass");
     c.slots = opt->max_games;
     for (int p = 0; p < 2; ++p) {
         c.seq[p] = opt->seq_capacity[p];
@@ -655,6 +676,8 @@ int cfr_batch_create(const cfr_batch_options *opt, cfr_batch **out)
         cfr::Engine &e = b->eng;
         e.spmv_order = opt->spmv_order;
         e.use_graph = opt->use_graph != 0;
+        e.down_pass = opt->down_pass;
+        e.async_admission = opt->async_admission != 0;
         e.lone = false;
         e.mode = opt->mode;
         e.check_every = opt->check_every;
@@ -687,6 +710,8 @@ int cfr_batch_add(cfr_batch *b, const cfr_game_desc *game, const cfr_game_params
         DeviceGuard guard(b->eng.device);
         cfr::HostGame hg;
         cfr::prepare_game(game, false, true, hg);
+        cfr::GameImage img;
+        cfr::build_image(hg, b->eng.prec, false, true, img);
         cfr::GameParams p;
         p.variant = gp->variant;
         p.avg_kind = gp->avg_weight;
@@ -696,7 +721,7 @@ int cfr_batch_add(cfr_batch *b, const cfr_game_desc *game, const cfr_game_params
         p.target = gp->target_exploitability;
         p.max_it = gp->max_iterations;
         int slot = -1;
-        rc = b->eng.add(hg, p, b->eng.phase == 0, &slot);
+        rc = b->eng.add(hg, img, p, b->eng.phase == 0, false, &slot);
         if (rc) return rc;
         *id = b->eng.slots[(size_t)slot].id;
         return CFR_OK;
@@ -717,7 +742,13 @@ int cfr_prepare(const cfr_game_desc *game, int precision, cfr_prepared **out)
         p = new cfr_prepared();
         p->precision = precision;
         cfr::prepare_game(game, false, true, p->hg);
-        cfr::own_game(p->hg, precision);
+        cfr::build_image(p->hg, precision, true, false, p->img);
+        for (int w = 0; w < 2; ++w) {
+            std::vector<int32_t>().swap(p->hg.own_idx[w]);
+            std::vector<double>().swap(p->hg.own_val[w]);
+            p->hg.idx[w] = nullptr;
+            p->hg.val[w] = nullptr;
+        }
         for (int q = 0; q < 2; ++q) {
             p->units[q] = game->player[q].n_seq + 1;
             p->units[2 + q] = game->player[q].n_inf + 1;
@@ -758,7 +789,14 @@ int cfr_batch_add_prepared(cfr_batch *b, const cfr_prepared *p, const cfr_game_p
         q.target = gp->target_exploitability;
         q.max_it = gp->max_iterations;
         int slot = -1;
-        rc = b->eng.add(p->hg, q, b->eng.phase == 0, &slot);
+        cfr::Engine &e = b->eng;
+        if (e.async_admission) {
+            // copies overlap the iterations of the games already running
+            const bool idle = e.active_set().empty();
+            rc = e.add(p->hg, p->img, q, e.phase == 0 && idle, true, &slot);
+        } else {
+            rc = e.add(p->hg, p->img, q, e.phase == 0, false, &slot);
+        }
         if (rc) return rc;
         *id = b->eng.slots[(size_t)slot].id;
         return CFR_OK;

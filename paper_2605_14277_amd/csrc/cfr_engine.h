@@ -8,6 +8,7 @@
 
 #include <cstdint>
 #include <map>
+#include <memory>
 #include <string>
 #include <utility>
 #include <vector>
@@ -70,14 +71,36 @@ struct HostGame {
     const double *val[2] = {nullptr, nullptr};
     std::vector<int32_t> own_idx[2];
     std::vector<double> own_val[2];
-    std::vector<float> own_valf[2];  // values already in float (then val[] is unused)
 };
-// Makes a prepared game self-contained: copies any arrays still owned by
-// the caller and, for a float value type, converts the values once.
-void own_game(HostGame &hg, int prec);
 // lone: also group the shallow levels for the one-launch sweep (k_top).
 // with_matrix = false: plans and row pointers only (for sizing).
 void prepare_game(const cfr_game_desc *g, bool lone, bool with_matrix, HostGame &hg);
+
+// Everything an engine copies to the device for one game, with the game's
+// own (local) indices: per player the treeplex arrays, the value slots, the
+// first strategy and the first-touch order; per product the row pointers
+// and the index and value streams.  Admission copies it and shifts the
+// indices to the game's global positions on the device.  The arrays live in
+// one host buffer (page-locked when asked and possible, so the copies are
+// DMA transfers that never hold up the host); with `borrow`, the index and
+// FP64 value streams are read from the HostGame's arrays instead.
+struct GameImage {
+    int prec = CFR_FP64;
+    int64_t nnz = 0;
+    int32_t n_seq[2] = {0, 0}, n_inf[2] = {0, 0};
+    struct Player {
+        size_t inf_first, seq_par, child_ptr, child_idx, cslot, ccount, b0, x0, perm, pos;
+    } pl[2];
+    size_t ptr[2] = {0, 0}, idx[2] = {0, 0}, val[2] = {0, 0};
+    const int32_t *idx_src[2] = {nullptr, nullptr};  // index streams
+    const void *val_src[2] = {nullptr, nullptr};     // value streams in the value type
+    size_t bytes = 0;
+    bool locked = false;  // the buffer is page-locked
+    char *base = nullptr;
+    std::shared_ptr<void> pinned;
+    std::vector<char> plain;
+};
+void build_image(const HostGame &hg, int prec, bool pinned, bool borrow, GameImage &img);
 
 // Per-game constants of the regret minimiser and the stopping rule.
 struct GameParams {
@@ -96,6 +119,7 @@ struct Capacity {
     int64_t nnz = 0;
     int64_t t_csr = 0, t_csc = 0;               // product blocks
     int64_t t_up[2] = {0, 0}, t_down[2] = {0, 0}, t_seq[2] = {0, 0};  // range blocks
+    int64_t t_dall[2] = {0, 0};  // range blocks of the one-launch top-down pass
     int64_t top_off[2] = {0, 0}, top_list[2] = {0, 0};
 };
 // Exact capacity of one game alone (the single-game solver).
@@ -132,6 +156,12 @@ struct Slot {
     std::vector<int32_t> old_of_new[2];  // internal -> caller numbering
     std::vector<SpmvBlock> blocks[2];    // product blocks (global fields)
     double last[5] = {0, 0, 0, 0, 0};    // last evaluation: expl, NashConv, BR1, BR2, value
+    // asynchronous admission: host copies the uploads read, and the event
+    // that marks their completion on the upload stream
+    std::vector<std::vector<char>> staging;
+    hipEvent_t up_ev = nullptr;
+    bool up_waited = false;
+    int64_t join_after = 0;  // a waiting game joins at a check once `checks` reaches this
     int64_t last_t = -1;                 // iteration of that evaluation
     bool reached = false;
 };
@@ -141,9 +171,11 @@ struct Slot {
 struct Tables {
     SpmvBlock *csr = nullptr, *csc = nullptr;
     RangeBlock *up[2] = {nullptr, nullptr}, *down[2] = {nullptr, nullptr},
-               *seq[2] = {nullptr, nullptr};
+               *seq[2] = {nullptr, nullptr}, *dall[2] = {nullptr, nullptr};
     SlotRef *root[2] = {nullptr, nullptr}, *fin = nullptr;
     int32_t n_csr = 0, n_csc = 0, n_seq[2] = {0, 0}, n_root[2] = {0, 0}, n_fin = 0;
+    int32_t n_dall[2] = {0, 0};
+    int dall_depth[2] = {0, 0};  // levels of the deepest game (its longest parent chain)
     struct Up {
         int32_t off, n;
         int variant, kind;
@@ -154,7 +186,7 @@ struct Tables {
     // host copies of the last upload (kept until the next one: the copies
     // are asynchronous)
     std::vector<SpmvBlock> h_csr, h_csc;
-    std::vector<RangeBlock> h_up[2], h_down[2], h_seq[2];
+    std::vector<RangeBlock> h_up[2], h_down[2], h_seq[2], h_dall[2];
     std::vector<SlotRef> h_root[2], h_fin;
     double bytes[2] = {0, 0};  // algorithmic bytes of one product launch over these games
     bool valid = false;
@@ -176,12 +208,17 @@ struct Engine {
     int items[2] = {kSpmvItemsDefault, kSpmvItemsDefault};
     int rows[2] = {kSpmvRowCap, kSpmvRowCap};
     int vec[2] = {1, 1};  // 16-byte stream loads in the products
+    int perm_on[2] = {0, 0};  // the product gathers a first-touch-ordered copy
     int xcd_remap = 1;
     int device = 0;
     bool use_graph = true;
     bool lone = false;  // a single game: shallow levels may run as one launch
+    int down_pass = CFR_DOWN_DEFAULT;  // top-down pass: one launch, or one per level
     hipStream_t st = nullptr;
     hipStream_t cap_st = nullptr;  // private stream used only to capture graphs
+    hipStream_t up_st = nullptr;   // admission copies (asynchronous admission)
+    bool async_admission = false;  // cfr_batch_add_prepared returns before its copies finish
+    Scalars *scal_stage = nullptr;  // page-locked staging of each slot's first scalars
     Capacity cap;
     void *ws = nullptr;
     size_t ws_bytes = 0;
@@ -206,6 +243,7 @@ struct Engine {
     hipGraphExec_t gexec = nullptr;
     int64_t check_every = 0;  // 0: no checks (single-game solver)
     int64_t phase = 0;        // iterations since the last check
+    int64_t checks = 0;       // checks done so far
 
     // host-side time and calls per activity (kHost* below), for reports
     enum { kHostTables = 0, kHostGraph, kHostEval, kHostEnqueue, kHostAdd, kHostRemove, kHostN };
@@ -228,11 +266,21 @@ struct Engine {
     int sequential() const;
     // Uploads a prepared game into free ranges and puts it at the uniform
     // strategy; *slot_out receives its slot.  CFR_ENOMEM when it does not fit.
-    int add(const HostGame &hg, const GameParams &gp, bool join_now, int *slot_out);
+    // async: copies on the upload stream without waiting (the game's host
+    // arrays must outlive them: a prepared game's do).
+    int add(const HostGame &hg, const GameImage &img, const GameParams &gp, bool join_now,
+            bool async, int *slot_out);
     void remove(int slot);
+    // Makes the stream wait for the admission copies of these games.
+    hipError_t wait_uploads(const std::vector<int> &set);
+    // Frees the host copies of finished admissions (all of them with wait).
+    void reap_uploads(bool wait);
     int set_params(int slot, const GameParams &gp);  // writes the game's constants to the device
     // Re-partitions every game's product blocks for a new tiling.
     void repartition(int which, int items_, int rows_, int vec_);
+    // Switches a product to (or back from) gathering the first-touch-ordered
+    // copy of its input: remaps every game's index stream in place.
+    int set_perm(int which, int on);
     void partition(Slot &s, int which);
 
     std::vector<int> active_set() const;

@@ -245,7 +245,7 @@ struct Carver {
 
 // Offsets of the block tables inside one table region.
 struct TableLayout {
-    size_t csr, csc, up[2], down[2], seq[2], root[2], fin, bytes;
+    size_t csr, csc, up[2], down[2], seq[2], dall[2], root[2], fin, bytes;
 };
 
 TableLayout table_layout(const Capacity &c)
@@ -263,6 +263,8 @@ TableLayout table_layout(const Capacity &c)
         k.take(sizeof(RangeBlock) * (size_t)std::max<int64_t>(c.t_down[p], 1));
         L.seq[p] = (k.cur + 255) & ~(size_t)255;
         k.take(sizeof(RangeBlock) * (size_t)std::max<int64_t>(c.t_seq[p], 1));
+        L.dall[p] = (k.cur + 255) & ~(size_t)255;
+        k.take(sizeof(RangeBlock) * (size_t)std::max<int64_t>(c.t_dall[p], 1));
         L.root[p] = (k.cur + 255) & ~(size_t)255;
         k.take(sizeof(SlotRef) * (size_t)c.slots);
     }
@@ -304,6 +306,12 @@ Layout carve(Carver &k, const Capacity &c, int prec)
         d.g = k.take(V * n);
         d.xbar = k.take(V * n);
         d.vinf = k.take(C * ni);
+        d.perm = (int32_t *)k.take(4 * n);
+        d.pos = (int32_t *)k.take(4 * n);
+        d.xp = k.take(V * n);
+        d.cslot = (int32_t *)k.take(4 * ni);
+        d.ccount = (uint8_t *)k.take(n);
+        d.cval = k.take(C * 4 * n);
         d.top_off = (int32_t *)k.take(4 * (size_t)std::max<int64_t>(c.top_off[p], 1));
         d.top_list = (int32_t *)k.take(4 * (size_t)std::max<int64_t>(c.top_list[p], 1));
     }
@@ -349,27 +357,6 @@ hipError_t h2d(void *dst, const T *src, size_t count, hipStream_t st)
 {
     if (count == 0) return hipSuccess;
     return hipMemcpyAsync(dst, src, sizeof(T) * count, hipMemcpyHostToDevice, st);
-}
-
-// Copies `count` doubles to the value type at dst (converting in chunks).
-hipError_t h2d_values(void *dst, const double *src, size_t count, int prec, hipStream_t st)
-{
-    if (count == 0) return hipSuccess;
-    if (value_bytes(prec) == 8) {
-        hipError_t e = h2d(dst, src, count, st);
-        if (e != hipSuccess) return e;
-        return hipStreamSynchronize(st);
-    }
-    const size_t kChunk = (size_t)1 << 24;
-    std::vector<float> tmp(std::min(count, kChunk));
-    for (size_t at = 0; at < count; at += kChunk) {
-        const size_t n = std::min(kChunk, count - at);
-        for (size_t i = 0; i < n; ++i) tmp[i] = (float)src[at + i];
-        hipError_t e = h2d((float *)dst + at, tmp.data(), n, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);  // tmp is reused
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
 }
 
 }  // namespace
@@ -439,22 +426,128 @@ void prepare_game(const cfr_game_desc *g, bool lone, bool with_matrix, HostGame 
     }
 }
 
-void own_game(HostGame &hg, int prec)
+// Page-locked host buffer freed with hipHostFree, or null.
+static std::shared_ptr<void> pinned_buffer(size_t bytes)
 {
+    void *p = nullptr;
+    if (bytes == 0 || hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return std::shared_ptr<void>(p, [](void *q) { (void)hipHostFree(q); });
+}
+
+void build_image(const HostGame &hg, int prec, bool pinned, bool borrow, GameImage &img)
+{
+    const size_t V = value_bytes(prec);
+    const size_t nnz = (size_t)hg.nnz;
+    img.prec = prec;
+    img.nnz = hg.nnz;
+    size_t cur = 0;
+    auto take = [&](size_t bytes) {
+        cur = (cur + 255) & ~(size_t)255;
+        const size_t at = cur;
+        cur += bytes;
+        return at;
+    };
+    for (int p = 0; p < 2; ++p) {
+        const size_t n = (size_t)hg.pl[p].n_seq, ni = (size_t)hg.pl[p].n_inf;
+        img.n_seq[p] = hg.pl[p].n_seq;
+        img.n_inf[p] = hg.pl[p].n_inf;
+        GameImage::Player &q = img.pl[p];
+        q.inf_first = take(4 * (ni + 1));
+        q.seq_par = take(4 * (n + 1));
+        q.child_ptr = take(4 * (n + 1));
+        q.child_idx = take(4 * ni);
+        q.cslot = take(4 * ni);
+        q.ccount = take(n + 1);
+        q.b0 = take(V * (n + 1));
+        q.x0 = take(V * (n + 1));
+        q.perm = take(4 * (n + 1));
+        q.pos = take(4 * (n + 1));
+    }
+    const bool copy_idx = !borrow, copy_val = !borrow || V == 4;
     for (int w = 0; w < 2; ++w) {
-        const size_t n = (size_t)hg.nnz;
-        if (hg.own_idx[w].empty() && n > 0) {
-            hg.own_idx[w].assign(hg.idx[w], hg.idx[w] + n);
-            hg.idx[w] = hg.own_idx[w].data();
+        img.ptr[w] = take(4 * hg.ptr[w].size());
+        img.idx[w] = copy_idx ? take(4 * nnz) : 0;
+        img.val[w] = copy_val ? take(V * nnz) : 0;
+    }
+    img.bytes = (cur + 255) & ~(size_t)255;
+    img.pinned = pinned ? pinned_buffer(img.bytes) : nullptr;
+    img.locked = img.pinned != nullptr;
+    if (img.locked) {
+        img.base = (char *)img.pinned.get();
+    } else {
+        img.plain.assign(img.bytes, 0);
+        img.base = img.plain.data();
+    }
+    char *B = img.base;
+    for (int p = 0; p < 2; ++p) {
+        const PlayerPlan &pl = hg.pl[p];
+        const GameImage::Player &q = img.pl[p];
+        const size_t n = (size_t)pl.n_seq, ni = (size_t)pl.n_inf;
+        std::memcpy(B + q.inf_first, pl.inf_first.data(), 4 * (ni + 1));
+        int32_t *sp = (int32_t *)(B + q.seq_par);
+        std::memcpy(sp, pl.seq_par.data(), 4 * n);
+        sp[n] = 0;  // the sentinel's parent: the empty sequence
+        std::memcpy(B + q.child_ptr, pl.child_ptr.data(), 4 * (n + 1));
+        if (ni) std::memcpy(B + q.child_idx, pl.child_idx.data(), 4 * ni);
+        // value slots: the decision points below a sequence with at most
+        // kFastKids of them, in ascending order (local 4 * sequence + rank)
+        int32_t *cs = (int32_t *)(B + q.cslot);
+        uint8_t *cc = (uint8_t *)(B + q.ccount);
+        for (size_t j = 0; j < ni; ++j) cs[j] = -1;
+        for (size_t a = 0; a < n; ++a) {
+            const int32_t c0 = pl.child_ptr[a], cnt = pl.child_ptr[a + 1] - c0;
+            cc[a] = (uint8_t)std::min(cnt, 255);
+            if (cnt > kFastKids) continue;
+            for (int32_t k = 0; k < cnt; ++k)
+                cs[(size_t)pl.child_idx[(size_t)(c0 + k)]] = 4 * (int32_t)a + k;
         }
-        if (value_bytes(prec) == 4) {
-            hg.own_valf[w].resize(n);
-            for (size_t i = 0; i < n; ++i) hg.own_valf[w][i] = (float)hg.val[w][i];
-            std::vector<double>().swap(hg.own_val[w]);
-            hg.val[w] = nullptr;
-        } else if (hg.own_val[w].empty() && n > 0) {
-            hg.own_val[w].assign(hg.val[w], hg.val[w] + n);
-            hg.val[w] = hg.own_val[w].data();
+        cc[n] = 0;
+        std::vector<char> hb, hx;
+        initial_strategy(prec, pl, hb, hx);
+        std::memcpy(B + q.b0, hb.data(), hb.size());
+        std::memcpy(B + q.x0, hx.data(), hx.size());
+    }
+    // first-touch order of each player's sequences in the product that
+    // gathers them (rows in order, columns ascending)
+    for (int w = 0; w < 2; ++w) {
+        const int q = 1 - w;
+        const int32_t n = hg.pl[q].n_seq;
+        int32_t *perm = (int32_t *)(B + img.pl[q].perm);
+        int32_t *pos = (int32_t *)(B + img.pl[q].pos);
+        std::vector<char> seen((size_t)n, 0);
+        int32_t next = 0;
+        for (size_t i = 0; i < nnz; ++i) {
+            const int32_t c = hg.idx[w][i];
+            if (!seen[(size_t)c]) {
+                seen[(size_t)c] = 1;
+                perm[next++] = c;
+            }
+        }
+        for (int32_t c = 0; c < n; ++c)
+            if (!seen[(size_t)c]) perm[next++] = c;
+        perm[n] = n;  // the sentinel maps to itself
+        for (int32_t j = 0; j <= n; ++j) pos[perm[j]] = j;
+    }
+    for (int w = 0; w < 2; ++w) {
+        std::memcpy(B + img.ptr[w], hg.ptr[w].data(), 4 * hg.ptr[w].size());
+        if (copy_idx) {
+            if (nnz) std::memcpy(B + img.idx[w], hg.idx[w], 4 * nnz);
+            img.idx_src[w] = (const int32_t *)(B + img.idx[w]);
+        } else {
+            img.idx_src[w] = hg.idx[w];
+        }
+        if (V == 4) {
+            float *f = (float *)(B + img.val[w]);
+            for (size_t i = 0; i < nnz; ++i) f[i] = (float)hg.val[w][i];
+            img.val_src[w] = f;
+        } else if (copy_val) {
+            if (nnz) std::memcpy(B + img.val[w], hg.val[w], 8 * nnz);
+            img.val_src[w] = B + img.val[w];
+        } else {
+            img.val_src[w] = hg.val[w];
         }
     }
 }
@@ -475,6 +568,7 @@ Capacity lone_capacity(const HostGame &hg, int items_csr, int rows_csr, int item
             if (lv > 0) c.t_down[p] += chunks(pl.lvl_seq[lv + 1] - pl.lvl_seq[lv]);
         }
         c.t_seq[p] = chunks(pl.n_seq);
+        c.t_dall[p] = pl.n_levels > 1 ? chunks(pl.n_seq - pl.lvl_seq[1]) : 0;
         c.top_off[p] = (int64_t)pl.top_off.size();
         c.top_list[p] = (int64_t)pl.top_list.size();
     }
@@ -507,6 +601,7 @@ void bound_tables(Capacity &c)
         c.t_up[p] = c.inf[p] / kRangeBlock + c.inf[p] + 1;
         c.t_down[p] = c.seq[p] / kRangeBlock + c.inf[p] + 1;
         c.t_seq[p] = c.seq[p] / kRangeBlock + c.slots + 1;
+        c.t_dall[p] = c.seq[p] / kRangeBlock + c.slots + 1;
         c.top_off[p] = 0;
         c.top_list[p] = 0;
     }
@@ -588,6 +683,9 @@ int64_t RangeAlloc::largest() const
 int Engine::init(const Capacity &c, int precision, int dev, hipStream_t stream, void *workspace,
                  size_t workspace_bytes)
 {
+    // value slots are addressed as 4 * sequence in int32
+    if (c.seq[0] > (int64_t)1 << 29 || c.seq[1] > (int64_t)1 << 29)
+        return fail(CFR_EINVAL, "more than 2^29 sequences per player");
     cap = c;
     prec = precision;
     device = dev;
@@ -633,6 +731,7 @@ int Engine::init(const Capacity &c, int precision, int dev, hipStream_t stream, 
             t.up[p] = (RangeBlock *)(base + T.up[p]);
             t.down[p] = (RangeBlock *)(base + T.down[p]);
             t.seq[p] = (RangeBlock *)(base + T.seq[p]);
+            t.dall[p] = (RangeBlock *)(base + T.dall[p]);
             t.root[p] = (SlotRef *)(base + T.root[p]);
         }
         t.fin = (SlotRef *)(base + T.fin);
@@ -645,6 +744,17 @@ int Engine::init(const Capacity &c, int precision, int dev, hipStream_t stream, 
         e = hipMemsetAsync(dp[p].child_idx, 0, 4 * (size_t)std::max<int64_t>(c.inf[p], 1), st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return device_error("workspace initialisation", e);
+    e = hipStreamCreateWithFlags(&up_st, hipStreamNonBlocking);
+    if (e != hipSuccess) return device_error("upload stream", e);
+    {
+        void *p = nullptr;
+        if (hipHostMalloc(&p, sizeof(Scalars) * (size_t)c.slots, hipHostMallocDefault) ==
+                hipSuccess &&
+            p)
+            scal_stage = (Scalars *)p;
+        else
+            (void)hipGetLastError();
+    }
     for (int p = 0; p < 2; ++p) {
         seq_alloc[p].init(c.seq[p]);
         inf_alloc[p].init(c.inf[p]);
@@ -672,8 +782,13 @@ void Engine::release()
         events[k].clear();
     }
     drop_graph();
+    reap_uploads(true);
     if (cap_st) (void)hipStreamDestroy(cap_st);
     cap_st = nullptr;
+    if (up_st) (void)hipStreamDestroy(up_st);
+    up_st = nullptr;
+    if (scal_stage) (void)hipHostFree(scal_stage);
+    scal_stage = nullptr;
     if (own_ws && ws) (void)hipFree(ws);
     ws = nullptr;
 }
@@ -720,6 +835,24 @@ void Engine::partition(Slot &s, int which)
     }
 }
 
+int Engine::set_perm(int which, int on)
+{
+    on = on ? 1 : 0;
+    if (perm_on[which] == on) return CFR_OK;
+    reap_uploads(true);  // the index streams of games still being copied
+    const int q = 1 - which;
+    for (Slot &s : slots) {
+        if (!s.live || s.nnz == 0) continue;
+        hipError_t e = launch_remap(idx[which] + s.nb, s.nnz, on ? dp[q].pos : dp[q].perm, st);
+        if (e != hipSuccess) return device_error("index remap", e);
+    }
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return device_error("index remap", e);
+    perm_on[which] = on;
+    drop_graph();
+    return CFR_OK;
+}
+
 void Engine::repartition(int which, int items_, int rows_, int vec_)
 {
     items[which] = items_;
@@ -751,7 +884,8 @@ int Engine::set_params(int k, const GameParams &gp)
     return CFR_OK;
 }
 
-int Engine::add(const HostGame &hg, const GameParams &gp, bool join_now, int *slot_out)
+int Engine::add(const HostGame &hg, const GameImage &img, const GameParams &gp, bool join_now,
+                bool async, int *slot_out)
 {
     HostTimer timer(&host_s[kHostAdd], &host_n[kHostAdd]);
     int k = -1;
@@ -788,14 +922,25 @@ int Engine::add(const HostGame &hg, const GameParams &gp, bool join_now, int *sl
     s.gp = gp;
     s.nb = nb;
     s.nnz = hg.nnz;
+    // Asynchronous admission copies the game's image on the upload stream
+    // and returns; the image must outlive the copies (a prepared game owns
+    // its own).  Indices are shifted to the game's global positions on the
+    // device.
+    const hipStream_t ups = async ? up_st : st;
+    const char *B = img.base;
     hipError_t e = hipSuccess;
 #define CHECK(x)                                                 \
     do {                                                         \
         e = (x);                                                 \
         if (e != hipSuccess) return device_error("add game", e); \
     } while (0)
+    auto cp = [&](void *dst, const void *src, size_t bytes) {
+        return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, ups) : hipSuccess;
+    };
+    const size_t R = accum_bytes(prec), V = value_bytes(prec);
     for (int p = 0; p < 2; ++p) {
         const PlayerPlan &pl = hg.pl[p];
+        const GameImage::Player &q = img.pl[p];
         s.sb[p] = sb[p];
         s.ib[p] = ib[p];
         s.n_seq[p] = pl.n_seq;
@@ -807,59 +952,51 @@ int Engine::add(const HostGame &hg, const GameParams &gp, bool join_now, int *sl
         s.old_of_new[p] = pl.old_of_new;
         const int32_t S = (int32_t)sb[p], I = (int32_t)ib[p];
         const size_t n = (size_t)pl.n_seq, ni = (size_t)pl.n_inf;
-        std::vector<int32_t> v(n + 1);
-        for (size_t i = 0; i <= ni; ++i) v[i] = pl.inf_first[i] + S;
-        CHECK(h2d(dp[p].inf_first + I, v.data(), ni + 1, st));
-        CHECK(hipStreamSynchronize(st));
-        for (size_t i = 0; i < n; ++i) v[i] = pl.seq_par[i] + S;
-        v[n] = S;
-        CHECK(h2d(dp[p].seq_par + S, v.data(), n + 1, st));
-        CHECK(hipStreamSynchronize(st));
-        for (size_t i = 0; i <= n; ++i) v[i] = pl.child_ptr[i] + I;
-        CHECK(h2d(dp[p].child_ptr + S, v.data(), n + 1, st));
-        CHECK(hipStreamSynchronize(st));
-        for (size_t i = 0; i < ni; ++i) v[i] = pl.child_idx[i] + I;
-        CHECK(h2d(dp[p].child_idx + I, v.data(), ni, st));
-        CHECK(hipStreamSynchronize(st));
+        DevPlayer &d = dp[p];
+        CHECK(cp(d.inf_first + I, B + q.inf_first, 4 * (ni + 1)));
+        CHECK(launch_add_offset(d.inf_first + I, (int64_t)ni + 1, S, ups));
+        CHECK(cp(d.seq_par + S, B + q.seq_par, 4 * (n + 1)));
+        CHECK(launch_add_offset(d.seq_par + S, (int64_t)n + 1, S, ups));
+        CHECK(cp(d.child_ptr + S, B + q.child_ptr, 4 * (n + 1)));
+        CHECK(launch_add_offset(d.child_ptr + S, (int64_t)n + 1, I, ups));
+        CHECK(cp(d.child_idx + I, B + q.child_idx, 4 * ni));
+        CHECK(launch_add_offset(d.child_idx + I, (int64_t)ni, I, ups));
+        CHECK(cp(d.cslot + I, B + q.cslot, 4 * ni));
+        CHECK(launch_add_offset_nonneg(d.cslot + I, (int64_t)ni, 4 * S, ups));
+        CHECK(cp(d.ccount + S, B + q.ccount, n + 1));
+        CHECK(cp((char *)d.b + V * (size_t)S, B + q.b0, V * (n + 1)));
+        CHECK(cp((char *)d.x + V * (size_t)S, B + q.x0, V * (n + 1)));
+        CHECK(cp(d.perm + S, B + q.perm, 4 * (n + 1)));
+        CHECK(launch_add_offset(d.perm + S, (int64_t)n + 1, S, ups));
+        CHECK(cp(d.pos + S, B + q.pos, 4 * (n + 1)));
+        CHECK(launch_add_offset(d.pos + S, (int64_t)n + 1, S, ups));
+        // state: zero regrets, predictions and averages
+        CHECK(hipMemsetAsync((char *)d.r + R * (size_t)S, 0, R * (n + 1), ups));
+        CHECK(hipMemsetAsync((char *)d.m + R * (size_t)S, 0, R * (n + 1), ups));
+        CHECK(hipMemsetAsync((char *)d.s + R * (size_t)S, 0, R * (n + 1), ups));
         if (lone) {
-            CHECK(h2d(dp[p].top_off, pl.top_off.data(), pl.top_off.size(), st));
-            CHECK(h2d(dp[p].top_list, pl.top_list.data(), pl.top_list.size(), st));
-            dp[p].top_levels = pl.top_levels;
-            dp[p].n_roots = pl.n_roots;
-            dp[p].top_fast = 1;
-            for (int32_t lv = 0; lv < pl.top_levels; ++lv) dp[p].top_fast &= pl.lvl_kind[lv] != 0;
+            CHECK(h2d(d.top_off, pl.top_off.data(), pl.top_off.size(), ups));
+            CHECK(h2d(d.top_list, pl.top_list.data(), pl.top_list.size(), ups));
+            d.top_levels = pl.top_levels;
+            d.n_roots = pl.n_roots;
+            d.top_fast = 1;
+            for (int32_t lv = 0; lv < pl.top_levels; ++lv) d.top_fast &= pl.lvl_kind[lv] != 0;
         }
-        // state: zero regrets, predictions and averages; uniform strategy
-        const size_t R = accum_bytes(prec), V = value_bytes(prec);
-        CHECK(hipMemsetAsync((char *)dp[p].r + R * (size_t)S, 0, R * (n + 1), st));
-        CHECK(hipMemsetAsync((char *)dp[p].m + R * (size_t)S, 0, R * (n + 1), st));
-        CHECK(hipMemsetAsync((char *)dp[p].s + R * (size_t)S, 0, R * (n + 1), st));
-        std::vector<char> hb, hx;
-        initial_strategy(prec, pl, hb, hx);
-        CHECK(hipMemcpyAsync((char *)dp[p].b + V * (size_t)S, hb.data(), hb.size(),
-                             hipMemcpyHostToDevice, st));
-        CHECK(hipMemcpyAsync((char *)dp[p].x + V * (size_t)S, hx.data(), hx.size(),
-                             hipMemcpyHostToDevice, st));
-        CHECK(hipStreamSynchronize(st));
     }
     // payoff matrix: row pointers at the row player's sequences, indices
-    // shifted to the column player's global sequences
+    // shifted to the column player's global sequences (then renumbered to
+    // first-touch order when the product gathers a permuted copy)
     for (int w = 0; w < 2; ++w) {
         s.ptr[w] = hg.ptr[w];
-        CHECK(h2d(ptr[w] + sb[w], hg.ptr[w].data(), hg.ptr[w].size(), st));
-        CHECK(h2d(idx[w] + nb, hg.idx[w], (size_t)hg.nnz, st));
+        CHECK(cp(ptr[w] + sb[w], B + img.ptr[w], 4 * hg.ptr[w].size()));
+        CHECK(cp(idx[w] + nb, img.idx_src[w], 4 * (size_t)hg.nnz));
         const int32_t col_base = (int32_t)sb[1 - w];
-        if (col_base != 0) CHECK(launch_add_offset(idx[w] + nb, hg.nnz, col_base, st));
-        CHECK(hipStreamSynchronize(st));
-        if (!hg.own_valf[w].empty() && value_bytes(prec) == 4) {
-            CHECK(h2d((float *)val[w] + nb, hg.own_valf[w].data(), (size_t)hg.nnz, st));
-            CHECK(hipStreamSynchronize(st));
-        } else {
-            CHECK(h2d_values((char *)val[w] + value_bytes(prec) * (size_t)nb, hg.val[w],
-                             (size_t)hg.nnz, prec, st));
-        }
+        if (col_base != 0) CHECK(launch_add_offset(idx[w] + nb, hg.nnz, col_base, ups));
+        if (perm_on[w]) CHECK(launch_remap(idx[w] + nb, hg.nnz, dp[1 - w].pos, ups));
+        CHECK(cp((char *)val[w] + V * (size_t)nb, img.val_src[w], V * (size_t)hg.nnz));
     }
-    // the game's scalars: t = 0, its constants
+    // the game's scalars: t = 0, its constants (from page-locked staging
+    // when there is some)
     {
         Scalars h{};
         h.alpha = gp.alpha;
@@ -867,8 +1004,24 @@ int Engine::add(const HostGame &hg, const GameParams &gp, bool join_now, int *sl
         h.gamma = gp.gamma;
         h.variant = gp.variant;
         h.avg_kind = gp.avg_kind;
-        CHECK(hipMemcpyAsync(sc + k, &h, sizeof h, hipMemcpyHostToDevice, st));
-        CHECK(hipStreamSynchronize(st));
+        const void *src = &h;
+        if (scal_stage) {
+            scal_stage[k] = h;
+            src = &scal_stage[k];
+        } else {
+            std::vector<char> b(sizeof h);
+            std::memcpy(b.data(), &h, sizeof h);
+            s.staging.push_back(std::move(b));
+            src = s.staging.back().data();
+        }
+        CHECK(cp(sc + k, src, sizeof h));
+    }
+    if (async) {
+        CHECK(hipEventCreateWithFlags(&s.up_ev, hipEventDisableTiming));
+        CHECK(hipEventRecord(s.up_ev, ups));
+    } else {
+        CHECK(hipStreamSynchronize(ups));
+        s.staging.clear();
     }
 #undef CHECK
     s.live = true;
@@ -876,6 +1029,9 @@ int Engine::add(const HostGame &hg, const GameParams &gp, bool join_now, int *sl
     partition(s, 1);
     s.active = join_now;
     s.pending = !join_now;
+    // a game admitted asynchronously while others iterate joins one check
+    // later, so that its copies overlap that check period
+    s.join_after = checks + (async && !join_now ? 1 : 0);
     if (join_now) {
         it.valid = false;
         drop_graph();
@@ -884,11 +1040,41 @@ int Engine::add(const HostGame &hg, const GameParams &gp, bool join_now, int *sl
     return CFR_OK;
 }
 
+hipError_t Engine::wait_uploads(const std::vector<int> &set)
+{
+    for (int k : set) {
+        Slot &s = slots[(size_t)k];
+        if (s.up_ev && !s.up_waited) {
+            hipError_t e = hipStreamWaitEvent(st, s.up_ev, 0);
+            if (e != hipSuccess) return e;
+            s.up_waited = true;
+        }
+    }
+    return hipSuccess;
+}
+
+void Engine::reap_uploads(bool wait)
+{
+    for (Slot &s : slots) {
+        if (!s.up_ev) continue;
+        if (!wait && hipEventQuery(s.up_ev) != hipSuccess) continue;
+        if (wait) (void)hipEventSynchronize(s.up_ev);
+        (void)hipEventDestroy(s.up_ev);
+        s.up_ev = nullptr;
+        s.staging.clear();
+    }
+}
+
 void Engine::remove(int k)
 {
     HostTimer timer(&host_s[kHostRemove], &host_n[kHostRemove]);
     Slot &s = slots[(size_t)k];
     if (!s.live) return;
+    if (s.up_ev) {
+        (void)hipEventSynchronize(s.up_ev);
+        (void)hipEventDestroy(s.up_ev);
+        s.up_ev = nullptr;
+    }
     for (int p = 0; p < 2; ++p) {
         seq_alloc[p].give(s.sb[p], (int64_t)s.n_seq[p] + 1);
         inf_alloc[p].give(s.ib[p], (int64_t)s.n_inf[p] + 1);
@@ -936,13 +1122,14 @@ bool Engine::tables_in_bounds(const Tables &T) const
                 r.hi > s.ib[p] + s.n_inf[p])
                 return false;
         }
-        for (const std::vector<RangeBlock> *v : {&T.h_down[p], &T.h_seq[p]})
+        for (const std::vector<RangeBlock> *v : {&T.h_down[p], &T.h_seq[p], &T.h_dall[p]})
             for (const RangeBlock &r : *v) {
                 if (!live(r.slot)) return false;
                 const Slot &s = slots[(size_t)r.slot];
                 if (r.hi - r.lo < 1 || r.hi - r.lo > kRangeBlock || r.lo < s.sb[p] ||
                     r.hi > s.sb[p] + s.n_seq[p])
                     return false;
+                if (v != &T.h_down[p] && r.aux != s.sb[p]) return false;
             }
         for (const SlotRef &r : T.h_root[p]) {
             if (!live(r.slot)) return false;
@@ -991,7 +1178,9 @@ int Engine::build_tables(Tables &T, char *region, const std::vector<int> &set)
         T.h_up[p].clear();
         T.h_down[p].clear();
         T.h_seq[p].clear();
+        T.h_dall[p].clear();
         T.h_root[p].clear();
+        T.dall_depth[p] = maxL;
         T.up_l[p].assign((size_t)maxL, {});
         T.up_level[p].assign((size_t)maxL, {0, 0});
         T.down_l[p].assign((size_t)maxL, {0, 0});
@@ -1026,6 +1215,9 @@ int Engine::build_tables(Tables &T, char *region, const std::vector<int> &set)
             const Slot &s = slots[(size_t)k];
             const int32_t first = (int32_t)T.h_seq[p].size();
             push_chunks(T.h_seq[p], s.sb[p], s.sb[p] + s.n_seq[p], k, (int32_t)s.sb[p]);
+            if (s.n_levels[p] > 1)
+                push_chunks(T.h_dall[p], s.sb[p] + s.lvl_seq[p][1], s.sb[p] + s.n_seq[p], k,
+                            (int32_t)s.sb[p]);
             if (p == 0) T.h_fin.push_back(SlotRef{k, 0, first, (int32_t)T.h_seq[p].size()});
             const int32_t j0 = s.n_levels[p] > 0 ? s.lvl_inf[p][0] : 0;
             const int32_t j1 = s.n_levels[p] > 0 ? s.lvl_inf[p][1] : 0;
@@ -1033,9 +1225,10 @@ int Engine::build_tables(Tables &T, char *region, const std::vector<int> &set)
                 SlotRef{k, (int32_t)s.sb[p], (int32_t)(s.ib[p] + j0), (int32_t)(s.ib[p] + j1)});
         }
         if ((int64_t)T.h_up[p].size() > cap.t_up[p] || (int64_t)T.h_down[p].size() > cap.t_down[p] ||
-            (int64_t)T.h_seq[p].size() > cap.t_seq[p])
+            (int64_t)T.h_seq[p].size() > cap.t_seq[p] || (int64_t)T.h_dall[p].size() > cap.t_dall[p])
             return fail(CFR_EINVAL, "internal: sweep tables exceed their capacity");
         T.n_seq[p] = (int32_t)T.h_seq[p].size();
+        T.n_dall[p] = (int32_t)T.h_dall[p].size();
         T.n_root[p] = (int32_t)T.h_root[p].size();
     }
     if ((int64_t)T.h_csr.size() > cap.t_csr || (int64_t)T.h_csc.size() > cap.t_csc)
@@ -1050,6 +1243,7 @@ int Engine::build_tables(Tables &T, char *region, const std::vector<int> &set)
         e = h2d(T.up[p], T.h_up[p].data(), T.h_up[p].size(), st);
         if (e == hipSuccess) e = h2d(T.down[p], T.h_down[p].data(), T.h_down[p].size(), st);
         if (e == hipSuccess) e = h2d(T.seq[p], T.h_seq[p].data(), T.h_seq[p].size(), st);
+        if (e == hipSuccess) e = h2d(T.dall[p], T.h_dall[p].data(), T.h_dall[p].size(), st);
         if (e == hipSuccess) e = h2d(T.root[p], T.h_root[p].data(), T.h_root[p].size(), st);
     }
     if (e == hipSuccess) e = h2d(T.fin, T.h_fin.data(), T.h_fin.size(), st);
@@ -1062,7 +1256,10 @@ int Engine::build_tables(Tables &T, char *region, const std::vector<int> &set)
 int Engine::rebuild()
 {
     drop_graph();
-    int rc = build_tables(it, tab_region[0], active_set());
+    const std::vector<int> act = active_set();
+    hipError_t e = wait_uploads(act);
+    if (e != hipSuccess) return device_error("admission copies", e);
+    int rc = build_tables(it, tab_region[0], act);
     if (rc) it.valid = false;
     return rc;
 }
@@ -1072,6 +1269,13 @@ hipError_t Engine::spmv(const Tables &T, int which, const void *xin, void *yout,
 {
     const SpmvBlock *tab = which == 0 ? T.csr : T.csc;
     const int32_t n = which == 0 ? T.n_csr : T.n_csc;
+    if (perm_on[which]) {
+        // the product reads the gathered player's vector in first-touch order
+        const int q = 1 - which;
+        hipError_t e = launch_gather(prec, T.seq[q], T.n_seq[q], dp[q].perm, xin, dp[q].xp, s);
+        if (e != hipSuccess) return e;
+        xin = dp[q].xp;
+    }
     if (timed) {
         hipEvent_t a, b;
         hipError_t e = hipEventCreate(&a);
@@ -1109,6 +1313,8 @@ hipError_t Engine::sweeps(const Tables &T, int p, double usign, hipStream_t s)
         // the shallow levels of the lone game, both directions, one launch
         if ((e = launch_top(prec, slots[0].gp.variant, d, usign, 1, sc, s)) != hipSuccess) return e;
     }
+    if (!top && down_pass == CFR_DOWN_DEFAULT && T.dall_depth[p] <= kDownAllMaxDepth)
+        return launch_down_all(prec, T.dall_depth[p], T.dall[p], T.n_dall[p], d, 1, sc, s);
     for (int L = std::max(low, 1); L < maxL; ++L) {
         const auto &dl = T.down_l[p][(size_t)L];
         if ((e = launch_down(prec, T.down[p] + dl.first, dl.second, d, 1, sc, s)) != hipSuccess)
@@ -1207,6 +1413,8 @@ int Engine::evaluate(const std::vector<int> &set, int kind)
         e = (x);                                                     \
         if (e != hipSuccess) return device_error("evaluation", e);   \
     } while (0)
+    e = wait_uploads(set);
+    if (e != hipSuccess) return device_error("admission copies", e);
     const void *src[2] = {dp[0].x, dp[1].x};
     if (kind == CFR_AVERAGE) {
         for (int p = 0; p < 2; ++p) {
@@ -1231,6 +1439,7 @@ int Engine::evaluate(const std::vector<int> &set, int kind)
 #undef CHECK
     int rc = sync("evaluation");
     if (rc) return rc;
+    reap_uploads(false);
     for (int k : set) {
         Slot &s = slots[(size_t)k];
         const double br1 = h[(size_t)k].out[0], br2 = h[(size_t)k].out[1];
@@ -1249,10 +1458,12 @@ int Engine::run(int64_t n)
     int64_t done = 0;
     while (done < n) {
         if (phase == 0) {
-            // games admitted since the last check join now
+            // games admitted since the last check join now (or, admitted
+            // asynchronously, once their copies had a check period)
             bool joined = false;
+            const bool idle = active_set().empty();
             for (Slot &s : slots)
-                if (s.live && s.pending) {
+                if (s.live && s.pending && (idle || s.join_after <= checks)) {
                     s.pending = false;
                     s.active = true;
                     joined = true;
@@ -1273,6 +1484,7 @@ int Engine::run(int64_t n)
         phase += chunk;
         if (phase < check_every) continue;
         phase = 0;
+        ++checks;
         rc = evaluate(act, CFR_AVERAGE);
         if (rc) return rc;
         bool changed = false;
@@ -1331,7 +1543,9 @@ int Engine::fetch_vector(int k, int player, int what, std::vector<double> &out)
     const void *src = what == 0 ? dp[player].x : what == 1 ? dp[player].s : dp[player].r;
     std::vector<char> h(n * el);
     Scalars hs{};
-    hipError_t e = hipMemcpyAsync(h.data(), (const char *)src + el * (size_t)S, n * el,
+    hipError_t e = wait_uploads({k});
+    if (e != hipSuccess) return device_error("admission copies", e);
+    e = hipMemcpyAsync(h.data(), (const char *)src + el * (size_t)S, n * el,
                                   hipMemcpyDeviceToHost, st);
     if (e == hipSuccess && what == 1)
         e = hipMemcpyAsync(&hs, sc + k, sizeof hs, hipMemcpyDeviceToHost, st);

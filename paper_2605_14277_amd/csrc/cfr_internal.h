@@ -74,6 +74,18 @@ struct DevPlayer {
     void *g = nullptr;             // value type
     void *xbar = nullptr;          // value type
     void *vinf = nullptr;          // [decision points] compute type
+    // first-touch order of this player's sequences in the product that
+    // gathers them: perm[j] = sequence at permuted position j, pos its
+    // inverse (global indices), xp the permuted copy the product reads
+    int32_t *perm = nullptr;
+    int32_t *pos = nullptr;
+    void *xp = nullptr;            // value type
+    // values of the decision points below each sequence in slots of four:
+    // a decision point whose parent sequence has at most kFastKids of them
+    // stores its value at cval[cslot[j]] = 4 * parent + rank (else -1)
+    int32_t *cslot = nullptr;      // [decision points]
+    uint8_t *ccount = nullptr;     // [sequences] decision points below (<= kFastKids when used)
+    void *cval = nullptr;          // [4 * sequences] compute type
     // shallow levels 0 .. top_levels-1 of a lone game in one launch (k_top),
     // one block per root decision point (n_roots of them)
     int32_t top_levels = 0;
@@ -106,6 +118,11 @@ hipError_t launch_up(int prec, int variant, int kind, int root, const RangeBlock
 // Top-down pass over the sequences of `tab` (one level).
 hipError_t launch_down(int prec, const RangeBlock *tab, int32_t n_tab, const DevPlayer &p,
                        int average, const Scalars *sc, hipStream_t st);
+// Top-down pass over every level below level 0 in one launch: each sequence
+// of `tab` (aux = its game's empty sequence) multiplies the behavioural
+// strategies of its at most max_depth (<= kDownAllMaxDepth) ancestors.
+hipError_t launch_down_all(int prec, int max_depth, const RangeBlock *tab, int32_t n_tab,
+                           const DevPlayer &p, int average, const Scalars *sc, hipStream_t st);
 // ObserveUtility on levels top_levels-1..0, then the top-down pass on levels
 // 0..top_levels-1 (with averaging when `average`) of the game in slot 0.
 hipError_t launch_top(int prec, int variant, const DevPlayer &p, double usign, int average,
@@ -125,8 +142,14 @@ hipError_t launch_root_value(int prec, const SlotRef *tab, int32_t n_tab, const 
 hipError_t launch_dot(int prec, const RangeBlock *tab, int32_t n_tab, const void *a,
                       const void *b, double *partials, const SlotRef *fin, int32_t n_fin,
                       Scalars *sc, int out_index, hipStream_t st);
-// a[i] += base for i < n.
+// a[i] += base for i < n (only where a[i] >= 0 for the second form).
 hipError_t launch_add_offset(int32_t *a, int64_t n, int32_t base, hipStream_t st);
+hipError_t launch_add_offset_nonneg(int32_t *a, int64_t n, int32_t base, hipStream_t st);
+// dst[i] = src[perm[i]] over the sequences of `tab` (value type).
+hipError_t launch_gather(int prec, const RangeBlock *tab, int32_t n_tab, const int32_t *perm,
+                         const void *src, void *dst, hipStream_t st);
+// a[i] = map[a[i]] for i < n.
+hipError_t launch_remap(int32_t *a, int64_t n, const int32_t *map, hipStream_t st);
 
 size_t value_bytes(int prec);
 size_t accum_bytes(int prec);
@@ -160,6 +183,7 @@ constexpr int kRangeBlock = 256;  // decision points or sequences per sweep bloc
 #ifndef CFR_TOP_PARTIAL
 #define CFR_TOP_PARTIAL 0
 #endif
+constexpr int kDownAllMaxDepth = 16;  // longest parent chain of the one-launch top-down pass
 constexpr int kFastActs = 4;        // fast sweep path: actions per decision point
 constexpr int kFastKids = 4;        // fast sweep path: decision points below a sequence
 constexpr int kTopThreads = 1024;   // threads of the shallow-level block

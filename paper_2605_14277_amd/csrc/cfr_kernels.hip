@@ -334,6 +334,23 @@ __device__ __forceinline__ typename Types<P>::C post_step(typename Types<P>::C r
     return r;
 }
 
+// Values of the decision points below each sequence, in slots: a decision
+// point whose parent sequence has at most kFastKids of them also stores its
+// value at cval[4 * parent + (its rank among them)], so the parent's level
+// reads them with its own action data instead of through child_idx.
+template <int P>
+struct Kids {
+    const int32_t *__restrict__ cslot;   // [decision points] slot, or -1
+    const uint8_t *__restrict__ ccount;  // [sequences] decision points below (if <= kFastKids)
+    typename Types<P>::C *__restrict__ cval;  // [4 * sequences]
+};
+
+template <int P>
+__device__ __forceinline__ void store_value(const Kids<P> &kd, int32_t cs, typename Types<P>::C v)
+{
+    if (cs >= 0) kd.cval[cs] = v;
+}
+
 // One decision point of ObserveUtility: counterfactual utilities of its
 // actions (own utility plus the values of the decision points below), its
 // value, the regret update with the variant's post-step, and regret
@@ -344,7 +361,8 @@ __device__ __forceinline__ void up_infoset(
     const int32_t *__restrict__ child_idx, const typename Types<P>::V *__restrict__ g,
     typename Types<P>::C usign, typename Types<P>::C *__restrict__ vinf,
     typename Types<P>::V *__restrict__ b, typename Types<P>::R *__restrict__ r,
-    typename Types<P>::R *__restrict__ m, typename Types<P>::C dpos, typename Types<P>::C dneg)
+    typename Types<P>::R *__restrict__ m, typename Types<P>::C dpos, typename Types<P>::C dneg,
+    const Kids<P> &kd)
 {
     using V = typename Types<P>::V;
     using R = typename Types<P>::R;
@@ -352,6 +370,7 @@ __device__ __forceinline__ void up_infoset(
     constexpr bool kPred = VAR == CFR_PCFR_PLUS || VAR == CFR_PCFR;
     const int32_t a0 = inf_first[j], a1 = inf_first[j + 1];
     const int32_t n = a1 - a0;
+    const int32_t cs = kd.cslot[j];
 
     auto cf_utility = [&](int32_t a) -> C {
         C acc = usign * (C)g[a];
@@ -371,6 +390,7 @@ __device__ __forceinline__ void up_infoset(
             }
         }
         vinf[j] = V_;
+        store_value(kd, cs, V_);
         C z[kMaxActs];
         C Z = 0;
 #pragma unroll
@@ -401,6 +421,7 @@ __device__ __forceinline__ void up_infoset(
     C V_ = 0;
     for (int32_t a = a0; a < a1; ++a) V_ = V_ + (C)b[a] * cf_utility(a);
     vinf[j] = V_;
+    store_value(kd, cs, V_);
     C Z = 0;
     for (int32_t a = a0; a < a1; ++a) {
         C inst = cf_utility(a) - V_;
@@ -424,29 +445,32 @@ __device__ __forceinline__ void up_infoset(
 // Fast path of up_infoset for a decision point with at most kFastActs
 // actions, each with at most kFastKids decision points below it.  Every
 // load is issued unconditionally (lanes past the end read a valid clamped
-// address and ignore the value), so one dependent round trip serves all
-// actions and children at once: offsets -> action data and child
-// pointers -> child ids -> child values.  The arithmetic and its order are
-// exactly those of up_infoset.
+// address and ignore the value), so two dependent rounds serve everything:
+// action range and own slot, then action data with the child counts and
+// child values (from the slots).  The arithmetic and its order are exactly
+// those of up_infoset (children in ascending order).
 template <int P, int VAR, int NC>
 __device__ __forceinline__ void up_infoset_fast(
-    int32_t j, const int32_t *__restrict__ inf_first, const int32_t *__restrict__ child_ptr,
-    const int32_t *__restrict__ child_idx, const typename Types<P>::V *__restrict__ g,
+    int32_t j, const int32_t *__restrict__ inf_first, const typename Types<P>::V *__restrict__ g,
     typename Types<P>::C usign, typename Types<P>::C *__restrict__ vinf,
     typename Types<P>::V *__restrict__ b, typename Types<P>::R *__restrict__ r,
-    typename Types<P>::R *__restrict__ m, typename Types<P>::C dpos, typename Types<P>::C dneg)
+    typename Types<P>::R *__restrict__ m, typename Types<P>::C dpos, typename Types<P>::C dneg,
+    const Kids<P> &kd)
 {
     using V = typename Types<P>::V;
     using R = typename Types<P>::R;
     using C = typename Types<P>::C;
     // NC = 0: a level without children below it (no child loads at all)
     constexpr int NA = kFastActs, NCA = NC > 0 ? NC : 1;
+    static_assert(NC == 0 || NC == 4, "child values are read as slots of four");
     constexpr bool kPred = VAR == CFR_PCFR_PLUS || VAR == CFR_PCFR;
     const int32_t a0 = inf_first[j], a1 = inf_first[j + 1];
+    const int32_t cs = kd.cslot[j];
     const int32_t n = a1 - a0;
     V gv[NA], bv[NA];
     R rv[NA], mv[NA];
-    int32_t c0[NA], c1[NA];
+    int cnt[NA];
+    C cv[NA][NCA];
 #pragma unroll
     for (int k = 0; k < NA; ++k) {
         const int32_t a = a0 + (k < n ? k : 0);
@@ -455,23 +479,12 @@ __device__ __forceinline__ void up_infoset_fast(
         rv[k] = r[a];
         if (kPred) mv[k] = m[a];
         if (NC > 0) {
-            c0[k] = child_ptr[a];
-            c1[k] = child_ptr[a + 1];
+            cnt[k] = kd.ccount[a];
+#pragma unroll
+            for (int i = 0; i < NC; ++i) cv[k][i] = kd.cval[4 * (int64_t)a + i];
         } else {
-            c0[k] = c1[k] = 0;
+            cnt[k] = 0;
         }
-    }
-    int32_t cid[NA][NCA];
-    C cv[NA][NCA];
-    if (NC > 0) {
-#pragma unroll
-        for (int k = 0; k < NA; ++k)
-#pragma unroll
-            for (int i = 0; i < NC; ++i) cid[k][i] = child_idx[c0[k] + i < c1[k] ? c0[k] + i : 0];
-#pragma unroll
-        for (int k = 0; k < NA; ++k)
-#pragma unroll
-            for (int i = 0; i < NC; ++i) cv[k][i] = vinf[cid[k][i]];
     }
     C q[NA];
     C V_ = 0;
@@ -481,12 +494,13 @@ __device__ __forceinline__ void up_infoset_fast(
             C acc = usign * (C)gv[k];
 #pragma unroll
             for (int i = 0; i < NC; ++i)
-                if (c0[k] + i < c1[k]) acc = acc + cv[k][i];
+                if (i < cnt[k]) acc = acc + cv[k][i];
             q[k] = acc;
             V_ = V_ + (C)bv[k] * acc;
         }
     }
     vinf[j] = V_;
+    store_value(kd, cs, V_);
     C z[NA];
     C Z = 0;
 #pragma unroll
@@ -566,7 +580,7 @@ __global__ __launch_bounds__(kThreads) void k_up(
     typename Types<P>::C *__restrict__ vinf, typename Types<P>::V *__restrict__ b,
     typename Types<P>::R *__restrict__ r, typename Types<P>::R *__restrict__ m,
     const Scalars *__restrict__ sc, const int32_t *__restrict__ seq_par,
-    typename Types<P>::V *__restrict__ x, typename Types<P>::R *__restrict__ s)
+    typename Types<P>::V *__restrict__ x, typename Types<P>::R *__restrict__ s, Kids<P> kd)
 {
     using R = typename Types<P>::R;
     using C = typename Types<P>::C;
@@ -580,14 +594,12 @@ __global__ __launch_bounds__(kThreads) void k_up(
         dneg = (C)gs->dneg;
     }
     if (KIND == 1)
-        up_infoset_fast<P, VAR, kFastKids>(j, inf_first, child_ptr, child_idx, g, usign, vinf, b,
-                                           r, m, dpos, dneg);
+        up_infoset_fast<P, VAR, kFastKids>(j, inf_first, g, usign, vinf, b, r, m, dpos, dneg, kd);
     else if (KIND == 2)
-        up_infoset_fast<P, VAR, 0>(j, inf_first, child_ptr, child_idx, g, usign, vinf, b, r, m,
-                                   dpos, dneg);
+        up_infoset_fast<P, VAR, 0>(j, inf_first, g, usign, vinf, b, r, m, dpos, dneg, kd);
     else
         up_infoset<P, VAR>(j, inf_first, child_ptr, child_idx, g, usign, vinf, b, r, m, dpos,
-                           dneg);
+                           dneg, kd);
     if (ROOT) down_infoset<P>(j, inf_first, seq_par, b, x, s, (R)gs->w, 1);
 }
 
@@ -608,7 +620,7 @@ __global__ __launch_bounds__(kTopThreads) void k_top(
     typename Types<P>::V *__restrict__ b, typename Types<P>::R *__restrict__ r,
     typename Types<P>::R *__restrict__ m, typename Types<P>::V *__restrict__ x,
     typename Types<P>::R *__restrict__ s, const Scalars *__restrict__ sc, int average,
-    int all_fast)
+    int all_fast, Kids<P> kd)
 {
     using R = typename Types<P>::R;
     using C = typename Types<P>::C;
@@ -623,11 +635,11 @@ __global__ __launch_bounds__(kTopThreads) void k_top(
         const int32_t *off = top_off + (size_t)lv * (n_roots + 1);
         for (int32_t i = off[root] + (int32_t)threadIdx.x; i < off[root + 1]; i += kTopThreads) {
             if (all_fast)
-                up_infoset_fast<P, VAR, kFastKids>(top_list[i], inf_first, child_ptr, child_idx, g,
-                                                   usign, vinf, b, r, m, dpos, dneg);
+                up_infoset_fast<P, VAR, kFastKids>(top_list[i], inf_first, g, usign, vinf, b, r,
+                                                   m, dpos, dneg, kd);
             else
                 up_infoset<P, VAR>(top_list[i], inf_first, child_ptr, child_idx, g, usign, vinf,
-                                   b, r, m, dpos, dneg);
+                                   b, r, m, dpos, dneg, kd);
         }
         __syncthreads();
     }
@@ -660,6 +672,49 @@ __global__ __launch_bounds__(kThreads) void k_down(const RangeBlock *__restrict_
         s[i] = s[i] + w * (R)x[i];
     }
     x[i] = x[seq_par[i]] * b[i];
+}
+
+// The whole top-down pass below level 0 in one launch: each sequence walks
+// its parent chain up to the game's empty sequence (aux), collecting the
+// behavioural strategies on the way, then multiplies them from the root
+// down: x = ((1 * b_0) * b_1) ... * b_own, the same products in the same
+// order as the level-by-level pass, so the result is bit for bit the same.
+// It reads only b and the parent links, which the bottom-up pass has
+// finished, never another thread's x.  MAXD bounds the chain length.
+template <int P, int MAXD>
+__global__ __launch_bounds__(kThreads) void k_down_all(const RangeBlock *__restrict__ tab,
+                                                       const int32_t *__restrict__ seq_par,
+                                                       const typename Types<P>::V *__restrict__ b,
+                                                       typename Types<P>::V *__restrict__ x,
+                                                       typename Types<P>::R *__restrict__ s,
+                                                       const Scalars *__restrict__ sc, int average)
+{
+    using V = typename Types<P>::V;
+    using R = typename Types<P>::R;
+    const RangeBlock rb = tab[blockIdx.x];
+    const int32_t i = rb.lo + (int32_t)threadIdx.x;
+    if (i >= rb.hi) return;
+    const int32_t root = rb.aux;
+    V chain[MAXD];
+    int d = 0;
+    int32_t q = i;
+#pragma unroll
+    for (int k = 0; k < MAXD; ++k) {
+        if (q != root) {
+            chain[k] = b[q];
+            q = seq_par[q];
+            d = k + 1;
+        }
+    }
+    V xv = (V)1;
+#pragma unroll
+    for (int k = MAXD - 1; k >= 0; --k)
+        if (k < d) xv = xv * chain[k];
+    if (average) {
+        R w = (R)sc[rb.slot].w;
+        s[i] = s[i] + w * (R)x[i];
+    }
+    x[i] = xv;
 }
 
 // ---------------------------------------------------------------------------
@@ -768,9 +823,42 @@ __global__ __launch_bounds__(kThreads) void k_add_offset(int32_t *a, int64_t n, 
     if (i < n) a[i] += base;
 }
 
+__global__ __launch_bounds__(kThreads) void k_add_offset_nonneg(int32_t *a, int64_t n,
+                                                                int32_t base)
+{
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n && a[i] >= 0) a[i] += base;
+}
+
+// The permuted copy of a strategy vector that a product gathers from.
+template <int P>
+__global__ __launch_bounds__(kThreads) void k_gather(const RangeBlock *__restrict__ tab,
+                                                     const int32_t *__restrict__ perm,
+                                                     const typename Types<P>::V *__restrict__ src,
+                                                     typename Types<P>::V *__restrict__ dst)
+{
+    const RangeBlock rb = tab[blockIdx.x];
+    const int32_t i = rb.lo + (int32_t)threadIdx.x;
+    if (i >= rb.hi) return;
+    dst[i] = src[perm[i]];
+}
+
+__global__ __launch_bounds__(kThreads) void k_remap(int32_t *a, int64_t n,
+                                                    const int32_t *__restrict__ map)
+{
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) a[i] = map[a[i]];
+}
+
 // ---------------------------------------------------------------------------
 // Launch helpers
 // ---------------------------------------------------------------------------
+
+template <int P>
+Kids<P> kids(const DevPlayer &p)
+{
+    return Kids<P>{p.cslot, p.ccount, (typename Types<P>::C *)p.cval};
+}
 
 template <int P, bool SEQ, int ITEMS, bool VEC>
 hipError_t spmv_launch(const SpmvBlock *tab, int32_t n_tab, const int32_t *ptr, const int32_t *idx,
@@ -833,7 +921,7 @@ hipError_t up_launch(const RangeBlock *tab, int32_t n_tab, const DevPlayer &p, d
                        tab, p.inf_first, p.child_ptr, p.child_idx, (const typename T::V *)p.g,
                        (typename T::C)usign, (typename T::C *)p.vinf, (typename T::V *)p.b,
                        (typename T::R *)p.r, (typename T::R *)p.m, sc, p.seq_par,
-                       (typename T::V *)p.x, (typename T::R *)p.s);
+                       (typename T::V *)p.x, (typename T::R *)p.s, kids<P>(p));
     return hipGetLastError();
 }
 
@@ -876,7 +964,7 @@ hipError_t top_t(const DevPlayer &p, double usign, int average, const Scalars *s
                        p.seq_par, (const typename T::V *)p.g, (typename T::C)usign,
                        (typename T::C *)p.vinf, (typename T::V *)p.b, (typename T::R *)p.r,
                        (typename T::R *)p.m, (typename T::V *)p.x, (typename T::R *)p.s, sc,
-                       average, p.top_fast);
+                       average, p.top_fast, kids<P>(p));
     return hipGetLastError();
 }
 
@@ -903,6 +991,25 @@ hipError_t down_t(const RangeBlock *tab, int32_t n_tab, const DevPlayer &p, int 
     hipLaunchKernelGGL((k_down<P>), dim3((unsigned)n_tab), dim3(kThreads), 0, st, tab, p.seq_par,
                        (const typename T::V *)p.b, (typename T::V *)p.x, (typename T::R *)p.s, sc,
                        average);
+    return hipGetLastError();
+}
+
+template <int P>
+hipError_t down_all_t(int maxd, const RangeBlock *tab, int32_t n_tab, const DevPlayer &p,
+                      int average, const Scalars *sc, hipStream_t st)
+{
+    using T = Types<P>;
+    if (n_tab <= 0) return hipSuccess;
+    if (maxd <= 8)
+        hipLaunchKernelGGL((k_down_all<P, 8>), dim3((unsigned)n_tab), dim3(kThreads), 0, st, tab,
+                           p.seq_par, (const typename T::V *)p.b, (typename T::V *)p.x,
+                           (typename T::R *)p.s, sc, average);
+    else if (maxd <= kDownAllMaxDepth)
+        hipLaunchKernelGGL((k_down_all<P, kDownAllMaxDepth>), dim3((unsigned)n_tab),
+                           dim3(kThreads), 0, st, tab, p.seq_par, (const typename T::V *)p.b,
+                           (typename T::V *)p.x, (typename T::R *)p.s, sc, average);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -994,6 +1101,12 @@ hipError_t launch_down(int prec, const RangeBlock *tab, int32_t n_tab, const Dev
     CFR_DISPATCH(prec, down_t<P>(tab, n_tab, p, average, sc, st));
 }
 
+hipError_t launch_down_all(int prec, int max_depth, const RangeBlock *tab, int32_t n_tab,
+                           const DevPlayer &p, int average, const Scalars *sc, hipStream_t st)
+{
+    CFR_DISPATCH(prec, down_all_t<P>(max_depth, tab, n_tab, p, average, sc, st));
+}
+
 hipError_t launch_normalize(int prec, const RangeBlock *tab, int32_t n_tab, const DevPlayer &p,
                             const Scalars *sc, hipStream_t st)
 {
@@ -1017,6 +1130,39 @@ hipError_t launch_dot(int prec, const RangeBlock *tab, int32_t n_tab, const void
                       Scalars *sc, int out_index, hipStream_t st)
 {
     CFR_DISPATCH(prec, dot_t<P>(tab, n_tab, a, b, partials, fin, n_fin, sc, out_index, st));
+}
+
+template <int P>
+hipError_t gather_t(const RangeBlock *tab, int32_t n_tab, const int32_t *perm, const void *src,
+                    void *dst, hipStream_t st)
+{
+    using V = typename Types<P>::V;
+    if (n_tab <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_gather<P>), dim3((unsigned)n_tab), dim3(kThreads), 0, st, tab, perm,
+                       (const V *)src, (V *)dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(int prec, const RangeBlock *tab, int32_t n_tab, const int32_t *perm,
+                         const void *src, void *dst, hipStream_t st)
+{
+    CFR_DISPATCH(prec, gather_t<P>(tab, n_tab, perm, src, dst, st));
+}
+
+hipError_t launch_remap(int32_t *a, int64_t n, const int32_t *map, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_remap, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0,
+                       st, a, n, map);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_offset_nonneg(int32_t *a, int64_t n, int32_t base, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_add_offset_nonneg, dim3((unsigned)((n + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, st, a, n, base);
+    return hipGetLastError();
 }
 
 hipError_t launch_add_offset(int32_t *a, int64_t n, int32_t base, hipStream_t st)

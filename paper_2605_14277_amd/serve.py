@@ -109,10 +109,12 @@ class Server:
 
     def __init__(self, seq_capacity, inf_capacity, nnz_capacity, max_games: int = 256,
                  precision: str = "fp32_acc64", check_every: int = 10, workers: int = 8,
-                 device: int = 0):
+                 device: int = 0, async_admission: bool = True):
+        # asynchronous admission: a request's copies to the device overlap
+        # the iterations of the requests already running
         self.batch = Batch(seq_capacity, inf_capacity, nnz_capacity, max_games=max_games,
                            precision=precision, mode="alternating", check_every=check_every,
-                           device=device)
+                           device=device, async_admission=async_admission)
         self.precision = precision
         self.check_every = check_every
         self.workers = workers
@@ -161,7 +163,8 @@ class Server:
                             break
                         raise
                     waiting.popleft()
-                    inflight[gid] = (k, clock() - t0)
+                    # the prepared game stays referenced while its copies may run
+                    inflight[gid] = (k, clock() - t0, prep)
                 if inflight:
                     self.batch.run(self.check_every)
                     now = clock() - t0
@@ -169,7 +172,7 @@ class Server:
                         st = self.batch.status(gid)
                         if st["state"] != "done":
                             continue
-                        k, admitted = inflight.pop(gid)
+                        k, admitted, _ = inflight.pop(gid)
                         rec = {"arrival": requests[k]["arrival"], "admitted": admitted,
                                "finished": now, "latency": now - requests[k]["arrival"],
                                "iterations": st["iterations"], "expl": st["expl"],

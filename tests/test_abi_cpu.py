@@ -236,3 +236,24 @@ def test_null_batch_calls(cfr):
     assert lib.cfr_batch_destroy(None) == cfr.CFR_OK
     lib.cfr_tune.argtypes = [C.c_void_p, C.c_int, C.c_void_p]
     assert lib.cfr_tune(None, 3, None) == cfr.CFR_EINVAL
+
+
+def test_prepare_without_device(cfr, games):
+    """cfr_prepare is host work only: it runs (and sizes the game) with no
+    device, keeping its streams in ordinary memory when none can be locked."""
+    from paper_2605_14277_amd import serve
+    g = games["stops"]
+    for prec in ("fp64", "fp32_acc64"):
+        p = serve.Prepared(g, prec)
+        assert list(p.units) == list(cfr.cfr_batch_game_size(cfr.GameArrays(g)))
+        p.close()
+    import copy
+    g2 = copy.copy(games["cfg1"])
+    g2.col_idx = np.array(g2.col_idx, dtype=np.int32, copy=True)
+    g2.col_idx[0] = 10**6
+    bad = cfr.GameArrays(g2)
+    with pytest.raises(cfr.CfrError) as ei:
+        h = C.c_void_p()
+        rc = cfr._lib.cfr_prepare(C.byref(bad.desc), 0, C.byref(h))
+        cfr._check(rc, "cfr_prepare")
+    assert ei.value.code == cfr.CFR_EINVAL

@@ -198,8 +198,9 @@ def test_tiling_and_tuner(cfr, mix):
     here exceeds the smallest block capacity)."""
     games = [g for _, g, _ in mix]
     out = []
-    for tiling in (None, {"items": [4, 8], "rows": [64, 128], "vec": [0, 1]},
-                   {"items": [16, 4], "rows": [256, 64], "vec": [1, 0]}, "tune"):
+    for tiling in (None, {"items": [4, 8], "rows": [64, 128], "vec": [0, 1], "perm": [1, 0]},
+                   {"items": [16, 4], "rows": [256, 64], "vec": [1, 0], "perm": [0, 1]},
+                   {"items": [8, 8], "rows": [128, 128], "vec": [1, 1], "perm": [1, 1]}, "tune"):
         b = make_batch(cfr, games, max_games=len(mix), precision="fp64")
         ids = [b.add(g, v) for _, g, v in mix]
         if tiling == "tune":
@@ -208,6 +209,7 @@ def test_tiling_and_tuner(cfr, mix):
             assert all(i in (4, 8, 16) for i in chosen["items"])
             assert all(64 <= r <= 256 for r in chosen["rows"])
             assert all(v in (0, 1) for v in chosen["vec"])
+            assert all(v in (0, 1) for v in chosen["perm"])
         elif tiling is not None:
             b.tiling = tiling
             assert b.tiling == tiling
@@ -232,3 +234,52 @@ def test_single_solver_tune(cfr, oracle_mod):
         assert rel_inf(s.strategy(p, "average"), orc.strategy(p, "average")) <= 1e-9
     s.close()
     orc.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_acc64", "fp32"])
+def test_chain_top_down_pass_equals_level_by_level(cfr, mix, precision):
+    """The one-launch top-down pass multiplies each sequence's parent chain
+    from the root down, the same products in the same order as one launch
+    per level: identical strategies, averages and regrets."""
+    for name, g, variant in mix:
+        out = []
+        for down in ("default", "levels"):
+            s = cfr.Solver(g, precision=precision, down_pass=down)
+            s.step(40, variant, "alternating")
+            out.append([s.strategy(p, k) for p in range(2) for k in ("current", "average")] +
+                       [s.regrets(p) for p in range(2)])
+            s.close()
+        for a, b in zip(*out):
+            assert np.array_equal(a, b), (name, precision)
+
+
+def test_asynchronous_admission(cfr, mix):
+    """Admission copies run on their own stream: a game added while others
+    iterate joins at the next check, one added to an idle batch at once, and
+    every game still equals the same game solved alone."""
+    from paper_2605_14277_amd import serve
+    pool = {name: (g, v) for name, g, v in mix}
+    names = ("cfg1", "stops", "s2d3", "cfg2_d8")
+    preps = {n: serve.Prepared(pool[n][0], "fp64") for n in names}
+    units = np.sum([preps[n].units for n in names], axis=0)
+    b = cfr.Batch([units[0], units[1]], [units[2], units[3]], int(units[4]), max_games=4,
+                  precision="fp64", check_every=10, async_admission=True)
+    g1 = serve.add_prepared(b, preps["cfg1"], pool["cfg1"][1])
+    assert b.status(g1)["state"] == "active"  # idle batch: joins at once
+    b.run(20)
+    g2 = serve.add_prepared(b, preps["stops"], pool["stops"][1])
+    g3 = serve.add_prepared(b, preps["cfg2_d8"], pool["cfg2_d8"][1])
+    assert b.status(g2)["state"] == "waiting"
+    b.run(10)  # the copies overlap this period; g2 and g3 join at its check
+    assert b.status(g2)["iterations"] == 0
+    b.run(30)
+    expect = {g1: ("cfg1", 60), g2: ("stops", 30), g3: ("cfg2_d8", 30)}
+    for gid, (name, iters) in expect.items():
+        assert b.status(gid)["iterations"] == iters, (name, b.status(gid))
+        g, variant = pool[name]
+        solo = lone(cfr, g, variant, "alternating", iters, "fp64")
+        assert_same(b, gid, solo, name)
+        solo.close()
+    b.close()
+    for p in preps.values():
+        p.close()
