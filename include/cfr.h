@@ -220,6 +220,18 @@ int cfr_kernel_timing(cfr_solver *s, int enable);
 int cfr_kernel_stats(cfr_solver *s, int kernel, int64_t *launches, double *total_ms,
                      double *bytes_per_launch);
 
+/* Checkpointing.  The state of a solver — iteration counter, averaging
+ * weights, and per player the cumulative regrets, predictions, average
+ * accumulators and current behavioural and sequence-form strategies — as
+ * an opaque byte image: cfr_state_size gives its length, cfr_get_state
+ * writes it to a host buffer (waits for the stream), cfr_set_state loads
+ * it into a solver created from the same game with the same precision
+ * (CFR_EINVAL otherwise; it also fixes the variant and mode recorded in the
+ * image).  A restored solver continues exactly as the original would.    */
+int cfr_state_size(cfr_solver *s, size_t *bytes);
+int cfr_get_state(cfr_solver *s, void *out, size_t len);
+int cfr_set_state(cfr_solver *s, const void *in, size_t len);
+
 /* Payoff-product tiling of the A y product (index 0) and of the A^T x
  * product (index 1): nonzeros per thread (4, 8 or 16; a block holds up to
  * 256 times that many less 3), rows per block (64..256), vec (1: the index

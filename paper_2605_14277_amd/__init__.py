@@ -94,6 +94,9 @@ _lib.cfr_iteration.argtypes = [C.c_void_p, _P(C.c_int64)]
 _lib.cfr_kernel_timing.argtypes = [C.c_void_p, C.c_int]
 _lib.cfr_kernel_stats.argtypes = [C.c_void_p, C.c_int, _P(C.c_int64), _P(C.c_double),
                                   _P(C.c_double)]
+_lib.cfr_state_size.argtypes = [C.c_void_p, _P(C.c_size_t)]
+_lib.cfr_get_state.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
+_lib.cfr_set_state.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
 _lib.cfr_get_tiling.argtypes = [C.c_void_p, _P(cfr_spmv_tiling)]
 _lib.cfr_set_tiling.argtypes = [C.c_void_p, _P(cfr_spmv_tiling)]
 _lib.cfr_tune.argtypes = [C.c_void_p, C.c_int, _P(cfr_spmv_tiling)]
@@ -127,6 +130,7 @@ _lib.cfr_prepared_destroy.argtypes = [C.c_void_p]
 for _f in ("cfr_options_default", "cfr_validate", "cfr_workspace_size", "cfr_create", "cfr_step",
            "cfr_strategy", "cfr_regrets", "cfr_exploitability", "cfr_iteration",
            "cfr_kernel_timing", "cfr_kernel_stats", "cfr_get_tiling", "cfr_set_tiling",
+           "cfr_state_size", "cfr_get_state", "cfr_set_state",
            "cfr_tune", "cfr_destroy", "cfr_batch_options_default", "cfr_game_params_default",
            "cfr_batch_game_size", "cfr_batch_workspace_size", "cfr_batch_create",
            "cfr_batch_add", "cfr_batch_run", "cfr_batch_status", "cfr_batch_strategy",
@@ -255,6 +259,19 @@ def cfr_kernel_stats(h, kernel: int):
     _check(_lib.cfr_kernel_stats(h, kernel, C.byref(n), C.byref(ms), C.byref(by)),
            "cfr_kernel_stats")
     return int(n.value), float(ms.value), float(by.value)
+
+
+def cfr_get_state(h) -> bytes:
+    n = C.c_size_t(0)
+    _check(_lib.cfr_state_size(h, C.byref(n)), "cfr_state_size")
+    buf = C.create_string_buffer(int(n.value))
+    _check(_lib.cfr_get_state(h, buf, n), "cfr_get_state")
+    return buf.raw
+
+
+def cfr_set_state(h, state: bytes):
+    buf = C.create_string_buffer(state, len(state))
+    _check(_lib.cfr_set_state(h, buf, len(state)), "cfr_set_state")
 
 
 def _tiling_dict(t: cfr_spmv_tiling) -> dict:
@@ -466,6 +483,13 @@ class Solver:
 
     def kernel_stats(self, kernel: int):
         return cfr_kernel_stats(self.h, kernel)
+
+    def get_state(self) -> bytes:
+        """Checkpoint image of the solver's state (see cfr_get_state)."""
+        return cfr_get_state(self.h)
+
+    def set_state(self, state: bytes):
+        cfr_set_state(self.h, state)
 
     @property
     def tiling(self) -> dict:

@@ -234,9 +234,17 @@ int tune(cfr::Engine &e, int reps, cfr_spmv_tiling *chosen)
     if (reps < 1) return fail(CFR_EINVAL, "reps must be >= 1");
     static const int kItems[] = {4, 8, 16};
     static const int kRows[] = {64, 128, 256};
+    // The current tiling is the incumbent; another replaces it only when
+    // more than 2% faster, so that timing noise between near-equal tilings
+    // does not flip the choice from run to run.
     for (int w = 0; w < 2; ++w) {
-        double best = -1;
         int bi = e.items[w], br = e.rows[w], bv = e.vec[w], bp = e.perm_on[w];
+        double best = -1;
+        {
+            int rc = e.time_spmv(w, reps, &best);
+            if (rc) return rc;
+            best *= 0.98;
+        }
         for (int perm = 0; perm < 2; ++perm) {
             int rc = e.set_perm(w, perm);
             if (rc) return rc;
@@ -247,7 +255,7 @@ int tune(cfr::Engine &e, int reps, cfr_spmv_tiling *chosen)
                         double ms = 0;
                         rc = e.time_spmv(w, reps, &ms);
                         if (rc) return rc;
-                        if (best < 0 || ms < best) {
+                        if (ms < best) {
                             best = ms;
                             bi = items;
                             br = rows;
@@ -506,6 +514,135 @@ int cfr_exploitability(cfr_solver *s, int kind, double *out)
     } catch (const std::exception &ex) {
         return fail(CFR_ENOMEM, std::string("host allocation failed: ") + ex.what());
     }
+}
+
+namespace {
+
+// Checkpoint image: header, then the slot's scalars, then per player the
+// arrays r, m, s (accumulator type) and b, x (value type) over the game's
+// sequences (internal numbering).
+struct StateHeader {
+    char magic[8];
+    int32_t version, precision, variant, mode;
+    int64_t n_seq[2], n_inf[2], nnz, t;
+};
+
+size_t state_bytes(const cfr_solver *s)
+{
+    const cfr::Slot &sl = s->eng.slots[0];
+    const size_t R = cfr::accum_bytes(s->eng.prec), V = cfr::value_bytes(s->eng.prec);
+    size_t b = sizeof(StateHeader) + sizeof(cfr::Scalars);
+    for (int p = 0; p < 2; ++p) b += (3 * R + 2 * V) * (size_t)sl.n_seq[p];
+    return b;
+}
+
+}  // namespace
+
+int cfr_state_size(cfr_solver *s, size_t *bytes)
+{
+    if (!s || !bytes) return fail(CFR_EINVAL, "null argument");
+    *bytes = state_bytes(s);
+    return CFR_OK;
+}
+
+int cfr_get_state(cfr_solver *s, void *out, size_t len)
+{
+    if (!s || !out) return fail(CFR_EINVAL, "null argument");
+    if (s->eng.failed) return fail(CFR_ESTATE, "solver is in an error state");
+    if (len < state_bytes(s)) return fail(CFR_EINVAL, "buffer smaller than cfr_state_size");
+    DeviceGuard guard(s->eng.device);
+    cfr::Engine &e = s->eng;
+    const cfr::Slot &sl = e.slots[0];
+    StateHeader h{};
+    std::memcpy(h.magic, "CFRSTATE", 8);
+    h.version = 1;
+    h.precision = e.prec;
+    h.variant = s->variant;
+    h.mode = s->mode;
+    for (int p = 0; p < 2; ++p) {
+        h.n_seq[p] = sl.n_seq[p];
+        h.n_inf[p] = sl.n_inf[p];
+    }
+    h.nnz = sl.nnz;
+    h.t = sl.t;
+    char *o = (char *)out;
+    std::memcpy(o, &h, sizeof h);
+    o += sizeof h;
+    const size_t R = cfr::accum_bytes(e.prec), V = cfr::value_bytes(e.prec);
+    hipError_t err = hipMemcpyAsync(o, e.sc, sizeof(cfr::Scalars), hipMemcpyDeviceToHost, e.st);
+    o += sizeof(cfr::Scalars);
+    for (int p = 0; p < 2 && err == hipSuccess; ++p) {
+        const size_t n = (size_t)sl.n_seq[p], S = (size_t)sl.sb[p];
+        const cfr::DevPlayer &d = e.dp[p];
+        const void *src[5] = {(const char *)d.r + R * S, (const char *)d.m + R * S,
+                              (const char *)d.s + R * S, (const char *)d.b + V * S,
+                              (const char *)d.x + V * S};
+        const size_t el[5] = {R, R, R, V, V};
+        for (int k = 0; k < 5 && err == hipSuccess; ++k) {
+            err = hipMemcpyAsync(o, src[k], el[k] * n, hipMemcpyDeviceToHost, e.st);
+            o += el[k] * n;
+        }
+    }
+    if (err != hipSuccess) return e.device_error("state copy", err);
+    return e.sync("state copy");
+}
+
+int cfr_set_state(cfr_solver *s, const void *in, size_t len)
+{
+    if (!s || !in) return fail(CFR_EINVAL, "null argument");
+    if (s->eng.failed) return fail(CFR_ESTATE, "solver is in an error state");
+    cfr::Engine &e = s->eng;
+    cfr::Slot &sl = e.slots[0];
+    if (len < sizeof(StateHeader)) return fail(CFR_EINVAL, "state image too short");
+    StateHeader h;
+    std::memcpy(&h, in, sizeof h);
+    if (std::memcmp(h.magic, "CFRSTATE", 8) != 0 || h.version != 1)
+        return fail(CFR_EINVAL, "not a state image of this library");
+    if (h.precision != e.prec || h.n_seq[0] != sl.n_seq[0] || h.n_seq[1] != sl.n_seq[1] ||
+        h.n_inf[0] != sl.n_inf[0] || h.n_inf[1] != sl.n_inf[1] || h.nnz != sl.nnz)
+        return fail(CFR_EINVAL, "state image of another game or precision");
+    if (len < state_bytes(s)) return fail(CFR_EINVAL, "state image too short");
+    if (s->variant >= 0 && h.variant >= 0 && (h.variant != s->variant || h.mode != s->mode))
+        return fail(CFR_ESTATE, "the solver already runs another variant or mode");
+    DeviceGuard guard(e.device);
+    const char *o = (const char *)in + sizeof h;
+    const size_t R = cfr::accum_bytes(e.prec), V = cfr::value_bytes(e.prec);
+    // the scalars carry the variant and constants the image was taken with
+    hipError_t err = hipMemcpyAsync(e.sc, o, sizeof(cfr::Scalars), hipMemcpyHostToDevice, e.st);
+    o += sizeof(cfr::Scalars);
+    for (int p = 0; p < 2 && err == hipSuccess; ++p) {
+        const size_t n = (size_t)sl.n_seq[p], S = (size_t)sl.sb[p];
+        cfr::DevPlayer &d = e.dp[p];
+        void *dst[5] = {(char *)d.r + R * S, (char *)d.m + R * S, (char *)d.s + R * S,
+                        (char *)d.b + V * S, (char *)d.x + V * S};
+        const size_t el[5] = {R, R, R, V, V};
+        for (int k = 0; k < 5 && err == hipSuccess; ++k) {
+            err = hipMemcpyAsync(dst[k], o, el[k] * n, hipMemcpyHostToDevice, e.st);
+            o += el[k] * n;
+        }
+    }
+    if (err != hipSuccess) return e.device_error("state copy", err);
+    int rc = e.sync("state copy");
+    if (rc) return rc;
+    sl.t = h.t;
+    if (h.variant >= 0) {
+        cfr::Scalars sc;
+        std::memcpy(&sc, (const char *)in + sizeof h, sizeof sc);
+        cfr::GameParams gp = sl.gp;
+        gp.variant = h.variant;
+        gp.avg_kind = sc.avg_kind;
+        gp.alpha = sc.alpha;
+        gp.beta = sc.beta;
+        gp.gamma = sc.gamma;
+        sl.gp = gp;
+        s->variant = h.variant;
+        s->mode = h.mode;
+        e.mode = h.mode;
+        e.it.valid = false;
+        e.ev.valid = false;
+        e.drop_graph();
+    }
+    return CFR_OK;
 }
 
 int cfr_iteration(cfr_solver *s, int64_t *t)

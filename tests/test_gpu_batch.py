@@ -283,3 +283,28 @@ def test_asynchronous_admission(cfr, mix):
     b.close()
     for p in preps.values():
         p.close()
+
+
+def test_many_games_in_one_batch(cfr, mix):
+    """Sixty games (copies of the mix under every variant) packed into one
+    batch: the tables hold every game's blocks and levels, and each game
+    still equals the same game solved alone."""
+    variants = ["vanilla", "cfr+", "dcfr", "pcfr+", "pcfr"]
+    entries = []
+    for rep in range(2):
+        for vi, v in enumerate(variants):
+            for name, g, _ in mix[:6]:
+                entries.append((name, g, v))
+    b = make_batch(cfr, [g for _, g, _ in entries], max_games=len(entries), precision="fp32_acc64",
+                   check_every=10)
+    ids = [b.add(g, v) for _, g, v in entries]
+    b.run(30)
+    seen = set()
+    for (name, g, v), gid in zip(entries, ids):
+        if (name, v) in seen:
+            continue
+        seen.add((name, v))
+        solo = lone(cfr, g, v, "alternating", 30, "fp32_acc64")
+        assert_same(b, gid, solo, f"{name}/{v}")
+        solo.close()
+    b.close()

@@ -201,6 +201,7 @@ def test_cfg3_dcfr_alternating_fp64(cfr, oracle_mod, large_game):
     g = large_game
     say(f"case: cfg3 dcfr alternating fp64 nnz={g.nnz}")
     gpu = cfr.Solver(g, precision="fp64")
+    say(f"  tiling {gpu.tune(reps=3)}")
     orc = oracle_mod.Oracle(g)
     for n in (1, 1, 2):
         gpu.step(n, "dcfr", "alternating")
@@ -220,6 +221,8 @@ def test_cfg3_dcfr_alternating_acc64(cfr, oracle_mod, large_game):
     g = large_game
     say(f"case: cfg3 dcfr alternating fp32_acc64 nnz={g.nnz}")
     gpu = cfr.Solver(g, precision="fp32_acc64")
+    # the launch configuration the benchmark times: tiling from the autotuner
+    say(f"  tiling {gpu.tune(reps=3)}")
     orc = oracle_mod.Oracle(g)
     for n in (1, 1):
         gpu.step(n, "dcfr", "alternating")
@@ -368,3 +371,33 @@ def test_kernel_timing_reports(cfr, games):
     s.kernel_timing(False)
     s.step(5, "cfr+", "alternating")
     assert s.iteration == 25
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_acc64"])
+@pytest.mark.parametrize("variant", ["dcfr", "pcfr+"])
+def test_checkpoint_resume_equals_uninterrupted(cfr, games, precision, variant):
+    """A state image taken after 30 iterations and loaded into a fresh
+    solver continues exactly as the original: after 20 more iterations
+    both equal an uninterrupted 50-iteration run bit for bit."""
+    g = games["stops"]
+    a = cfr.Solver(g, precision=precision, alpha=2.0, gamma=3.0)
+    a.step(30, variant, "alternating")
+    state = a.get_state()
+    b = cfr.Solver(g, precision=precision)  # other constants: the image carries them
+    b.set_state(state)
+    assert b.iteration == 30
+    a.step(20, variant, "alternating")
+    b.step(20, variant, "alternating")
+    c = cfr.Solver(g, precision=precision, alpha=2.0, gamma=3.0)
+    c.step(50, variant, "alternating")
+    for x in (a, b):
+        for p in range(2):
+            for kind in ("current", "average"):
+                assert np.array_equal(x.strategy(p, kind), c.strategy(p, kind))
+            assert np.array_equal(x.regrets(p), c.regrets(p))
+    other = cfr.Solver(games["cfg1"], precision=precision)
+    with pytest.raises(cfr.CfrError) as ei:
+        other.set_state(state)
+    assert ei.value.code == cfr.CFR_EINVAL
+    for x in (a, b, c, other):
+        x.close()
