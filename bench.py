@@ -431,7 +431,7 @@ def main():
     if args.sweep:
         sweep = []
         s.step(3, variant, mode)
-        for vec in (0, 1):
+        for vec in (0, 1, 2):
             for items in (4, 8, 16):
                 for rows in (64, 128, 256):
                     s.tiling = {"items": [items, items], "rows": [rows, rows], "vec": [vec, vec]}

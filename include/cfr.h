@@ -236,7 +236,9 @@ int cfr_set_state(cfr_solver *s, const void *in, size_t len);
  * product (index 1): nonzeros per thread (4, 8 or 16; a block holds up to
  * 256 times that many less 3), rows per block (64..256), vec (1: the index
  * and value streams are read with 16-byte loads, four elements per lane;
- * 0: one 4-byte load per element) and perm (1: before the product, the
+ * 2: the same loads, turned around in LDS so that each gather instruction
+ * reads consecutive elements; 0: one 4-byte load per element) and perm
+ * (1: before the product, the
  * gathered strategy is copied into the order in which the rows first use
  * its entries, and the product gathers from that copy, so each row's
  * gathers touch consecutive entries; the index stream is renumbered once

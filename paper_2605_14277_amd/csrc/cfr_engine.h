@@ -152,6 +152,7 @@ struct Slot {
     int64_t sb[2] = {0, 0}, ib[2] = {0, 0}, nb = 0, nnz = 0;
     std::vector<int32_t> lvl_inf[2], lvl_seq[2];
     std::vector<uint8_t> lvl_kind[2];
+    std::vector<uint8_t> lvl_slots[2];   // per level: kSlotsWrite | kSlotsRead
     std::vector<int32_t> ptr[2];         // local row pointers of csr / csc (re-partitioning)
     std::vector<int32_t> old_of_new[2];  // internal -> caller numbering
     std::vector<SpmvBlock> blocks[2];    // product blocks (global fields)

@@ -949,6 +949,18 @@ int Engine::add(const HostGame &hg, const GameImage &img, const GameParams &gp, 
         s.lvl_inf[p] = pl.lvl_inf;
         s.lvl_seq[p] = pl.lvl_seq;
         s.lvl_kind[p] = pl.lvl_kind;
+        // Small levels store their values in the parent's slots and the
+        // level above reads them from there (one dependent load fewer);
+        // big levels write their values contiguously, since slot writes
+        // scatter.  Levels that the one-launch shallow sweep covers, and
+        // the one right below them, keep to the plain layout it reads.
+        s.lvl_slots[p].assign((size_t)pl.n_levels, 0);
+        const int32_t top_low = lone ? pl.top_levels : 0;
+        for (int32_t L = 1; L < pl.n_levels; ++L)
+            if (pl.lvl_inf[L + 1] - pl.lvl_inf[L] <= kSlotLevelMax && L > top_low) {
+                s.lvl_slots[p][L] |= kSlotsWrite;
+                s.lvl_slots[p][L - 1] |= kSlotsRead;
+            }
         s.old_of_new[p] = pl.old_of_new;
         const int32_t S = (int32_t)sb[p], I = (int32_t)ib[p];
         const size_t n = (size_t)pl.n_seq, ni = (size_t)pl.n_inf;
@@ -1193,7 +1205,7 @@ int Engine::build_tables(Tables &T, char *region, const std::vector<int> &set)
                     const Slot &s = slots[(size_t)k];
                     if (s.gp.variant != c || L >= s.n_levels[p]) continue;
                     push_chunks(T.h_up[p], s.ib[p] + s.lvl_inf[p][L], s.ib[p] + s.lvl_inf[p][L + 1],
-                                k, 0);
+                                k, s.lvl_slots[p][L]);
                     kind = std::min(kind, (int)s.lvl_kind[p][L]);
                 }
                 const int32_t n = (int32_t)T.h_up[p].size() - off;

@@ -48,7 +48,8 @@ struct SpmvBlock {
 static_assert(sizeof(SpmvBlock) == 32, "one scalar load per block");
 
 // A range [lo, hi) of at most one block's worth of decision points or
-// sequences of one game.  aux: the game's empty sequence (normalisation).
+// sequences of one game.  aux: the game's empty sequence (sequence tables)
+// or the value-slot flags (bottom-up tables).
 struct RangeBlock {
     int32_t lo, hi, slot, aux;
 };
@@ -184,6 +185,10 @@ constexpr int kRangeBlock = 256;  // decision points or sequences per sweep bloc
 #define CFR_TOP_PARTIAL 0
 #endif
 constexpr int kDownAllMaxDepth = 16;  // longest parent chain of the one-launch top-down pass
+// value-slot flags of a bottom-up table entry (RangeBlock::aux)
+constexpr int kSlotsWrite = 1;  // the level's decision points store values in parent slots
+constexpr int kSlotsRead = 2;   // the level reads its children's values from slots
+constexpr int32_t kSlotLevelMax = 65536;  // largest level (per game) that writes slots
 constexpr int kFastActs = 4;        // fast sweep path: actions per decision point
 constexpr int kFastKids = 4;        // fast sweep path: decision points below a sequence
 constexpr int kTopThreads = 1024;   // threads of the shallow-level block

@@ -157,19 +157,23 @@ __device__ void begin_iteration(Scalars *sc)
 // evaluation bit for bit; otherwise a power-of-two group of lanes shares
 // each row and combines its partial sums with cross-lane shuffles.
 //
-// VEC: the index and value streams are read four elements per lane with
+// VEC 1: the index and value streams are read four elements per lane with
 // 16-byte loads from the block's first element rounded down to a multiple
 // of four (the block partition leaves room for the up to three elements
 // before it); products are staged at their offset from that aligned start.
 // Elements outside the block gather entry 0 and stage a zero that no row
-// reads.  Otherwise every element is its own 4-byte load.
+// reads.  One gather instruction then reads every fourth element.
+// VEC 2: the same 16-byte loads, after which each wave turns its own
+// 256-element chunks around through LDS, so that one gather instruction
+// reads 64 consecutive elements (whose column indices lie close together).
+// VEC 0: every element is its own 4-byte load, consecutive across lanes.
 //
 // Each table entry gives a block's rows, nonzeros and game in one scalar
 // load.  The loads of a block are all issued
 // unconditionally (lanes past the end read the block's first entry and
 // ignore it): index/value stream and row pointers in one round, gathers in
 // the next; the reduction then reads only LDS.
-template <int P, bool SEQ, int ITEMS, bool VEC>
+template <int P, bool SEQ, int ITEMS, int VEC>
 __global__ __launch_bounds__(kSpmvThreads) void k_spmv(
     int32_t n_blk, const SpmvBlock *__restrict__ tab, const int32_t *__restrict__ ptr,
     const int32_t *__restrict__ idx, const typename Types<P>::V *__restrict__ val,
@@ -220,7 +224,82 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(
     // kSpmvRowCap = kSpmvThreads rows)
     const int32_t pr = ptr[rb + (tid < nr ? tid : 0)];
     int32_t sh = 0;  // staging offset of the block's first element
-    if (VEC) {
+    if (VEC == 2) {
+        constexpr int NV = ITEMS / 4;
+        const int64_t e_al = e0 & ~(int64_t)3;
+        sh = (int32_t)(e0 - e_al);
+        const int32_t n_al = n + sh;
+        if (n > 0) {
+            v4i c4[NV];
+            V v4[NV][4];
+#pragma unroll
+            for (int j = 0; j < NV; ++j) {
+                const int32_t vi = j * kSpmvThreads + tid;
+                const int64_t at = e_al + 4 * (int64_t)(4 * vi < n_al ? vi : 0);
+                c4[j] = load4(idx + at);
+                load4(val + at, v4[j]);
+            }
+            // Staging slot 4*vi + e holds element e of lane vi's load; a
+            // wave's loads of round j fill slots [4*(j*256 + w0), +256), w0
+            // its first thread, and it reads them back as slot
+            // 4*(j*256 + w0) + 64*e + lane.  The chunks of different waves
+            // are disjoint and the LDS serves one wave's accesses in order,
+            // so a wave-level code-motion barrier is all the ordering needed.
+            const int lane = tid & 63;
+            const int32_t w0 = tid & ~63;
+            constexpr int IS = (int)(sizeof(L) / sizeof(int32_t));  // index view: ints per slot
+            int32_t *ti = reinterpret_cast<int32_t *>(prod);
+#pragma unroll
+            for (int j = 0; j < NV; ++j) {
+                const int32_t vi = j * kSpmvThreads + tid;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) ti[IS * (4 * vi + e)] = c4[j][e];
+            }
+            __builtin_amdgcn_wave_barrier();
+            // all index reads first, then all gathers (one round)
+            int32_t ct[NV][4];
+#pragma unroll
+            for (int j = 0; j < NV; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int32_t sl = 4 * (j * kSpmvThreads + w0) + 64 * e + lane;
+                    const int32_t q = sl - sh;
+                    const int32_t c = ti[IS * sl];
+                    ct[j][e] = (q >= 0 && q < n) ? c : 0;
+                }
+            V gx[NV][4];
+#pragma unroll
+            for (int j = 0; j < NV; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) gx[j][e] = xin[ct[j][e]];
+            __builtin_amdgcn_wave_barrier();
+            // the values take the same way round while the gathers fly
+#pragma unroll
+            for (int j = 0; j < NV; ++j) {
+                const int32_t vi = j * kSpmvThreads + tid;
+                L o[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) o[e] = (L)v4[j][e];
+                store4(&prod[4 * vi], o);
+            }
+            __builtin_amdgcn_wave_barrier();
+            L vt[NV][4];
+#pragma unroll
+            for (int j = 0; j < NV; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    vt[j][e] = prod[4 * (j * kSpmvThreads + w0) + 64 * e + lane];
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int j = 0; j < NV; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int32_t sl = 4 * (j * kSpmvThreads + w0) + 64 * e + lane;
+                    const int32_t q = sl - sh;
+                    prod[sl] = (q >= 0 && q < n) ? (L)((C)vt[j][e] * (C)gx[j][e]) : (L)0;
+                }
+        }
+    } else if (VEC == 1) {
         constexpr int NV = ITEMS / 4;
         const int64_t e_al = e0 & ~(int64_t)3;
         sh = (int32_t)(e0 - e_al);
@@ -334,10 +413,15 @@ __device__ __forceinline__ typename Types<P>::C post_step(typename Types<P>::C r
     return r;
 }
 
-// Values of the decision points below each sequence, in slots: a decision
-// point whose parent sequence has at most kFastKids of them also stores its
-// value at cval[4 * parent + (its rank among them)], so the parent's level
-// reads them with its own action data instead of through child_idx.
+// Values of the decision points below each sequence, in slots: on a level
+// flagged to write slots (SL & kSlotsWrite), a decision point whose parent
+// sequence has at most kFastKids of them stores its value at
+// cval[4 * parent + (its rank among them)] instead of vinf, and the parent's
+// level (SL & kSlotsRead) reads them with its own action data instead of
+// through child_idx.  Only small levels write slots (their writes scatter);
+// the flags come with each block of the table and select a compiled copy
+// of the level's code, so that each copy issues its loads in as few
+// dependent rounds as it can.
 template <int P>
 struct Kids {
     const int32_t *__restrict__ cslot;   // [decision points] slot, or -1
@@ -345,17 +429,21 @@ struct Kids {
     typename Types<P>::C *__restrict__ cval;  // [4 * sequences]
 };
 
+// The value of decision point j for its parent's level.
 template <int P>
-__device__ __forceinline__ void store_value(const Kids<P> &kd, int32_t cs, typename Types<P>::C v)
+__device__ __forceinline__ void store_value(const Kids<P> &kd, int32_t cs, int32_t j,
+                                            typename Types<P>::C *__restrict__ vinf,
+                                            typename Types<P>::C v)
 {
     if (cs >= 0) kd.cval[cs] = v;
+    else vinf[j] = v;
 }
 
 // One decision point of ObserveUtility: counterfactual utilities of its
 // actions (own utility plus the values of the decision points below), its
 // value, the regret update with the variant's post-step, and regret
 // matching for the next strategy.
-template <int P, int VAR>
+template <int P, int VAR, int SL>
 __device__ __forceinline__ void up_infoset(
     int32_t j, const int32_t *__restrict__ inf_first, const int32_t *__restrict__ child_ptr,
     const int32_t *__restrict__ child_idx, const typename Types<P>::V *__restrict__ g,
@@ -370,10 +458,15 @@ __device__ __forceinline__ void up_infoset(
     constexpr bool kPred = VAR == CFR_PCFR_PLUS || VAR == CFR_PCFR;
     const int32_t a0 = inf_first[j], a1 = inf_first[j + 1];
     const int32_t n = a1 - a0;
-    const int32_t cs = kd.cslot[j];
+    const int32_t cs = (SL & kSlotsWrite) ? kd.cslot[j] : -1;
 
     auto cf_utility = [&](int32_t a) -> C {
         C acc = usign * (C)g[a];
+        const int cnt = (SL & kSlotsRead) ? (int)kd.ccount[a] : kFastKids + 1;
+        if (cnt <= kFastKids) {
+            for (int i = 0; i < cnt; ++i) acc = acc + kd.cval[4 * (int64_t)a + i];
+            return acc;
+        }
         const int32_t c1 = child_ptr[a + 1];
         for (int32_t c = child_ptr[a]; c < c1; ++c) acc = acc + vinf[child_idx[c]];
         return acc;
@@ -389,8 +482,7 @@ __device__ __forceinline__ void up_infoset(
                 V_ = V_ + (C)b[a0 + k] * q[k];
             }
         }
-        vinf[j] = V_;
-        store_value(kd, cs, V_);
+        store_value(kd, cs, j, vinf, V_);
         C z[kMaxActs];
         C Z = 0;
 #pragma unroll
@@ -420,8 +512,7 @@ __device__ __forceinline__ void up_infoset(
     // large decision points: recompute instead of holding every action
     C V_ = 0;
     for (int32_t a = a0; a < a1; ++a) V_ = V_ + (C)b[a] * cf_utility(a);
-    vinf[j] = V_;
-    store_value(kd, cs, V_);
+    store_value(kd, cs, j, vinf, V_);
     C Z = 0;
     for (int32_t a = a0; a < a1; ++a) {
         C inst = cf_utility(a) - V_;
@@ -445,13 +536,15 @@ __device__ __forceinline__ void up_infoset(
 // Fast path of up_infoset for a decision point with at most kFastActs
 // actions, each with at most kFastKids decision points below it.  Every
 // load is issued unconditionally (lanes past the end read a valid clamped
-// address and ignore the value), so two dependent rounds serve everything:
-// action range and own slot, then action data with the child counts and
-// child values (from the slots).  The arithmetic and its order are exactly
-// those of up_infoset (children in ascending order).
-template <int P, int VAR, int NC>
+// address and ignore the value), so one dependent round serves each of:
+// action range (and own slot); action data with child pointers, or with
+// child counts and values when the block reads slots; otherwise child ids;
+// child values.  The arithmetic and its order are exactly those of
+// up_infoset (children in ascending order).
+template <int P, int VAR, int NC, int SL>
 __device__ __forceinline__ void up_infoset_fast(
-    int32_t j, const int32_t *__restrict__ inf_first, const typename Types<P>::V *__restrict__ g,
+    int32_t j, const int32_t *__restrict__ inf_first, const int32_t *__restrict__ child_ptr,
+    const int32_t *__restrict__ child_idx, const typename Types<P>::V *__restrict__ g,
     typename Types<P>::C usign, typename Types<P>::C *__restrict__ vinf,
     typename Types<P>::V *__restrict__ b, typename Types<P>::R *__restrict__ r,
     typename Types<P>::R *__restrict__ m, typename Types<P>::C dpos, typename Types<P>::C dneg,
@@ -465,25 +558,51 @@ __device__ __forceinline__ void up_infoset_fast(
     static_assert(NC == 0 || NC == 4, "child values are read as slots of four");
     constexpr bool kPred = VAR == CFR_PCFR_PLUS || VAR == CFR_PCFR;
     const int32_t a0 = inf_first[j], a1 = inf_first[j + 1];
-    const int32_t cs = kd.cslot[j];
+    const int32_t cs = (SL & kSlotsWrite) ? kd.cslot[j] : -1;
     const int32_t n = a1 - a0;
     V gv[NA], bv[NA];
     R rv[NA], mv[NA];
     int cnt[NA];
     C cv[NA][NCA];
+    if (NC > 0 && (SL & kSlotsRead)) {
 #pragma unroll
-    for (int k = 0; k < NA; ++k) {
-        const int32_t a = a0 + (k < n ? k : 0);
-        gv[k] = g[a];
-        bv[k] = b[a];
-        rv[k] = r[a];
-        if (kPred) mv[k] = m[a];
-        if (NC > 0) {
+        for (int k = 0; k < NA; ++k) {
+            const int32_t a = a0 + (k < n ? k : 0);
+            gv[k] = g[a];
+            bv[k] = b[a];
+            rv[k] = r[a];
+            if (kPred) mv[k] = m[a];
             cnt[k] = kd.ccount[a];
 #pragma unroll
             for (int i = 0; i < NC; ++i) cv[k][i] = kd.cval[4 * (int64_t)a + i];
-        } else {
-            cnt[k] = 0;
+        }
+    } else {
+        int32_t c0[NA];
+#pragma unroll
+        for (int k = 0; k < NA; ++k) {
+            const int32_t a = a0 + (k < n ? k : 0);
+            gv[k] = g[a];
+            bv[k] = b[a];
+            rv[k] = r[a];
+            if (kPred) mv[k] = m[a];
+            if (NC > 0) {
+                c0[k] = child_ptr[a];
+                cnt[k] = child_ptr[a + 1] - c0[k];
+            } else {
+                c0[k] = 0;
+                cnt[k] = 0;
+            }
+        }
+        if (NC > 0) {
+            int32_t cid[NA][NCA];
+#pragma unroll
+            for (int k = 0; k < NA; ++k)
+#pragma unroll
+                for (int i = 0; i < NC; ++i) cid[k][i] = child_idx[i < cnt[k] ? c0[k] + i : 0];
+#pragma unroll
+            for (int k = 0; k < NA; ++k)
+#pragma unroll
+                for (int i = 0; i < NC; ++i) cv[k][i] = vinf[cid[k][i]];
         }
     }
     C q[NA];
@@ -499,8 +618,7 @@ __device__ __forceinline__ void up_infoset_fast(
             V_ = V_ + (C)bv[k] * acc;
         }
     }
-    vinf[j] = V_;
-    store_value(kd, cs, V_);
+    store_value(kd, cs, j, vinf, V_);
     C z[NA];
     C Z = 0;
 #pragma unroll
@@ -593,13 +711,26 @@ __global__ __launch_bounds__(kThreads) void k_up(
         dpos = (C)gs->dpos;
         dneg = (C)gs->dneg;
     }
-    if (KIND == 1)
-        up_infoset_fast<P, VAR, kFastKids>(j, inf_first, g, usign, vinf, b, r, m, dpos, dneg, kd);
-    else if (KIND == 2)
-        up_infoset_fast<P, VAR, 0>(j, inf_first, g, usign, vinf, b, r, m, dpos, dneg, kd);
-    else
-        up_infoset<P, VAR>(j, inf_first, child_ptr, child_idx, g, usign, vinf, b, r, m, dpos,
-                           dneg, kd);
+    auto level = [&](auto sl) {
+        constexpr int SL = decltype(sl)::value;
+        if (KIND == 1)
+            up_infoset_fast<P, VAR, kFastKids, SL>(j, inf_first, child_ptr, child_idx, g, usign,
+                                                   vinf, b, r, m, dpos, dneg, kd);
+        else if (KIND == 2)
+            up_infoset_fast<P, VAR, 0, SL & kSlotsWrite>(j, inf_first, child_ptr, child_idx, g,
+                                                         usign, vinf, b, r, m, dpos, dneg, kd);
+        else
+            up_infoset<P, VAR, SL>(j, inf_first, child_ptr, child_idx, g, usign, vinf, b, r, m,
+                                   dpos, dneg, kd);
+    };
+    // the flags are the same for the whole block (one scalar branch); the
+    // level under the empty sequence never writes slots
+    switch (ROOT ? rb.aux & kSlotsRead : rb.aux) {
+    case 0: level(std::integral_constant<int, 0>()); break;
+    case kSlotsWrite: level(std::integral_constant<int, kSlotsWrite>()); break;
+    case kSlotsRead: level(std::integral_constant<int, kSlotsRead>()); break;
+    default: level(std::integral_constant<int, kSlotsWrite | kSlotsRead>()); break;
+    }
     if (ROOT) down_infoset<P>(j, inf_first, seq_par, b, x, s, (R)gs->w, 1);
 }
 
@@ -635,11 +766,12 @@ __global__ __launch_bounds__(kTopThreads) void k_top(
         const int32_t *off = top_off + (size_t)lv * (n_roots + 1);
         for (int32_t i = off[root] + (int32_t)threadIdx.x; i < off[root + 1]; i += kTopThreads) {
             if (all_fast)
-                up_infoset_fast<P, VAR, kFastKids>(top_list[i], inf_first, g, usign, vinf, b, r,
-                                                   m, dpos, dneg, kd);
+                up_infoset_fast<P, VAR, kFastKids, 0>(top_list[i], inf_first, child_ptr,
+                                                      child_idx, g, usign, vinf, b, r, m, dpos,
+                                                      dneg, kd);
             else
-                up_infoset<P, VAR>(top_list[i], inf_first, child_ptr, child_idx, g, usign, vinf,
-                                   b, r, m, dpos, dneg, kd);
+                up_infoset<P, VAR, 0>(top_list[i], inf_first, child_ptr, child_idx, g, usign,
+                                      vinf, b, r, m, dpos, dneg, kd);
         }
         __syncthreads();
     }
@@ -860,7 +992,7 @@ Kids<P> kids(const DevPlayer &p)
     return Kids<P>{p.cslot, p.ccount, (typename Types<P>::C *)p.cval};
 }
 
-template <int P, bool SEQ, int ITEMS, bool VEC>
+template <int P, bool SEQ, int ITEMS, int VEC>
 hipError_t spmv_launch(const SpmvBlock *tab, int32_t n_tab, const int32_t *ptr, const int32_t *idx,
                        const void *val, const void *xin, void *yout, int xcd_remap, int begin,
                        Scalars *sc, hipStream_t st)
@@ -873,7 +1005,7 @@ hipError_t spmv_launch(const SpmvBlock *tab, int32_t n_tab, const int32_t *ptr, 
     return hipGetLastError();
 }
 
-template <int P, bool SEQ, bool VEC>
+template <int P, bool SEQ, int VEC>
 hipError_t spmv_items(int items, const SpmvBlock *tab, int32_t n_tab, const int32_t *ptr,
                       const int32_t *idx, const void *val, const void *xin, void *yout,
                       int xcd_remap, int begin, Scalars *sc, hipStream_t st)
@@ -898,18 +1030,24 @@ hipError_t spmv_t(int items, int vec, const SpmvBlock *tab, int32_t n_tab, const
                   int sequential, int begin, Scalars *sc, hipStream_t st)
 {
     if (n_tab <= 0) return hipSuccess;
-    if (sequential) {
-        if (vec)
-            return spmv_items<P, true, true>(items, tab, n_tab, ptr, idx, val, xin, yout,
-                                             xcd_remap, begin, sc, st);
-        return spmv_items<P, true, false>(items, tab, n_tab, ptr, idx, val, xin, yout, xcd_remap,
-                                          begin, sc, st);
+#define CFR_SPMV_VEC(SQ)                                                                      \
+    switch (vec) {                                                                            \
+    case 0:                                                                                   \
+        return spmv_items<P, SQ, 0>(items, tab, n_tab, ptr, idx, val, xin, yout, xcd_remap,   \
+                                    begin, sc, st);                                           \
+    case 1:                                                                                   \
+        return spmv_items<P, SQ, 1>(items, tab, n_tab, ptr, idx, val, xin, yout, xcd_remap,   \
+                                    begin, sc, st);                                           \
+    case 2:                                                                                   \
+        return spmv_items<P, SQ, 2>(items, tab, n_tab, ptr, idx, val, xin, yout, xcd_remap,   \
+                                    begin, sc, st);                                           \
+    default: return hipErrorInvalidValue;                                                     \
     }
-    if (vec)
-        return spmv_items<P, false, true>(items, tab, n_tab, ptr, idx, val, xin, yout, xcd_remap,
-                                          begin, sc, st);
-    return spmv_items<P, false, false>(items, tab, n_tab, ptr, idx, val, xin, yout, xcd_remap,
-                                       begin, sc, st);
+    if (sequential) {
+        CFR_SPMV_VEC(true)
+    }
+    CFR_SPMV_VEC(false)
+#undef CFR_SPMV_VEC
 }
 
 template <int P, int VAR, int KIND, bool ROOT>

@@ -200,7 +200,9 @@ def test_tiling_and_tuner(cfr, mix):
     out = []
     for tiling in (None, {"items": [4, 8], "rows": [64, 128], "vec": [0, 1], "perm": [1, 0]},
                    {"items": [16, 4], "rows": [256, 64], "vec": [1, 0], "perm": [0, 1]},
-                   {"items": [8, 8], "rows": [128, 128], "vec": [1, 1], "perm": [1, 1]}, "tune"):
+                   {"items": [8, 8], "rows": [128, 128], "vec": [1, 1], "perm": [1, 1]},
+                   {"items": [16, 8], "rows": [256, 128], "vec": [2, 2], "perm": [0, 1]},
+                   {"items": [4, 16], "rows": [64, 256], "vec": [2, 0], "perm": [1, 0]}, "tune"):
         b = make_batch(cfr, games, max_games=len(mix), precision="fp64")
         ids = [b.add(g, v) for _, g, v in mix]
         if tiling == "tune":
@@ -208,12 +210,31 @@ def test_tiling_and_tuner(cfr, mix):
             say(f"  tuner chose {chosen}")
             assert all(i in (4, 8, 16) for i in chosen["items"])
             assert all(64 <= r <= 256 for r in chosen["rows"])
-            assert all(v in (0, 1) for v in chosen["vec"])
+            assert all(v in (0, 1, 2) for v in chosen["vec"])
             assert all(v in (0, 1) for v in chosen["perm"])
         elif tiling is not None:
             b.tiling = tiling
             assert b.tiling == tiling
         b.run(40)
+        out.append([b.strategy(gid, p, "average") for gid in ids for p in range(2)])
+        b.close()
+    for other in out[1:]:
+        for a, c in zip(out[0], other):
+            assert np.array_equal(a, c)
+
+
+@pytest.mark.parametrize("precision", ["fp32_acc64", "fp32"])
+def test_stream_load_forms_agree(cfr, mix, precision):
+    """The three ways of reading the index and value streams stage every
+    product at the same place, so with the same blocks the FP32 row sums
+    (lane groups) come out bit for bit the same."""
+    games = [g for _, g, _ in mix]
+    out = []
+    for vec in (0, 1, 2):
+        b = make_batch(cfr, games, max_games=len(mix), precision=precision)
+        ids = [b.add(g, v) for _, g, v in mix]
+        b.tiling = {"items": [8, 16], "rows": [128, 256], "vec": [vec, vec], "perm": [0, 1]}
+        b.run(30)
         out.append([b.strategy(gid, p, "average") for gid in ids for p in range(2)])
         b.close()
     for other in out[1:]:
