@@ -65,18 +65,26 @@ def measured_traffic(kernel: str, digest: str, tiling: dict):
     return ent.get("bytes_per_launch")
 
 
-def algorithmic_bytes_per_iteration(g, vbytes: int, abytes: int, predictive: bool) -> float:
+def algorithmic_bytes_per_iteration(g, vbytes: int, abytes: int, predictive: bool,
+                                    product_bytes=None) -> float:
     """Bytes one iteration must move at minimum: both payoff streams (index +
-    value), row pointers, each gathered vector once and each product's output
-    once, and per sequence: regret and average read-modify-write in the
-    accumulator type, the utility read, the behavioural strategy written and
-    read, the strategy written, one int32 of treeplex structure (plus the
-    prediction's read and write for predictive variants)."""
+    value, or in stream form 3 each quad's index and four values), row
+    pointers, each gathered vector once and each product's output once, and
+    per sequence: regret and average read-modify-write in the accumulator
+    type, the utility read, the behavioural strategy written and read, the
+    strategy written, one int32 of treeplex structure (plus the prediction's
+    read and write for predictive variants).  product_bytes: the two
+    products' bytes per launch as the library counts them for the stream
+    form in use (the element-stream formula when None)."""
     n1, n2 = g.n_seq
-    payoff = 2 * g.nnz * (4 + vbytes) + 4 * (n1 + 1) + 4 * (n2 + 1)
-    vectors = 2 * (n1 + n2) * vbytes
+    if product_bytes is None:
+        payoff = 2 * g.nnz * (4 + vbytes) + 4 * (n1 + 1) + 4 * (n2 + 1)
+        vectors = 2 * (n1 + n2) * vbytes
+        products = payoff + vectors
+    else:
+        products = sum(product_bytes)
     per_seq = 4 * abytes + 4 * vbytes + 4 + (2 * abytes if predictive else 0)
-    return float(payoff + vectors + (n1 + n2) * per_seq)
+    return float(products + (n1 + n2) * per_seq)
 
 
 def cpu_baseline(g, variant, mode, budget_s: float):
@@ -431,21 +439,23 @@ def main():
     if args.sweep:
         sweep = []
         s.step(3, variant, mode)
-        for vec in (0, 1, 2):
-            for items in (4, 8, 16):
-                for rows in (64, 128, 256):
-                    s.tiling = {"items": [items, items], "rows": [rows, rows], "vec": [vec, vec]}
-                    s.kernel_timing(True)
-                    s.step(20, variant, mode)
-                    us = []
-                    for k in (0, 1):
-                        n, tot, _ = s.kernel_stats(k)
-                        us.append(tot / n * 1e3)
-                    s.kernel_timing(False)
-                    sweep.append({"vec": vec, "items": items, "rows": rows, "csr_us": us[0],
-                                  "csc_us": us[1]})
-                    log(f"[sweep] vec {vec} items {items:2d} rows {rows:3d}: A y {us[0]:7.1f} us, "
-                        f"A^T x {us[1]:7.1f} us")
+        for perm in (0, 1):
+            for vec in (0, 1, 2, 3):
+                for items in ((16,) if vec == 3 else (4, 8, 16)):
+                    for rows in (64, 128, 256):
+                        s.tiling = {"items": [items, items], "rows": [rows, rows],
+                                    "vec": [vec, vec], "perm": [perm, perm]}
+                        s.kernel_timing(True)
+                        s.step(20, variant, mode)
+                        us = []
+                        for k in (0, 1):
+                            n, tot, _ = s.kernel_stats(k)
+                            us.append(tot / n * 1e3)
+                        s.kernel_timing(False)
+                        sweep.append({"perm": perm, "vec": vec, "items": items, "rows": rows,
+                                      "csr_us": us[0], "csc_us": us[1]})
+                        log(f"[sweep] perm {perm} vec {vec} items {items:2d} rows {rows:3d}: "
+                            f"A y {us[0]:7.1f} us, A^T x {us[1]:7.1f} us")
     tune_s = None
     if args.tiling:
         parts = args.tiling.split(":")
@@ -488,6 +498,7 @@ def main():
         n, tot, by = s.kernel_stats(k)
         stats.append((tot, name, n, by))
     s.kernel_timing(False)
+    product_bytes = [st[3] for st in stats]
     stats.sort(reverse=True)
     tot, kname, nl, by = stats[0]
     avg_ms = tot / nl
@@ -500,7 +511,15 @@ def main():
 
     vbytes = 8 if precision == "fp64" else 4
     abytes = 4 if precision == "fp32" else 8
-    alg = algorithmic_bytes_per_iteration(g, vbytes, abytes, variant in ("pcfr+", "pcfr"))
+    alg = algorithmic_bytes_per_iteration(g, vbytes, abytes, variant in ("pcfr+", "pcfr"),
+                                          product_bytes)
+    # what the element stream (index + value per nonzero) would have to move
+    # for the same product: the rate at which this launch does the work of
+    # the plain sparse format
+    w = 0 if kname == "spmv_csr" else 1
+    n_rows, n_cols = g.n_seq[w], g.n_seq[1 - w]
+    by_elem = g.nnz * (4 + vbytes) + 4 * (n_rows + 1) + vbytes * (n_cols + n_rows)
+    elem_gbs = by_elem / (avg_ms * 1e-3) / 1e9
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -534,7 +553,9 @@ def main():
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "avg_launch_us": avg_ms * 1e3,
-                     "bytes_per_launch": by},
+                     "bytes_per_launch": by, "stream_form": tiling["vec"][w],
+                     "element_stream_bytes_per_launch": by_elem,
+                     "element_stream_equiv_gbs": elem_gbs},
         "cpu_baseline": cpu,
         "expl_average": e["expl"],
     }

@@ -237,14 +237,20 @@ int cfr_set_state(cfr_solver *s, const void *in, size_t len);
  * 256 times that many less 3), rows per block (64..256), vec (1: the index
  * and value streams are read with 16-byte loads, four elements per lane;
  * 2: the same loads, turned around in LDS so that each gather instruction
- * reads consecutive elements; 0: one 4-byte load per element) and perm
+ * reads consecutive elements; 0: one 4-byte load per element; 3: quads, a
+ * copy of the matrix in which each element is a run of at most four
+ * nonzeros of a row whose columns share one aligned group of four, stored
+ * as one index and four values and gathered with one 16-byte load; only
+ * with 16 nonzeros per thread; the library allocates this copy itself, on
+ * first use, outside any caller workspace, and frees it on destroy) and perm
  * (1: before the product, the
  * gathered strategy is copied into the order in which the rows first use
  * its entries, and the product gathers from that copy, so each row's
  * gathers touch consecutive entries; the index stream is renumbered once
  * when the flag changes).  Rows longer than one block's capacity are
  * summed by a tree in every order; every other row keeps its summation
- * order under every choice.                                              */
+ * order under every choice (quads add -0.0 at absent positions, which
+ * changes no sum).                                                       */
 typedef struct cfr_spmv_tiling {
     int items[2];
     int rows[2];

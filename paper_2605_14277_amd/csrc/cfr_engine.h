@@ -140,6 +140,19 @@ struct RangeAlloc {
     int64_t largest() const;
 };
 
+// Stream form 3 of one product: a derived copy of every game's matrix in
+// quads, in memory the engine allocates itself on first use and grows when
+// needed.  Each game owns a range of quads, built on the device from its
+// element arrays in their current numbering (and dropped when that
+// numbering changes or the game leaves).
+struct QuadStore {
+    int32_t *ptr = nullptr;   // [row player's sequence capacity] game-local quad row pointers
+    uint32_t *idx = nullptr;  // [cap] quad index | presence mask << kQuadMaskShift
+    void *val = nullptr;      // [4 * cap] value type
+    int64_t cap = 0;
+    RangeAlloc alloc;
+};
+
 // One game held by an engine.
 struct Slot {
     bool live = false;     // holds a game
@@ -154,6 +167,9 @@ struct Slot {
     std::vector<uint8_t> lvl_kind[2];
     std::vector<uint8_t> lvl_slots[2];   // per level: kSlotsWrite | kSlotsRead
     std::vector<int32_t> ptr[2];         // local row pointers of csr / csc (re-partitioning)
+    int64_t qb[2] = {-1, -1};            // first quad of the game's stream-form-3 copy (-1: none)
+    int64_t nq[2] = {0, 0};              // quads in it
+    std::vector<int32_t> qptr[2];        // its local quad row pointers
     std::vector<int32_t> old_of_new[2];  // internal -> caller numbering
     std::vector<SpmvBlock> blocks[2];    // product blocks (global fields)
     double last[5] = {0, 0, 0, 0, 0};    // last evaluation: expl, NashConv, BR1, BR2, value
@@ -236,6 +252,7 @@ struct Engine {
     size_t tab_bytes = 0;
 
     RangeAlloc seq_alloc[2], inf_alloc[2], nnz_alloc;
+    QuadStore quad[2];
     std::vector<Slot> slots;
     int64_t next_id = 0;
     Tables it, ev;  // tables of the iterating games / of the last evaluated set
@@ -283,6 +300,11 @@ struct Engine {
     // copy of its input: remaps every game's index stream in place.
     int set_perm(int which, int on);
     void partition(Slot &s, int which);
+    // Builds the quad copies that products in stream form 3 need for the
+    // games of `set` (waits for their admission copies and for the stream).
+    int ensure_quads(const std::vector<int> &set);
+    void drop_quads(Slot &s, int which);
+    int grow_quads(int which, int64_t need);
 
     std::vector<int> active_set() const;
     int build_tables(Tables &T, char *region, const std::vector<int> &set);

@@ -302,13 +302,13 @@ Layout carve(Carver &k, const Capacity &c, int prec)
         d.m = k.take(R * n);
         d.s = k.take(R * n);
         d.b = k.take(V * n);
-        d.x = k.take(V * n);
+        d.x = k.take(V * (n + kVecPad));
         d.g = k.take(V * n);
-        d.xbar = k.take(V * n);
+        d.xbar = k.take(V * (n + kVecPad));
         d.vinf = k.take(C * ni);
         d.perm = (int32_t *)k.take(4 * n);
         d.pos = (int32_t *)k.take(4 * n);
-        d.xp = k.take(V * n);
+        d.xp = k.take(V * (n + kVecPad));
         d.cslot = (int32_t *)k.take(4 * ni);
         d.ccount = (uint8_t *)k.take(n);
         d.cval = k.take(C * 4 * n);
@@ -791,6 +791,12 @@ void Engine::release()
     scal_stage = nullptr;
     if (own_ws && ws) (void)hipFree(ws);
     ws = nullptr;
+    for (QuadStore &Q : quad) {
+        if (Q.ptr) (void)hipFree(Q.ptr);
+        if (Q.idx) (void)hipFree(Q.idx);
+        if (Q.val) (void)hipFree(Q.val);
+        Q = QuadStore();
+    }
 }
 
 int Engine::device_error(const char *what, hipError_t e)
@@ -817,22 +823,136 @@ int Engine::sequential() const
 void Engine::partition(Slot &s, int which)
 {
     const int k = (int)(&s - slots.data());
-    const std::vector<int32_t> blk =
-        partition_rows(s.ptr[which], spmv_block_cap(items[which]), rows[which]);
     s.blocks[which].clear();
+    const bool quads = vec[which] == 3;
+    // stream form 3 partitions the game's quads, once they are built
+    if (quads && s.qb[which] < 0) return;
+    const std::vector<int32_t> &rp = quads ? s.qptr[which] : s.ptr[which];
+    const int64_t base = quads ? s.qb[which] : s.nb;
+    const std::vector<int32_t> blk =
+        partition_rows(rp, spmv_block_cap_v(items[which], vec[which]), rows[which]);
     s.blocks[which].reserve(blk.size());
     for (size_t i = 0; i + 1 < blk.size(); ++i) {
         const int32_t r0 = blk[i], r1 = blk[i + 1];
         SpmvBlock b{};
         b.row0 = (int32_t)(s.sb[which] + r0);
         b.nr = r1 - r0;
-        b.n = s.ptr[which][r1] - s.ptr[which][r0];
-        b.p0 = s.ptr[which][r0];
-        b.e0 = s.nb + s.ptr[which][r0];
+        b.n = rp[r1] - rp[r0];
+        b.p0 = rp[r0];
+        b.e0 = base + rp[r0];
         b.slot = k;
         b.begin = i == 0 ? 1 : 0;
         s.blocks[which].push_back(b);
     }
+}
+
+void Engine::drop_quads(Slot &s, int which)
+{
+    if (s.qb[which] >= 0 && s.nq[which] > 0) quad[which].alloc.give(s.qb[which], s.nq[which]);
+    s.qb[which] = -1;
+    s.nq[which] = 0;
+    s.qptr[which].clear();
+    s.qptr[which].shrink_to_fit();
+    if (vec[which] == 3) s.blocks[which].clear();
+}
+
+int Engine::grow_quads(int which, int64_t need)
+{
+    QuadStore &Q = quad[which];
+    const size_t V = value_bytes(prec);
+    const int64_t ncap = std::max<int64_t>(need, Q.cap + Q.cap / 2);
+    uint32_t *ni = nullptr;
+    void *nv = nullptr;
+    hipError_t e = hipMalloc((void **)&ni, 4 * (size_t)ncap);
+    if (e == hipSuccess) e = hipMalloc(&nv, 4 * V * (size_t)ncap);
+    if (e != hipSuccess) {
+        if (ni) (void)hipFree(ni);
+        if (nv) (void)hipFree(nv);
+        (void)hipGetLastError();
+        return fail(CFR_ENOMEM, "cannot allocate the quad stream of a product");
+    }
+    if (Q.cap > 0) {
+        e = hipMemcpyAsync(ni, Q.idx, 4 * (size_t)Q.cap, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(nv, Q.val, 4 * V * (size_t)Q.cap, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            (void)hipFree(ni);
+            (void)hipFree(nv);
+            return device_error("quad stream copy", e);
+        }
+        (void)hipFree(Q.idx);
+        (void)hipFree(Q.val);
+        Q.alloc.give(Q.cap, ncap - Q.cap);
+    } else {
+        Q.alloc.init(ncap);
+    }
+    Q.idx = ni;
+    Q.val = nv;
+    Q.cap = ncap;
+    Q.alloc.cap = ncap;
+    drop_graph();
+    return CFR_OK;
+}
+
+int Engine::ensure_quads(const std::vector<int> &set)
+{
+    for (int w = 0; w < 2; ++w) {
+        if (vec[w] != 3) continue;
+        bool any = false;
+        for (int k : set) any |= slots[(size_t)k].qb[w] < 0;
+        if (!any) continue;
+        reap_uploads(true);  // the element arrays of games still being copied
+        QuadStore &Q = quad[w];
+        hipError_t e = hipSuccess;
+        if (!Q.ptr) {
+            e = hipMalloc((void **)&Q.ptr, 4 * (size_t)std::max<int64_t>(cap.seq[w], 1));
+            if (e != hipSuccess) {
+                Q.ptr = nullptr;
+                (void)hipGetLastError();
+                return fail(CFR_ENOMEM, "cannot allocate the quad row pointers of a product");
+            }
+        }
+        for (int k : set) {
+            Slot &s = slots[(size_t)k];
+            if (s.qb[w] >= 0) continue;
+            const int32_t nr = (int32_t)s.ptr[w].size() - 1;
+            const int32_t row0 = (int32_t)s.sb[w];
+            std::vector<int32_t> qp((size_t)nr + 1, 0);
+            // quads per row, counted into the row-pointer slots themselves
+            e = launch_quad_count(ptr[w], idx[w], s.nb, row0, nr, Q.ptr + row0, st);
+            if (e == hipSuccess && nr > 0)
+                e = hipMemcpyAsync(qp.data() + 1, Q.ptr + row0, 4 * (size_t)nr,
+                                   hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) return device_error("quad count", e);
+            for (int32_t r = 0; r < nr; ++r) qp[(size_t)r + 1] += qp[(size_t)r];
+            const int64_t nq = qp[(size_t)nr];
+            int64_t qb = 0;
+            if (nq > 0) {
+                qb = Q.alloc.take(nq);
+                if (qb < 0) {
+                    int rc = grow_quads(w, Q.cap + nq);
+                    if (rc) return rc;
+                    qb = Q.alloc.take(nq);
+                    if (qb < 0) return fail(CFR_ENOMEM, "quad stream exhausted");
+                }
+            }
+            e = hipMemcpyAsync(Q.ptr + row0, qp.data(), 4 * ((size_t)nr + 1),
+                               hipMemcpyHostToDevice, st);
+            if (e == hipSuccess)
+                e = launch_quad_fill(prec, ptr[w], idx[w], val[w], s.nb, row0, nr, Q.ptr, qb, Q.idx,
+                                     Q.val, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) return device_error("quad fill", e);
+            s.qb[w] = qb;
+            s.nq[w] = nq;
+            s.qptr[w] = std::move(qp);
+            partition(s, w);
+        }
+        drop_graph();
+    }
+    return CFR_OK;
 }
 
 int Engine::set_perm(int which, int on)
@@ -849,6 +969,11 @@ int Engine::set_perm(int which, int on)
     hipError_t e = hipStreamSynchronize(st);
     if (e != hipSuccess) return device_error("index remap", e);
     perm_on[which] = on;
+    // quad copies follow the numbering of the index stream
+    for (Slot &s : slots)
+        if (s.live) drop_quads(s, which);
+    it.valid = false;
+    ev.valid = false;
     drop_graph();
     return CFR_OK;
 }
@@ -1092,6 +1217,7 @@ void Engine::remove(int k)
         inf_alloc[p].give(s.ib[p], (int64_t)s.n_inf[p] + 1);
     }
     if (s.nnz > 0) nnz_alloc.give(s.nb, s.nnz);
+    for (int w = 0; w < 2; ++w) drop_quads(s, w);
     const bool was_active = s.active;
     s = Slot();
     if (was_active) {
@@ -1115,15 +1241,21 @@ bool Engine::tables_in_bounds(const Tables &T) const
     auto live = [&](int k) { return k >= 0 && k < (int)slots.size() && slots[(size_t)k].live; };
     for (int w = 0; w < 2; ++w) {
         const std::vector<SpmvBlock> &v = w == 0 ? T.h_csr : T.h_csc;
-        const int cap_nnz = spmv_block_cap(items[w]);
+        const int cap_nnz = spmv_block_cap_v(items[w], vec[w]);
+        const bool quads = vec[w] == 3;
+        if (quads && (items[w] != kQuadItems || !quad[w].idx)) {
+            for (const SpmvBlock &b : v)
+                if (b.n > 0) return false;
+        }
         for (const SpmvBlock &b : v) {
             if (!live(b.slot)) return false;
             const Slot &s = slots[(size_t)b.slot];
             if (b.nr < 1 || b.nr > kSpmvRowCap || b.n < 0 || (b.n > cap_nnz && b.nr != 1))
                 return false;
             if (b.row0 < s.sb[w] || (int64_t)b.row0 + b.nr > s.sb[w] + s.n_seq[w]) return false;
-            if (b.e0 < s.nb || b.e0 + b.n > s.nb + s.nnz) return false;
-            if (b.e0 - s.nb != b.p0) return false;
+            const int64_t base = quads ? s.qb[w] : s.nb, len = quads ? s.nq[w] : s.nnz;
+            if (base < 0 || b.e0 < base || b.e0 + b.n > base + len) return false;
+            if (b.e0 - base != b.p0) return false;
         }
     }
     for (int p = 0; p < 2; ++p) {
@@ -1162,6 +1294,8 @@ int Engine::build_tables(Tables &T, char *region, const std::vector<int> &set)
     // the previous upload may still be in flight
     hipError_t e = hipStreamSynchronize(st);
     if (e != hipSuccess) return device_error("table upload", e);
+    int qrc = ensure_quads(set);
+    if (qrc) return qrc;
     const double V = (double)value_bytes(prec);
     T.h_csr.clear();
     T.h_csc.clear();
@@ -1171,9 +1305,12 @@ int Engine::build_tables(Tables &T, char *region, const std::vector<int> &set)
         const Slot &s = slots[(size_t)k];
         T.h_csr.insert(T.h_csr.end(), s.blocks[0].begin(), s.blocks[0].end());
         T.h_csc.insert(T.h_csc.end(), s.blocks[1].begin(), s.blocks[1].end());
+        // stream bytes: each nonzero's index and value, or each quad's
+        // index and four values
         for (int w = 0; w < 2; ++w)
-            T.bytes[w] += (double)s.nnz * (4.0 + V) + 4.0 * (s.n_seq[w] + 1) +
-                          V * s.n_seq[1 - w] + V * s.n_seq[w];
+            T.bytes[w] += (vec[w] == 3 ? (double)s.nq[w] * (4.0 + 4.0 * V)
+                                       : (double)s.nnz * (4.0 + V)) +
+                          4.0 * (s.n_seq[w] + 1) + V * s.n_seq[1 - w] + V * s.n_seq[w];
     }
     std::vector<int> classes;
     for (int k : set) classes.push_back(slots[(size_t)k].gp.variant);
@@ -1288,23 +1425,25 @@ hipError_t Engine::spmv(const Tables &T, int which, const void *xin, void *yout,
         if (e != hipSuccess) return e;
         xin = dp[q].xp;
     }
+    const bool quads = vec[which] == 3;
+    const int32_t *rp = quads ? quad[which].ptr : ptr[which];
+    const int32_t *ix = quads ? (const int32_t *)quad[which].idx : idx[which];
+    const void *vl = quads ? quad[which].val : val[which];
     if (timed) {
         hipEvent_t a, b;
         hipError_t e = hipEventCreate(&a);
         if (e == hipSuccess) e = hipEventCreate(&b);
         if (e != hipSuccess) return e;
         (void)hipEventRecord(a, s);
-        e = launch_spmv(prec, items[which], vec[which], tab, n, ptr[which], idx[which], val[which],
-                        xin, yout,
-                        xcd_remap, sequential(), begin ? 1 : 0, sc, s);
+        e = launch_spmv(prec, items[which], vec[which], tab, n, rp, ix, vl, xin, yout, xcd_remap,
+                        sequential(), begin ? 1 : 0, sc, s);
         (void)hipEventRecord(b, s);
         events[which].emplace_back(a, b);
         launches[which]++;
         return e;
     }
-    return launch_spmv(prec, items[which], vec[which], tab, n, ptr[which], idx[which], val[which],
-                       xin, yout,
-                       xcd_remap, sequential(), begin ? 1 : 0, sc, s);
+    return launch_spmv(prec, items[which], vec[which], tab, n, rp, ix, vl, xin, yout, xcd_remap,
+                       sequential(), begin ? 1 : 0, sc, s);
 }
 
 hipError_t Engine::sweeps(const Tables &T, int p, double usign, hipStream_t s)

@@ -151,6 +151,16 @@ hipError_t launch_gather(int prec, const RangeBlock *tab, int32_t n_tab, const i
                          const void *src, void *dst, hipStream_t st);
 // a[i] = map[a[i]] for i < n.
 hipError_t launch_remap(int32_t *a, int64_t n, const int32_t *map, hipStream_t st);
+// Quad stream of one game's product (rows [row0, row0 + nr) of the global
+// row space; element row pointers `ptr` hold game-local offsets into the
+// index/value arrays at element base nb).  Count: quads of each row into
+// cnt[0 .. nr).  Fill: quads of row r from quad qb + qptr[row0 + r]
+// (qptr: game-local quad offsets at the global rows).
+hipError_t launch_quad_count(const int32_t *ptr, const int32_t *idx, int64_t nb, int32_t row0,
+                             int32_t nr, int32_t *cnt, hipStream_t st);
+hipError_t launch_quad_fill(int prec, const int32_t *ptr, const int32_t *idx, const void *val,
+                            int64_t nb, int32_t row0, int32_t nr, const int32_t *qptr, int64_t qb,
+                            uint32_t *qidx, void *qval, hipStream_t st);
 
 size_t value_bytes(int prec);
 size_t accum_bytes(int prec);
@@ -178,6 +188,16 @@ inline bool spmv_items_supported(int items) { return items == 4 || items == 8 ||
 // to three elements the 16-byte stream loads start before the block.
 __host__ __device__ constexpr int spmv_block_cap(int items) { return kSpmvThreads * items - 3; }
 constexpr int kStreamPad = 4;  // readable elements past the end of the index/value arrays
+// Stream form 3 (quads): element = quad index | presence mask << kQuadMaskShift
+constexpr int kQuadMaskShift = 28;
+constexpr uint32_t kQuadIndexMask = (1u << kQuadMaskShift) - 1;
+constexpr int kQuadItems = 16;  // the only items value of stream form 3 (1024 quads a block)
+constexpr int kVecPad = 4;      // readable entries past the end of every gathered vector
+// Stream elements one block of the product may hold under stream form vec.
+__host__ __device__ constexpr int spmv_block_cap_v(int items, int vec)
+{
+    return vec == 3 ? kSpmvThreads * items / 4 : spmv_block_cap(items);
+}
 constexpr int kRangeBlock = 256;  // decision points or sequences per sweep block
 // 1: run the shallow levels in one launch (k_top) even when deeper levels
 // remain as per-level launches

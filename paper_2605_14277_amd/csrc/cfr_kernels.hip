@@ -111,6 +111,23 @@ __device__ __forceinline__ void load4(const double *p, double (&o)[4])
     o[2] = b.x;
     o[3] = b.y;
 }
+// Four entries of a gathered vector (aligned to four), through the caches.
+__device__ __forceinline__ void load4_cached(const float *p, float (&o)[4])
+{
+    const v4f t = *(const v4f *)p;
+    o[0] = t.x;
+    o[1] = t.y;
+    o[2] = t.z;
+    o[3] = t.w;
+}
+__device__ __forceinline__ void load4_cached(const double *p, double (&o)[4])
+{
+    const v2d a = *(const v2d *)p, b = *((const v2d *)p + 1);
+    o[0] = a.x;
+    o[1] = a.y;
+    o[2] = b.x;
+    o[3] = b.y;
+}
 __device__ __forceinline__ void store4(float *p, const float (&o)[4])
 {
     *(v4f *)p = v4f{o[0], o[1], o[2], o[3]};
@@ -167,6 +184,15 @@ __device__ void begin_iteration(Scalars *sc)
 // 256-element chunks around through LDS, so that one gather instruction
 // reads 64 consecutive elements (whose column indices lie close together).
 // VEC 0: every element is its own 4-byte load, consecutive across lanes.
+// VEC 3: the stream is in quads (a derived copy of the matrix): each element
+// is a run of at most four nonzeros of one row, in row order, whose columns
+// lie in one aligned group of four (quad index | presence mask << 28), with
+// four values (any value where the mask is clear); one aligned 16-byte
+// gather fetches the four input entries.  Absent positions stage -0.0,
+// which leaves every sum unchanged (x + -0.0 == x exactly, signed zeros
+// included), so the row sums are exactly those of the nonzeros in row
+// order.  Row pointers and block extents count quads; staging slot 4*q + k
+// holds position k of quad q.
 //
 // Each table entry gives a block's rows, nonzeros and game in one scalar
 // load.  The loads of a block are all issued
@@ -205,11 +231,23 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(
     const int32_t rb = bk.row0, nr = bk.nr, n = bk.n, p0 = bk.p0;
     const int64_t e0 = bk.e0;
 
-    if (n > spmv_block_cap(ITEMS)) {
+    constexpr int32_t kBlockCap = VEC == 3 ? kSpmvThreads * ITEMS / 4 : spmv_block_cap(ITEMS);
+    if (n > kBlockCap) {
         // a single long row: strided partial sums, then a fixed-order tree
         C acc = 0;
-        for (int32_t i = tid; i < n; i += kSpmvThreads)
-            acc = acc + (C)val[e0 + i] * (C)xin[idx[e0 + i]];
+        if (VEC == 3) {
+            for (int32_t i = tid; i < n; i += kSpmvThreads) {
+                const uint32_t qd = (uint32_t)idx[e0 + i];
+                const int64_t c0 = 4 * (int64_t)(qd & kQuadIndexMask);
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if ((qd >> (kQuadMaskShift + k)) & 1u)
+                        acc = acc + (C)val[4 * (e0 + i) + k] * (C)xin[c0 + k];
+            }
+        } else {
+            for (int32_t i = tid; i < n; i += kSpmvThreads)
+                acc = acc + (C)val[e0 + i] * (C)xin[idx[e0 + i]];
+        }
         red[tid] = acc;
         __syncthreads();
         for (int w = kSpmvThreads / 2; w > 0; w >>= 1) {
@@ -224,7 +262,37 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(
     // kSpmvRowCap = kSpmvThreads rows)
     const int32_t pr = ptr[rb + (tid < nr ? tid : 0)];
     int32_t sh = 0;  // staging offset of the block's first element
-    if (VEC == 2) {
+    int32_t per = 1;  // staging slots per stream element
+    if (VEC == 3) {
+        constexpr int NQ = ITEMS / 4;
+        per = 4;
+        if (n > 0) {
+            uint32_t qd[NQ];
+            V v4[NQ][4];
+#pragma unroll
+            for (int j = 0; j < NQ; ++j) {
+                const int32_t qi = j * kSpmvThreads + tid;
+                const int64_t at = e0 + (qi < n ? qi : 0);
+                qd[j] = (uint32_t)__builtin_nontemporal_load(idx + at);
+                load4(val + 4 * at, v4[j]);
+            }
+            V gx[NQ][4];
+#pragma unroll
+            for (int j = 0; j < NQ; ++j)
+                load4_cached(xin + 4 * (int64_t)(qd[j] & kQuadIndexMask), gx[j]);
+#pragma unroll
+            for (int j = 0; j < NQ; ++j) {
+                const int32_t qi = j * kSpmvThreads + tid;
+                L o[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    o[k] = (qi < n && ((qd[j] >> (kQuadMaskShift + k)) & 1u))
+                               ? (L)((C)v4[j][k] * (C)gx[j][k])
+                               : (L)(-0.0);
+                store4(&prod[4 * qi], o);
+            }
+        }
+    } else if (VEC == 2) {
         constexpr int NV = ITEMS / 4;
         const int64_t e_al = e0 & ~(int64_t)3;
         sh = (int32_t)(e0 - e_al);
@@ -360,8 +428,8 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(
             if (i < n) prod[i] = (L)((C)v[k] * (C)gx[k]);
         }
     }
-    if (tid < nr) s_ptr[tid] = pr - p0 + sh;
-    if (tid == 0) s_ptr[nr] = n + sh;
+    if (tid < nr) s_ptr[tid] = per * (pr - p0) + sh;
+    if (tid == 0) s_ptr[nr] = per * n + sh;
     __syncthreads();
     if (SEQ) {
         if (tid < nr) {
@@ -384,7 +452,7 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(
     // row of the block its own group, and not far above the mean row length
     int Lr = 64;
     while (Lr > 1 && Lr * nr > kSpmvThreads) Lr >>= 1;
-    while (Lr > 1 && Lr > 2 * (n / nr + 1)) Lr >>= 1;
+    while (Lr > 1 && Lr > 2 * (per * n / nr + 1)) Lr >>= 1;
     const int lane = tid & (Lr - 1);
     const int groups = kSpmvThreads / Lr;
     for (int32_t r = tid / Lr; r < nr; r += groups) {
@@ -983,6 +1051,63 @@ __global__ __launch_bounds__(kThreads) void k_remap(int32_t *a, int64_t n,
 }
 
 // ---------------------------------------------------------------------------
+// Quad stream construction (stream form 3)
+// ---------------------------------------------------------------------------
+
+// A row's quads: maximal runs of consecutive nonzeros (in row order) whose
+// columns increase and share one aligned group of four.
+__global__ __launch_bounds__(kThreads) void k_quad_count(const int32_t *__restrict__ ptr,
+                                                         const int32_t *__restrict__ idx,
+                                                         int64_t nb, int32_t row0, int32_t nr,
+                                                         int32_t *__restrict__ cnt)
+{
+    const int32_t r = (int32_t)(blockIdx.x * kThreads + threadIdx.x);
+    if (r >= nr) return;
+    const int32_t a = ptr[row0 + r], z = ptr[row0 + r + 1];
+    int32_t c = 0, prev = -1;
+    for (int32_t e = a; e < z; ++e) {
+        const int32_t col = idx[nb + e];
+        if (c == 0 || (col >> 2) != (prev >> 2) || col <= prev) ++c;
+        prev = col;
+    }
+    cnt[r] = c;
+}
+
+template <int P>
+__global__ __launch_bounds__(kThreads) void k_quad_fill(
+    const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+    const typename Types<P>::V *__restrict__ val, int64_t nb, int32_t row0, int32_t nr,
+    const int32_t *__restrict__ qptr, int64_t qb, uint32_t *__restrict__ qidx,
+    typename Types<P>::V *__restrict__ qval)
+{
+    using V = typename Types<P>::V;
+    const int32_t r = (int32_t)(blockIdx.x * kThreads + threadIdx.x);
+    if (r >= nr) return;
+    const int32_t a = ptr[row0 + r], z = ptr[row0 + r + 1];
+    int64_t q = qb + qptr[row0 + r];
+    uint32_t mask = 0;
+    int32_t prev = -1;
+    V v[4] = {0, 0, 0, 0};
+    auto emit = [&]() {
+        qidx[q] = (uint32_t)(prev >> 2) | (mask << kQuadMaskShift);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) qval[4 * q + k] = v[k];
+        ++q;
+        mask = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = 0;
+    };
+    for (int32_t e = a; e < z; ++e) {
+        const int32_t col = idx[nb + e];
+        if (mask != 0 && ((col >> 2) != (prev >> 2) || col <= prev)) emit();
+        v[col & 3] = val[nb + e];
+        mask |= 1u << (col & 3);
+        prev = col;
+    }
+    if (mask != 0) emit();
+}
+
+// ---------------------------------------------------------------------------
 // Launch helpers
 // ---------------------------------------------------------------------------
 
@@ -1040,6 +1165,9 @@ hipError_t spmv_t(int items, int vec, const SpmvBlock *tab, int32_t n_tab, const
                                     begin, sc, st);                                           \
     case 2:                                                                                   \
         return spmv_items<P, SQ, 2>(items, tab, n_tab, ptr, idx, val, xin, yout, xcd_remap,   \
+                                    begin, sc, st);                                           \
+    case 3:                                                                                   \
+        return spmv_items<P, SQ, 3>(items, tab, n_tab, ptr, idx, val, xin, yout, xcd_remap,   \
                                     begin, sc, st);                                           \
     default: return hipErrorInvalidValue;                                                     \
     }
@@ -1285,6 +1413,35 @@ hipError_t launch_gather(int prec, const RangeBlock *tab, int32_t n_tab, const i
                          const void *src, void *dst, hipStream_t st)
 {
     CFR_DISPATCH(prec, gather_t<P>(tab, n_tab, perm, src, dst, st));
+}
+
+hipError_t launch_quad_count(const int32_t *ptr, const int32_t *idx, int64_t nb, int32_t row0,
+                             int32_t nr, int32_t *cnt, hipStream_t st)
+{
+    if (nr <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_quad_count, dim3((unsigned)((nr + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, st, ptr, idx, nb, row0, nr, cnt);
+    return hipGetLastError();
+}
+
+template <int P>
+hipError_t quad_fill_t(const int32_t *ptr, const int32_t *idx, const void *val, int64_t nb,
+                       int32_t row0, int32_t nr, const int32_t *qptr, int64_t qb, uint32_t *qidx,
+                       void *qval, hipStream_t st)
+{
+    using V = typename Types<P>::V;
+    if (nr <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_quad_fill<P>), dim3((unsigned)((nr + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, st, ptr, idx, (const V *)val, nb, row0, nr, qptr, qb,
+                       qidx, (V *)qval);
+    return hipGetLastError();
+}
+
+hipError_t launch_quad_fill(int prec, const int32_t *ptr, const int32_t *idx, const void *val,
+                            int64_t nb, int32_t row0, int32_t nr, const int32_t *qptr, int64_t qb,
+                            uint32_t *qidx, void *qval, hipStream_t st)
+{
+    CFR_DISPATCH(prec, quad_fill_t<P>(ptr, idx, val, nb, row0, nr, qptr, qb, qidx, qval, st));
 }
 
 hipError_t launch_remap(int32_t *a, int64_t n, const int32_t *map, hipStream_t st)

@@ -143,11 +143,20 @@ def test_targets_stop_games_at_checks(cfr, mix):
     b.close()
 
 
-def test_games_join_and_leave(cfr, mix):
+QUADS = {"items": [16, 16], "rows": [256, 256], "vec": [3, 3], "perm": [0, 1]}
+
+
+@pytest.mark.parametrize("tiling", [None, QUADS], ids=["elements", "quads"])
+def test_games_join_and_leave(cfr, mix, tiling):
+    """Games join at checks and leave between them; their ranges (and, in
+    stream form 3, their quad copies) are reused, and every game still
+    equals the same game solved alone."""
     K = 10
     pool = {name: (g, v) for name, g, v in mix}
     b = make_batch(cfr, [pool[n][0] for n in ("cfg1", "stops", "s2d3", "cfg2_d8")],
                    max_games=4, precision="fp64", mode="alternating", check_every=K)
+    if tiling is not None:
+        b.tiling = tiling
     g1 = b.add(*pool["cfg1"])
     g2 = b.add(*pool["stops"])
     b.run(30)
@@ -202,7 +211,9 @@ def test_tiling_and_tuner(cfr, mix):
                    {"items": [16, 4], "rows": [256, 64], "vec": [1, 0], "perm": [0, 1]},
                    {"items": [8, 8], "rows": [128, 128], "vec": [1, 1], "perm": [1, 1]},
                    {"items": [16, 8], "rows": [256, 128], "vec": [2, 2], "perm": [0, 1]},
-                   {"items": [4, 16], "rows": [64, 256], "vec": [2, 0], "perm": [1, 0]}, "tune"):
+                   {"items": [4, 16], "rows": [64, 256], "vec": [2, 0], "perm": [1, 0]},
+                   {"items": [16, 16], "rows": [256, 64], "vec": [3, 3], "perm": [0, 1]},
+                   {"items": [16, 8], "rows": [128, 256], "vec": [3, 2], "perm": [1, 1]}, "tune"):
         b = make_batch(cfr, games, max_games=len(mix), precision="fp64")
         ids = [b.add(g, v) for _, g, v in mix]
         if tiling == "tune":
@@ -210,7 +221,7 @@ def test_tiling_and_tuner(cfr, mix):
             say(f"  tuner chose {chosen}")
             assert all(i in (4, 8, 16) for i in chosen["items"])
             assert all(64 <= r <= 256 for r in chosen["rows"])
-            assert all(v in (0, 1, 2) for v in chosen["vec"])
+            assert all(v in (0, 1, 2, 3) for v in chosen["vec"])
             assert all(v in (0, 1) for v in chosen["perm"])
         elif tiling is not None:
             b.tiling = tiling
@@ -274,7 +285,8 @@ def test_chain_top_down_pass_equals_level_by_level(cfr, mix, precision):
             assert np.array_equal(a, b), (name, precision)
 
 
-def test_asynchronous_admission(cfr, mix):
+@pytest.mark.parametrize("tiling", [None, QUADS], ids=["elements", "quads"])
+def test_asynchronous_admission(cfr, mix, tiling):
     """Admission copies run on their own stream: a game added while others
     iterate joins at the next check, one added to an idle batch at once, and
     every game still equals the same game solved alone."""
@@ -285,6 +297,8 @@ def test_asynchronous_admission(cfr, mix):
     units = np.sum([preps[n].units for n in names], axis=0)
     b = cfr.Batch([units[0], units[1]], [units[2], units[3]], int(units[4]), max_games=4,
                   precision="fp64", check_every=10, async_admission=True)
+    if tiling is not None:
+        b.tiling = tiling
     g1 = serve.add_prepared(b, preps["cfg1"], pool["cfg1"][1])
     assert b.status(g1)["state"] == "active"  # idle batch: joins at once
     b.run(20)
@@ -318,6 +332,7 @@ def test_many_games_in_one_batch(cfr, mix):
                 entries.append((name, g, v))
     b = make_batch(cfr, [g for _, g, _ in entries], max_games=len(entries), precision="fp32_acc64",
                    check_every=10)
+    b.tiling = QUADS  # the same tiling for the lone solves below
     ids = [b.add(g, v) for _, g, v in entries]
     b.run(30)
     seen = set()
@@ -325,7 +340,9 @@ def test_many_games_in_one_batch(cfr, mix):
         if (name, v) in seen:
             continue
         seen.add((name, v))
-        solo = lone(cfr, g, v, "alternating", 30, "fp32_acc64")
+        solo = cfr.Solver(g, precision="fp32_acc64")
+        solo.tiling = QUADS
+        solo.step(30, v, "alternating")
         assert_same(b, gid, solo, f"{name}/{v}")
         solo.close()
     b.close()

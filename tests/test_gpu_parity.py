@@ -280,6 +280,76 @@ def test_long_rows(cfr, oracle_mod, cols):
     compare_fp64(gpu, orc, tol=1e-12, what=f"3x{cols}")
 
 
+QUADS = {"items": [16, 16], "rows": [256, 128], "vec": [3, 3], "perm": [0, 1]}
+
+
+@pytest.mark.parametrize("cols", [1023, 4096, 4100, 9000])
+def test_long_rows_quads(cfr, oracle_mod, cols):
+    """Stream form 3 (quads): a block holds 1024 quads, so rows of 4096
+    nonzeros still fit and longer ones take the long-row path."""
+    rng = np.random.default_rng(cols)
+    M = rng.uniform(-1, 1, size=(3, cols))
+    g = gg.matrix_game(M)
+    say(f"case: matrix game 3x{cols}, quads")
+    gpu = cfr.Solver(g, precision="fp64")
+    gpu.tiling = QUADS
+    orc = oracle_mod.Oracle(g)
+    gpu.step(100, "cfr+", "alternating")
+    orc.step(100, "cfr+", "alternating")
+    compare_fp64(gpu, orc, tol=1e-12, what=f"3x{cols}-quads")
+
+
+@pytest.mark.parametrize("name", ["stops", "cfg2_d8", "showdown", "cfg2"])
+def test_quads_fp64_equal_elementwise(cfr, oracle_mod, games, name):
+    """Absent quad positions add -0.0, which leaves every FP64 row sum exactly
+    as the element stream gives it: the two forms agree bit for bit, and
+    both match the oracle."""
+    if name == "showdown":
+        g = gg.public_game(4, S=6, max_depth=6, branch_lo=2, branch_hi=4, p_stop=0.1,
+                           payoff_kind="showdown")
+    elif name == "cfg2":
+        g = gg.cfg2()
+    else:
+        g = games[name] if name in games else gg.make_config(name)
+    say(f"case: {name} quads vs elements, fp64, nnz={g.nnz}")
+    out = []
+    for tiling in (None, QUADS, dict(QUADS, perm=[1, 0], rows=[64, 256])):
+        gpu = cfr.Solver(g, precision="fp64")
+        if tiling is not None:
+            gpu.tiling = tiling
+            assert gpu.tiling == tiling
+        gpu.step(60, "dcfr", "alternating")
+        out.append([gpu.strategy(p, k) for p in range(2) for k in ("current", "average")] +
+                   [gpu.regrets(p) for p in range(2)])
+        last = gpu
+    for other in out[1:]:
+        for a, c in zip(out[0], other):
+            assert np.array_equal(a, c)
+    orc = oracle_mod.Oracle(g)
+    orc.step(60, "dcfr", "alternating")
+    compare_fp64(last, orc, tol=1e-9, what=f"{name}-quads")
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp32_acc64"])
+def test_quads_fp32_short_horizon(cfr, oracle_mod, precision):
+    """Stream form 3 in the FP32 modes tracks the FP64 oracle on the same
+    float32 payoffs within 1e-4."""
+    g = gg.cfg2()
+    gpu = cfr.Solver(g, precision=precision)
+    gpu.tiling = QUADS
+    orc = oracle_mod.Oracle(_float_rounded(g))
+    for n in (1, 2, 2):
+        gpu.step(n, "cfr+", "alternating")
+        orc.step(n, "cfr+", "alternating")
+        for p in range(2):
+            for kind in ("current", "average"):
+                d = float(np.max(np.abs(gpu.strategy(p, kind) - orc.strategy(p, kind))))
+                assert d <= 1e-4, (gpu.iteration, p, kind, d)
+        d = abs(gpu.exploitability()["expl"] - orc.exploitability()["expl"])
+        say(f"[{precision} quads] t={gpu.iteration} expl err {d:.2e}")
+        assert d <= 1e-4
+
+
 def test_player_without_decisions(cfr, oracle_mod):
     from test_oracle_pins import _decision_problem
     g = _decision_problem()
