@@ -193,9 +193,11 @@ struct Tables {
     int32_t n_csr = 0, n_csc = 0, n_seq[2] = {0, 0}, n_root[2] = {0, 0}, n_fin = 0;
     int32_t n_dall[2] = {0, 0};
     int dall_depth[2] = {0, 0};  // levels of the deepest game (its longest parent chain)
+    RangeBlock dall_direct[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};  // hi > lo: one game's range
     struct Up {
         int32_t off, n;
         int variant, kind;
+        RangeBlock direct;  // hi > lo: the whole launch is this one range of one game
     };
     std::vector<std::vector<Up>> up_l[2];                      // per level: one launch per variant
     std::vector<std::pair<int32_t, int32_t>> up_level[2];      // per level: all of its entries

@@ -1346,7 +1346,15 @@ int Engine::build_tables(Tables &T, char *region, const std::vector<int> &set)
                     kind = std::min(kind, (int)s.lvl_kind[p][L]);
                 }
                 const int32_t n = (int32_t)T.h_up[p].size() - off;
-                if (n > 0) T.up_l[p][L].push_back(Tables::Up{off, n, c, kind});
+                // a launch over one game's level: its range goes by value
+                RangeBlock dr{0, 0, 0, 0};
+                if (set.size() == 1) {
+                    const Slot &s = slots[(size_t)set[0]];
+                    dr = RangeBlock{(int32_t)(s.ib[p] + s.lvl_inf[p][L]),
+                                    (int32_t)(s.ib[p] + s.lvl_inf[p][L + 1]), set[0],
+                                    (int32_t)s.lvl_slots[p][L]};
+                }
+                if (n > 0) T.up_l[p][L].push_back(Tables::Up{off, n, c, kind, dr});
             }
             T.up_level[p][L] = {lvl_start, (int32_t)T.h_up[p].size() - lvl_start};
             if (L > 0) {
@@ -1378,6 +1386,14 @@ int Engine::build_tables(Tables &T, char *region, const std::vector<int> &set)
             return fail(CFR_EINVAL, "internal: sweep tables exceed their capacity");
         T.n_seq[p] = (int32_t)T.h_seq[p].size();
         T.n_dall[p] = (int32_t)T.h_dall[p].size();
+        T.dall_direct[p] = RangeBlock{0, 0, 0, 0};
+        if (set.size() == 1) {
+            const Slot &s = slots[(size_t)set[0]];
+            if (s.n_levels[p] > 1)
+                T.dall_direct[p] = RangeBlock{(int32_t)(s.sb[p] + s.lvl_seq[p][1]),
+                                              (int32_t)(s.sb[p] + s.n_seq[p]), set[0],
+                                              (int32_t)s.sb[p]};
+        }
         T.n_root[p] = (int32_t)T.h_root[p].size();
     }
     if ((int64_t)T.h_csr.size() > cap.t_csr || (int64_t)T.h_csc.size() > cap.t_csc)
@@ -1457,7 +1473,8 @@ hipError_t Engine::sweeps(const Tables &T, int p, double usign, hipStream_t s)
     // top-down step)
     for (int L = maxL - 1; L >= low; --L)
         for (const Tables::Up &u : T.up_l[p][(size_t)L])
-            if ((e = launch_up(prec, u.variant, u.kind, L == 0 ? 1 : 0, T.up[p] + u.off, u.n, d,
+            if ((e = launch_up(prec, u.variant, u.kind, L == 0 ? 1 : 0, T.up[p] + u.off, u.n,
+                               &u.direct, d,
                                usign, sc, s)) != hipSuccess)
                 return e;
     if (top) {
@@ -1465,7 +1482,8 @@ hipError_t Engine::sweeps(const Tables &T, int p, double usign, hipStream_t s)
         if ((e = launch_top(prec, slots[0].gp.variant, d, usign, 1, sc, s)) != hipSuccess) return e;
     }
     if (!top && down_pass == CFR_DOWN_DEFAULT && T.dall_depth[p] <= kDownAllMaxDepth)
-        return launch_down_all(prec, T.dall_depth[p], T.dall[p], T.n_dall[p], d, 1, sc, s);
+        return launch_down_all(prec, T.dall_depth[p], T.dall[p], T.n_dall[p], &T.dall_direct[p], d,
+                               1, sc, s);
     for (int L = std::max(low, 1); L < maxL; ++L) {
         const auto &dl = T.down_l[p][(size_t)L];
         if ((e = launch_down(prec, T.down[p] + dl.first, dl.second, d, 1, sc, s)) != hipSuccess)

@@ -112,10 +112,12 @@ hipError_t launch_spmv(int prec, int items, int vec, const SpmvBlock *tab, int32
 // ObserveUtility on the decision points of `tab` (one level), fused with the
 // variant's post-step and regret matching; kind 0 generic, 1 fast, 2 fast
 // without children; root: the level under the empty sequence, whose
-// top-down step (with averaging) is done in the same launch.
+// top-down step (with averaging) is done in the same launch.  direct (may be
+// null; host memory): one game's whole range [lo, hi) with its slot and aux,
+// used instead of the table (blocks of kRangeBlock, no table load).
 hipError_t launch_up(int prec, int variant, int kind, int root, const RangeBlock *tab,
-                     int32_t n_tab, const DevPlayer &p, double usign, const Scalars *sc,
-                     hipStream_t st);
+                     int32_t n_tab, const RangeBlock *direct, const DevPlayer &p, double usign,
+                     const Scalars *sc, hipStream_t st);
 // Top-down pass over the sequences of `tab` (one level).
 hipError_t launch_down(int prec, const RangeBlock *tab, int32_t n_tab, const DevPlayer &p,
                        int average, const Scalars *sc, hipStream_t st);
@@ -123,7 +125,8 @@ hipError_t launch_down(int prec, const RangeBlock *tab, int32_t n_tab, const Dev
 // of `tab` (aux = its game's empty sequence) multiplies the behavioural
 // strategies of its at most max_depth (<= kDownAllMaxDepth) ancestors.
 hipError_t launch_down_all(int prec, int max_depth, const RangeBlock *tab, int32_t n_tab,
-                           const DevPlayer &p, int average, const Scalars *sc, hipStream_t st);
+                           const RangeBlock *direct, const DevPlayer &p, int average,
+                           const Scalars *sc, hipStream_t st);
 // ObserveUtility on levels top_levels-1..0, then the top-down pass on levels
 // 0..top_levels-1 (with averaging when `average`) of the game in slot 0.
 hipError_t launch_top(int prec, int variant, const DevPlayer &p, double usign, int average,
@@ -208,7 +211,7 @@ constexpr int kDownAllMaxDepth = 16;  // longest parent chain of the one-launch 
 // value-slot flags of a bottom-up table entry (RangeBlock::aux)
 constexpr int kSlotsWrite = 1;  // the level's decision points store values in parent slots
 constexpr int kSlotsRead = 2;   // the level reads its children's values from slots
-constexpr int32_t kSlotLevelMax = 65536;  // largest level (per game) that writes slots
+constexpr int32_t kSlotLevelMax = 262144;  // largest level (per game) that writes slots
 constexpr int kFastActs = 4;        // fast sweep path: actions per decision point
 constexpr int kFastKids = 4;        // fast sweep path: decision points below a sequence
 constexpr int kTopThreads = 1024;   // threads of the shallow-level block

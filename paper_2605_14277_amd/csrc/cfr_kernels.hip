@@ -719,17 +719,19 @@ __device__ __forceinline__ void down_infoset(int32_t j, const int32_t *__restric
                                              const typename Types<P>::V *__restrict__ b,
                                              typename Types<P>::V *__restrict__ x,
                                              typename Types<P>::R *__restrict__ s,
-                                             typename Types<P>::R w, int average)
+                                             typename Types<P>::R w, int average,
+                                             bool parent_is_root = false)
 {
     using V = typename Types<P>::V;
     using R = typename Types<P>::R;
     const int32_t a0 = inf_first[j], a1 = inf_first[j + 1];
     const int32_t n = a1 - a0;
     if (n <= kFastActs) {
-        // all loads at once (clamped addresses), then the stores
+        // all loads at once (clamped addresses), then the stores; under the
+        // empty sequence the parent's realisation weight is exactly 1
         V bv[kFastActs], xv[kFastActs];
         R sv[kFastActs];
-        const V xp = x[seq_par[a0]];
+        const V xp = parent_is_root ? (V)1 : x[seq_par[a0]];
 #pragma unroll
         for (int k = 0; k < kFastActs; ++k) {
             const int32_t a = a0 + (k < n ? k : 0);
@@ -746,11 +748,24 @@ __device__ __forceinline__ void down_infoset(int32_t j, const int32_t *__restric
         }
         return;
     }
-    const V xp = x[seq_par[a0]];
+    const V xp = parent_is_root ? (V)1 : x[seq_par[a0]];
     for (int32_t a = a0; a < a1; ++a) {
         if (average) s[a] = s[a] + w * (R)x[a];
         x[a] = xp * b[a];
     }
+}
+
+// The range of one block of a sweep launch: the table's entry, or with a
+// direct range (hi > lo: one game's contiguous range, passed by value) the
+// block's share of it, which saves the dependent load of the entry.
+__device__ __forceinline__ RangeBlock block_range(const RangeBlock *__restrict__ tab,
+                                                  const RangeBlock &dr)
+{
+    if (dr.hi > dr.lo) {
+        const int32_t lo = dr.lo + (int32_t)blockIdx.x * kRangeBlock;
+        return RangeBlock{lo, min(lo + kRangeBlock, dr.hi), dr.slot, dr.aux};
+    }
+    return tab[blockIdx.x];
 }
 
 // One level of ObserveUtility over the decision points of the table's
@@ -766,11 +781,12 @@ __global__ __launch_bounds__(kThreads) void k_up(
     typename Types<P>::C *__restrict__ vinf, typename Types<P>::V *__restrict__ b,
     typename Types<P>::R *__restrict__ r, typename Types<P>::R *__restrict__ m,
     const Scalars *__restrict__ sc, const int32_t *__restrict__ seq_par,
-    typename Types<P>::V *__restrict__ x, typename Types<P>::R *__restrict__ s, Kids<P> kd)
+    typename Types<P>::V *__restrict__ x, typename Types<P>::R *__restrict__ s, Kids<P> kd,
+    RangeBlock dr)
 {
     using R = typename Types<P>::R;
     using C = typename Types<P>::C;
-    const RangeBlock rb = tab[blockIdx.x];
+    const RangeBlock rb = block_range(tab, dr);
     const int32_t j = rb.lo + (int32_t)threadIdx.x;
     if (j >= rb.hi) return;
     const Scalars *gs = sc + rb.slot;
@@ -799,7 +815,7 @@ __global__ __launch_bounds__(kThreads) void k_up(
     case kSlotsRead: level(std::integral_constant<int, kSlotsRead>()); break;
     default: level(std::integral_constant<int, kSlotsWrite | kSlotsRead>()); break;
     }
-    if (ROOT) down_infoset<P>(j, inf_first, seq_par, b, x, s, (R)gs->w, 1);
+    if (ROOT) down_infoset<P>(j, inf_first, seq_par, b, x, s, (R)gs->w, 1, true);
 }
 
 // The shallow levels of one player in one launch: block `root` owns the
@@ -887,11 +903,12 @@ __global__ __launch_bounds__(kThreads) void k_down_all(const RangeBlock *__restr
                                                        const typename Types<P>::V *__restrict__ b,
                                                        typename Types<P>::V *__restrict__ x,
                                                        typename Types<P>::R *__restrict__ s,
-                                                       const Scalars *__restrict__ sc, int average)
+                                                       const Scalars *__restrict__ sc, int average,
+                                                       RangeBlock dr)
 {
     using V = typename Types<P>::V;
     using R = typename Types<P>::R;
-    const RangeBlock rb = tab[blockIdx.x];
+    const RangeBlock rb = block_range(tab, dr);
     const int32_t i = rb.lo + (int32_t)threadIdx.x;
     if (i >= rb.hi) return;
     const int32_t root = rb.aux;
@@ -1178,44 +1195,53 @@ hipError_t spmv_t(int items, int vec, const SpmvBlock *tab, int32_t n_tab, const
 #undef CFR_SPMV_VEC
 }
 
+// Blocks of a sweep launch: the table's entries, or those of the direct range.
+inline unsigned sweep_grid(int32_t n_tab, const RangeBlock &dr)
+{
+    if (dr.hi > dr.lo) return (unsigned)((dr.hi - dr.lo + kRangeBlock - 1) / kRangeBlock);
+    return (unsigned)n_tab;
+}
+
 template <int P, int VAR, int KIND, bool ROOT>
-hipError_t up_launch(const RangeBlock *tab, int32_t n_tab, const DevPlayer &p, double usign,
-                     const Scalars *sc, hipStream_t st)
+hipError_t up_launch(const RangeBlock *tab, int32_t n_tab, const RangeBlock &dr,
+                     const DevPlayer &p, double usign, const Scalars *sc, hipStream_t st)
 {
     using T = Types<P>;
-    hipLaunchKernelGGL((k_up<P, VAR, KIND, ROOT>), dim3((unsigned)n_tab), dim3(kThreads), 0, st,
-                       tab, p.inf_first, p.child_ptr, p.child_idx, (const typename T::V *)p.g,
+    hipLaunchKernelGGL((k_up<P, VAR, KIND, ROOT>), dim3(sweep_grid(n_tab, dr)), dim3(kThreads), 0,
+                       st, tab, p.inf_first, p.child_ptr, p.child_idx, (const typename T::V *)p.g,
                        (typename T::C)usign, (typename T::C *)p.vinf, (typename T::V *)p.b,
                        (typename T::R *)p.r, (typename T::R *)p.m, sc, p.seq_par,
-                       (typename T::V *)p.x, (typename T::R *)p.s, kids<P>(p));
+                       (typename T::V *)p.x, (typename T::R *)p.s, kids<P>(p), dr);
     return hipGetLastError();
 }
 
 template <int P, int VAR>
-hipError_t up_t(int kind, int root, const RangeBlock *tab, int32_t n_tab, const DevPlayer &p,
-                double usign, const Scalars *sc, hipStream_t st)
+hipError_t up_t(int kind, int root, const RangeBlock *tab, int32_t n_tab, const RangeBlock &dr,
+                const DevPlayer &p, double usign, const Scalars *sc, hipStream_t st)
 {
-    if (n_tab <= 0) return hipSuccess;
+    if (sweep_grid(n_tab, dr) == 0) return hipSuccess;
     if (root) {
-        if (kind == 1) return up_launch<P, VAR, 1, true>(tab, n_tab, p, usign, sc, st);
-        if (kind == 2) return up_launch<P, VAR, 2, true>(tab, n_tab, p, usign, sc, st);
-        return up_launch<P, VAR, 0, true>(tab, n_tab, p, usign, sc, st);
+        if (kind == 1) return up_launch<P, VAR, 1, true>(tab, n_tab, dr, p, usign, sc, st);
+        if (kind == 2) return up_launch<P, VAR, 2, true>(tab, n_tab, dr, p, usign, sc, st);
+        return up_launch<P, VAR, 0, true>(tab, n_tab, dr, p, usign, sc, st);
     }
-    if (kind == 1) return up_launch<P, VAR, 1, false>(tab, n_tab, p, usign, sc, st);
-    if (kind == 2) return up_launch<P, VAR, 2, false>(tab, n_tab, p, usign, sc, st);
-    return up_launch<P, VAR, 0, false>(tab, n_tab, p, usign, sc, st);
+    if (kind == 1) return up_launch<P, VAR, 1, false>(tab, n_tab, dr, p, usign, sc, st);
+    if (kind == 2) return up_launch<P, VAR, 2, false>(tab, n_tab, dr, p, usign, sc, st);
+    return up_launch<P, VAR, 0, false>(tab, n_tab, dr, p, usign, sc, st);
 }
 
 template <int P>
 hipError_t up_dispatch(int variant, int kind, int root, const RangeBlock *tab, int32_t n_tab,
-                       const DevPlayer &p, double usign, const Scalars *sc, hipStream_t st)
+                       const RangeBlock &dr, const DevPlayer &p, double usign, const Scalars *sc,
+                       hipStream_t st)
 {
     switch (variant) {
-    case CFR_VANILLA: return up_t<P, CFR_VANILLA>(kind, root, tab, n_tab, p, usign, sc, st);
-    case CFR_PLUS: return up_t<P, CFR_PLUS>(kind, root, tab, n_tab, p, usign, sc, st);
-    case CFR_DCFR: return up_t<P, CFR_DCFR>(kind, root, tab, n_tab, p, usign, sc, st);
-    case CFR_PCFR_PLUS: return up_t<P, CFR_PCFR_PLUS>(kind, root, tab, n_tab, p, usign, sc, st);
-    case CFR_PCFR: return up_t<P, CFR_PCFR>(kind, root, tab, n_tab, p, usign, sc, st);
+    case CFR_VANILLA: return up_t<P, CFR_VANILLA>(kind, root, tab, n_tab, dr, p, usign, sc, st);
+    case CFR_PLUS: return up_t<P, CFR_PLUS>(kind, root, tab, n_tab, dr, p, usign, sc, st);
+    case CFR_DCFR: return up_t<P, CFR_DCFR>(kind, root, tab, n_tab, dr, p, usign, sc, st);
+    case CFR_PCFR_PLUS:
+        return up_t<P, CFR_PCFR_PLUS>(kind, root, tab, n_tab, dr, p, usign, sc, st);
+    case CFR_PCFR: return up_t<P, CFR_PCFR>(kind, root, tab, n_tab, dr, p, usign, sc, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1261,19 +1287,20 @@ hipError_t down_t(const RangeBlock *tab, int32_t n_tab, const DevPlayer &p, int 
 }
 
 template <int P>
-hipError_t down_all_t(int maxd, const RangeBlock *tab, int32_t n_tab, const DevPlayer &p,
-                      int average, const Scalars *sc, hipStream_t st)
+hipError_t down_all_t(int maxd, const RangeBlock *tab, int32_t n_tab, const RangeBlock &dr,
+                      const DevPlayer &p, int average, const Scalars *sc, hipStream_t st)
 {
     using T = Types<P>;
-    if (n_tab <= 0) return hipSuccess;
+    const unsigned grid = sweep_grid(n_tab, dr);
+    if (grid == 0) return hipSuccess;
     if (maxd <= 8)
-        hipLaunchKernelGGL((k_down_all<P, 8>), dim3((unsigned)n_tab), dim3(kThreads), 0, st, tab,
-                           p.seq_par, (const typename T::V *)p.b, (typename T::V *)p.x,
-                           (typename T::R *)p.s, sc, average);
+        hipLaunchKernelGGL((k_down_all<P, 8>), dim3(grid), dim3(kThreads), 0, st, tab, p.seq_par,
+                           (const typename T::V *)p.b, (typename T::V *)p.x, (typename T::R *)p.s,
+                           sc, average, dr);
     else if (maxd <= kDownAllMaxDepth)
-        hipLaunchKernelGGL((k_down_all<P, kDownAllMaxDepth>), dim3((unsigned)n_tab),
-                           dim3(kThreads), 0, st, tab, p.seq_par, (const typename T::V *)p.b,
-                           (typename T::V *)p.x, (typename T::R *)p.s, sc, average);
+        hipLaunchKernelGGL((k_down_all<P, kDownAllMaxDepth>), dim3(grid), dim3(kThreads), 0, st,
+                           tab, p.seq_par, (const typename T::V *)p.b, (typename T::V *)p.x,
+                           (typename T::R *)p.s, sc, average, dr);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -1349,10 +1376,11 @@ hipError_t launch_spmv(int prec, int items, int vec, const SpmvBlock *tab, int32
 }
 
 hipError_t launch_up(int prec, int variant, int kind, int root, const RangeBlock *tab,
-                     int32_t n_tab, const DevPlayer &p, double usign, const Scalars *sc,
-                     hipStream_t st)
+                     int32_t n_tab, const RangeBlock *direct, const DevPlayer &p, double usign,
+                     const Scalars *sc, hipStream_t st)
 {
-    CFR_DISPATCH(prec, up_dispatch<P>(variant, kind, root, tab, n_tab, p, usign, sc, st));
+    const RangeBlock dr = direct ? *direct : RangeBlock{0, 0, 0, 0};
+    CFR_DISPATCH(prec, up_dispatch<P>(variant, kind, root, tab, n_tab, dr, p, usign, sc, st));
 }
 
 hipError_t launch_top(int prec, int variant, const DevPlayer &p, double usign, int average,
@@ -1368,9 +1396,11 @@ hipError_t launch_down(int prec, const RangeBlock *tab, int32_t n_tab, const Dev
 }
 
 hipError_t launch_down_all(int prec, int max_depth, const RangeBlock *tab, int32_t n_tab,
-                           const DevPlayer &p, int average, const Scalars *sc, hipStream_t st)
+                           const RangeBlock *direct, const DevPlayer &p, int average,
+                           const Scalars *sc, hipStream_t st)
 {
-    CFR_DISPATCH(prec, down_all_t<P>(max_depth, tab, n_tab, p, average, sc, st));
+    const RangeBlock dr = direct ? *direct : RangeBlock{0, 0, 0, 0};
+    CFR_DISPATCH(prec, down_all_t<P>(max_depth, tab, n_tab, dr, p, average, sc, st));
 }
 
 hipError_t launch_normalize(int prec, const RangeBlock *tab, int32_t n_tab, const DevPlayer &p,
