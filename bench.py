@@ -119,10 +119,25 @@ def copy_probe(torch, nbytes: int = 1600 << 20, reps: int = 5):
                       "ms_per_copy": ms, "copy_GBs": 2 * nbytes / (ms * 1e-3) / 1e9}), flush=True)
 
 
-def solve_alone(cfr, g, variant, target, max_it, K, precision):
+def parse_tiling(text: str) -> dict:
+    """'items_Ay,items_ATx:rows_Ay,rows_ATx[:vec_Ay,vec_ATx[:perm_Ay,perm_ATx]]'."""
+    parts = text.split(":")
+    return {"items": [int(v) for v in parts[0].split(",")],
+            "rows": [int(v) for v in parts[1].split(",")],
+            "vec": [int(v) for v in parts[2].split(",")] if len(parts) > 2 else [1, 1],
+            "perm": [int(v) for v in parts[3].split(",")] if len(parts) > 3 else [0, 0]}
+
+
+def solve_alone(cfr, g, variant, target, max_it, K, precision, tiling=None):
     """One game solved alone with the same stopping rule as in a batch:
-    checks every K iterations, stop at exploitability <= target or max_it."""
+    checks every K iterations, stop at exploitability <= target or max_it.
+    With a tiling, the solver uses it too; its set-up (the quad copies of
+    stream form 3) happens before the timed solve, as the game's creation
+    does."""
     s = cfr.Solver(g, precision=precision)
+    if tiling is not None:
+        s.tiling = tiling
+        s.exploitability("current")  # builds the tables (and quad copies) untimed
     t0 = time.perf_counter()
     while True:
         s.step(K, variant, "alternating")
@@ -193,7 +208,7 @@ def bench_batched(args, torch):
     idx = list(range(0, n, max(1, args.baseline_stride)))
     seq_s, seq_it, seq_e = 0.0, [], []
     for i in idx:
-        el, it, e = solve_alone(cfr, games[i], variant, targets[i], max_it, K, precision)
+        el, it, e = solve_alone(cfr, games[i], variant, targets[i], max_it, K, precision, tiling)
         seq_s += el
         seq_it.append(it)
         seq_e.append(e)
@@ -207,7 +222,8 @@ def bench_batched(args, torch):
         pidx = list(range(0, n, args.plain_stride))
         ps, pr = 0.0, 0
         for i in pidx:
-            el, it, e = solve_alone(cfr, games[i], "vanilla", targets[i], max_it, K, "fp32_acc64")
+            el, it, e = solve_alone(cfr, games[i], "vanilla", targets[i], max_it, K, "fp32_acc64",
+                                    tiling)
             ps += el
             pr += int(e <= targets[i])
         plain = {"games": len(pidx), "seconds": ps, "solves_per_s": len(pidx) / ps,
@@ -282,6 +298,9 @@ def bench_serving(args, torch):
     log(f"[bench] device budget {budget / 1e9:.0f} GB -> capacity {nz:.3e} nonzeros, "
         f"{args.max_games} slots")
 
+    # product tiling of the serving loop and of the one-at-a-time solves
+    tiling = parse_tiling(args.serve_tiling)
+    log(f"[bench] product tiling {tiling}")
     # one game at a time: each distinct request solved alone once
     service = {}
     t0 = time.perf_counter()
@@ -289,7 +308,7 @@ def bench_serving(args, torch):
         key = (int(which[k]), str(var[k]), float(rel[k]))
         if key not in service:
             el, it, e = solve_alone(cfr, pool_games[key[0]], key[1], key[2] * ranges[key[0]], max_it,
-                                    K, precision)
+                                    K, precision, tiling)
             service[key] = (el, it)
     log(f"[bench] {len(service)} distinct requests solved alone in {time.perf_counter() - t0:.1f}s")
     svc = np.array([service[(int(which[k]), str(var[k]), float(rel[k]))][0] for k in range(n)])
@@ -301,7 +320,7 @@ def bench_serving(args, torch):
                  "target": float(rel[k] * ranges[which[k]]), "max_iterations": max_it}
                 for k in range(n)]
         srv = serve.Server(seq, inf, nz, max_games=args.max_games, precision=precision,
-                           check_every=K)
+                           check_every=K, tiling=tiling)
         t0 = time.perf_counter()
         out = srv.serve(reqs, prepared=prepared)
         host = srv.batch.host_stats()
@@ -348,7 +367,7 @@ def bench_serving(args, torch):
                                f"CFR+ or DCFR, target 1e-2 or 1e-3 of the payoff range or "
                                f"{max_it} iterations, checks every {K}, {args.budget_gb:g} GB "
                                f"device budget, {args.max_games} slots",
-                   "value_rate": rates[len(rates) // 2]},
+                   "value_rate": rates[len(rates) // 2], "tiling": tiling},
         "rates": per_rate,
         "pool": {"games": args.pool, "nnz_median": float(np.median(nnz)),
                  "nnz_max": int(nnz.max()), "generate_s": gen_s, "prepare_s": prep_s},
@@ -369,6 +388,9 @@ def main():
     ap.add_argument("--rel-target", type=float, default=1e-3,
                     help="batch: exploitability target as a fraction of the payoff range")
     ap.add_argument("--tune-reps", type=int, default=5, help="batch: autotuner launches each")
+    ap.add_argument("--serve-tiling", default="16,16:256,256:2,2:1,1",
+                    help="serve: product tiling of the serving loop and of the one-at-a-time "
+                         "solves (stream form 2: no per-game quad copy to build at admission)")
     ap.add_argument("--baseline-stride", type=int, default=1,
                     help="batch: solve every k-th game alone for the one-at-a-time rate")
     ap.add_argument("--rates", default="50,200,800", help="serve: arrival rates (req/s)")
@@ -458,11 +480,7 @@ def main():
                             f"A y {us[0]:7.1f} us, A^T x {us[1]:7.1f} us")
     tune_s = None
     if args.tiling:
-        parts = args.tiling.split(":")
-        s.tiling = {"items": [int(v) for v in parts[0].split(",")],
-                    "rows": [int(v) for v in parts[1].split(",")],
-                    "vec": [int(v) for v in parts[2].split(",")] if len(parts) > 2 else [1, 1],
-                    "perm": [int(v) for v in parts[3].split(",")] if len(parts) > 3 else [0, 0]}
+        s.tiling = parse_tiling(args.tiling)
     elif not args.no_tune:
         t0 = time.perf_counter()
         s.tune(reps=10)

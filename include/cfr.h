@@ -403,10 +403,11 @@ int cfr_batch_kernel_timing(cfr_batch *b, int enable);
 int cfr_batch_kernel_stats(cfr_batch *b, int kernel, int64_t *launches, double *total_ms,
                            double *bytes_per_launch);
 
-/* Host seconds and calls spent so far by the batch's runtime: out[0..5]
+/* Host seconds and calls spent so far by the batch's runtime: out[0..6]
  * seconds in table builds, graph captures, evaluations (including their
- * wait for the stream), iteration enqueues, game additions and removals;
- * out[6..11] the matching call counts.  For reports.                     */
+ * wait for the stream), iteration enqueues, game additions, removals and
+ * quad-copy builds (stream form 3; part of the table builds); out[7..13]
+ * the matching call counts.  For reports.                                 */
 int cfr_batch_host_stats(cfr_batch *b, double *out);
 
 int cfr_batch_destroy(cfr_batch *b);

@@ -411,13 +411,14 @@ def cfr_batch_kernel_stats(h, kernel: int):
     return int(n.value), float(ms.value), float(by.value)
 
 
-HOST_STATS = ("tables", "graph", "evaluate", "enqueue", "add", "remove")
+HOST_STATS = ("tables", "graph", "evaluate", "enqueue", "add", "remove", "quads")
 
 
 def cfr_batch_host_stats(h) -> dict:
-    out = np.zeros(12)
+    n = len(HOST_STATS)
+    out = np.zeros(2 * n)
     _check(_lib.cfr_batch_host_stats(h, _dptr(out)), "cfr_batch_host_stats")
-    return {k: {"seconds": float(out[i]), "calls": int(out[6 + i])}
+    return {k: {"seconds": float(out[i]), "calls": int(out[n + i])}
             for i, k in enumerate(HOST_STATS)}
 
 

@@ -266,9 +266,18 @@ struct Engine {
     int64_t checks = 0;       // checks done so far
 
     // host-side time and calls per activity (kHost* below), for reports
-    enum { kHostTables = 0, kHostGraph, kHostEval, kHostEnqueue, kHostAdd, kHostRemove, kHostN };
-    double host_s[kHostN] = {0, 0, 0, 0, 0, 0};
-    int64_t host_n[kHostN] = {0, 0, 0, 0, 0, 0};
+    enum {
+        kHostTables = 0,
+        kHostGraph,
+        kHostEval,
+        kHostEnqueue,
+        kHostAdd,
+        kHostRemove,
+        kHostQuads,  // quad-copy builds (inside table builds)
+        kHostN
+    };
+    double host_s[kHostN] = {0, 0, 0, 0, 0, 0, 0};
+    int64_t host_n[kHostN] = {0, 0, 0, 0, 0, 0, 0};
 
     // per-launch timing of the payoff products (HIP events on st)
     bool timing = false;

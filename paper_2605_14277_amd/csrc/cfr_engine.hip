@@ -899,12 +899,16 @@ int Engine::ensure_quads(const std::vector<int> &set)
 {
     for (int w = 0; w < 2; ++w) {
         if (vec[w] != 3) continue;
-        bool any = false;
-        for (int k : set) any |= slots[(size_t)k].qb[w] < 0;
-        if (!any) continue;
-        reap_uploads(true);  // the element arrays of games still being copied
+        std::vector<int> todo;
+        for (int k : set)
+            if (slots[(size_t)k].qb[w] < 0) todo.push_back(k);
+        if (todo.empty()) continue;
+        HostTimer timer(&host_s[kHostQuads], &host_n[kHostQuads]);
+        // the stream waits for these games' admission copies (and only
+        // theirs: games admitted meanwhile keep copying)
+        hipError_t e = wait_uploads(todo);
+        if (e != hipSuccess) return device_error("admission copies", e);
         QuadStore &Q = quad[w];
-        hipError_t e = hipSuccess;
         if (!Q.ptr) {
             e = hipMalloc((void **)&Q.ptr, 4 * (size_t)std::max<int64_t>(cap.seq[w], 1));
             if (e != hipSuccess) {
@@ -913,41 +917,56 @@ int Engine::ensure_quads(const std::vector<int> &set)
                 return fail(CFR_ENOMEM, "cannot allocate the quad row pointers of a product");
             }
         }
-        for (int k : set) {
-            Slot &s = slots[(size_t)k];
-            if (s.qb[w] >= 0) continue;
+        // quads per row of every game, counted into the row-pointer slots
+        // themselves, brought back with one synchronisation
+        std::vector<std::vector<int32_t>> qp(todo.size());
+        for (size_t t = 0; t < todo.size() && e == hipSuccess; ++t) {
+            const Slot &s = slots[(size_t)todo[t]];
             const int32_t nr = (int32_t)s.ptr[w].size() - 1;
             const int32_t row0 = (int32_t)s.sb[w];
-            std::vector<int32_t> qp((size_t)nr + 1, 0);
-            // quads per row, counted into the row-pointer slots themselves
+            qp[t].assign((size_t)nr + 1, 0);
             e = launch_quad_count(ptr[w], idx[w], s.nb, row0, nr, Q.ptr + row0, st);
             if (e == hipSuccess && nr > 0)
-                e = hipMemcpyAsync(qp.data() + 1, Q.ptr + row0, 4 * (size_t)nr,
+                e = hipMemcpyAsync(qp[t].data() + 1, Q.ptr + row0, 4 * (size_t)nr,
                                    hipMemcpyDeviceToHost, st);
-            if (e == hipSuccess) e = hipStreamSynchronize(st);
-            if (e != hipSuccess) return device_error("quad count", e);
-            for (int32_t r = 0; r < nr; ++r) qp[(size_t)r + 1] += qp[(size_t)r];
-            const int64_t nq = qp[(size_t)nr];
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return device_error("quad count", e);
+        int64_t need = 0;
+        for (auto &v : qp) {
+            for (size_t r = 1; r < v.size(); ++r) v[r] += v[r - 1];
+            need += v.back();
+        }
+        // room for all of them at once (one reallocation at most)
+        if (need > 0 && Q.alloc.largest() < need) {
+            int rc = grow_quads(w, std::max<int64_t>(Q.cap + need, 2 * Q.cap));
+            if (rc) return rc;
+        }
+        for (size_t t = 0; t < todo.size(); ++t) {
+            Slot &s = slots[(size_t)todo[t]];
+            const int32_t nr = (int32_t)qp[t].size() - 1;
+            const int32_t row0 = (int32_t)s.sb[w];
+            const int64_t nq = qp[t].back();
             int64_t qb = 0;
             if (nq > 0) {
                 qb = Q.alloc.take(nq);
                 if (qb < 0) {
-                    int rc = grow_quads(w, Q.cap + nq);
+                    int rc = grow_quads(w, std::max<int64_t>(Q.cap + nq, 2 * Q.cap));
                     if (rc) return rc;
                     qb = Q.alloc.take(nq);
                     if (qb < 0) return fail(CFR_ENOMEM, "quad stream exhausted");
                 }
             }
-            e = hipMemcpyAsync(Q.ptr + row0, qp.data(), 4 * ((size_t)nr + 1),
+            // the host row pointers live in the slot, so the copy may run on
+            s.qptr[w] = std::move(qp[t]);
+            e = hipMemcpyAsync(Q.ptr + row0, s.qptr[w].data(), 4 * ((size_t)nr + 1),
                                hipMemcpyHostToDevice, st);
             if (e == hipSuccess)
                 e = launch_quad_fill(prec, ptr[w], idx[w], val[w], s.nb, row0, nr, Q.ptr, qb, Q.idx,
                                      Q.val, st);
-            if (e == hipSuccess) e = hipStreamSynchronize(st);
             if (e != hipSuccess) return device_error("quad fill", e);
             s.qb[w] = qb;
             s.nq[w] = nq;
-            s.qptr[w] = std::move(qp);
             partition(s, w);
         }
         drop_graph();

@@ -1072,22 +1072,39 @@ __global__ __launch_bounds__(kThreads) void k_remap(int32_t *a, int64_t n,
 // ---------------------------------------------------------------------------
 
 // A row's quads: maximal runs of consecutive nonzeros (in row order) whose
-// columns increase and share one aligned group of four.
+// columns increase and share one aligned group of four.  One wave per row
+// (four rows per block): the wave reads 64 consecutive nonzeros at a time,
+// each lane decides whether its nonzero starts a quad (the previous one is
+// in another group, does not precede it, or belongs to another row), and
+// the quads are counted and ranked with ballots.
+constexpr int kQuadRowsPerBlock = kThreads / 64;
+
+__device__ __forceinline__ bool starts_quad(int32_t col, int32_t prev, bool first)
+{
+    return first || (col >> 2) != (prev >> 2) || col <= prev;
+}
+
 __global__ __launch_bounds__(kThreads) void k_quad_count(const int32_t *__restrict__ ptr,
                                                          const int32_t *__restrict__ idx,
                                                          int64_t nb, int32_t row0, int32_t nr,
                                                          int32_t *__restrict__ cnt)
 {
-    const int32_t r = (int32_t)(blockIdx.x * kThreads + threadIdx.x);
-    if (r >= nr) return;
+    const int lane = (int)(threadIdx.x & 63);
+    const int32_t r = (int32_t)(blockIdx.x * kQuadRowsPerBlock + (threadIdx.x >> 6));
+    if (r >= nr) return;  // the whole wave
     const int32_t a = ptr[row0 + r], z = ptr[row0 + r + 1];
-    int32_t c = 0, prev = -1;
-    for (int32_t e = a; e < z; ++e) {
-        const int32_t col = idx[nb + e];
-        if (c == 0 || (col >> 2) != (prev >> 2) || col <= prev) ++c;
-        prev = col;
+    int32_t c = 0;
+    for (int32_t base = a; base < z; base += 64) {
+        const int32_t e = base + lane;
+        bool st = false;
+        if (e < z) {
+            const int32_t col = idx[nb + e];
+            const int32_t prev = e > a ? idx[nb + e - 1] : -1;
+            st = starts_quad(col, prev, e == a);
+        }
+        c += __popcll(__ballot(st));
     }
-    cnt[r] = c;
+    if (lane == 0) cnt[r] = c;
 }
 
 template <int P>
@@ -1098,30 +1115,42 @@ __global__ __launch_bounds__(kThreads) void k_quad_fill(
     typename Types<P>::V *__restrict__ qval)
 {
     using V = typename Types<P>::V;
-    const int32_t r = (int32_t)(blockIdx.x * kThreads + threadIdx.x);
-    if (r >= nr) return;
+    const int lane = (int)(threadIdx.x & 63);
+    const int32_t r = (int32_t)(blockIdx.x * kQuadRowsPerBlock + (threadIdx.x >> 6));
+    if (r >= nr) return;  // the whole wave
     const int32_t a = ptr[row0 + r], z = ptr[row0 + r + 1];
-    int64_t q = qb + qptr[row0 + r];
-    uint32_t mask = 0;
-    int32_t prev = -1;
-    V v[4] = {0, 0, 0, 0};
-    auto emit = [&]() {
-        qidx[q] = (uint32_t)(prev >> 2) | (mask << kQuadMaskShift);
+    int64_t q0 = qb + qptr[row0 + r];  // first quad of this pass
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int32_t base = a; base < z; base += 64) {
+        const int32_t e = base + lane;
+        bool st = false;
+        int32_t col = 0;
+        if (e < z) {
+            col = idx[nb + e];
+            const int32_t prev = e > a ? idx[nb + e - 1] : -1;
+            st = starts_quad(col, prev, e == a);
+        }
+        const uint64_t ball = __ballot(st);
+        if (st) {
+            // this quad: the nonzeros from e while none starts a new one
+            const int64_t q = q0 + __popcll(ball & below);
+            V v[4] = {0, 0, 0, 0};
+            uint32_t mask = 1u << (col & 3);
+            v[col & 3] = val[nb + e];
+            int32_t prev = col;
+            for (int k = 1; k < 4 && e + k < z; ++k) {
+                const int32_t c2 = idx[nb + e + k];
+                if (starts_quad(c2, prev, false)) break;
+                mask |= 1u << (c2 & 3);
+                v[c2 & 3] = val[nb + e + k];
+                prev = c2;
+            }
+            qidx[q] = (uint32_t)(col >> 2) | (mask << kQuadMaskShift);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) qval[4 * q + k] = v[k];
-        ++q;
-        mask = 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) v[k] = 0;
-    };
-    for (int32_t e = a; e < z; ++e) {
-        const int32_t col = idx[nb + e];
-        if (mask != 0 && ((col >> 2) != (prev >> 2) || col <= prev)) emit();
-        v[col & 3] = val[nb + e];
-        mask |= 1u << (col & 3);
-        prev = col;
+            for (int k = 0; k < 4; ++k) qval[4 * q + k] = v[k];
+        }
+        q0 += __popcll(ball);
     }
-    if (mask != 0) emit();
 }
 
 // ---------------------------------------------------------------------------
@@ -1449,7 +1478,8 @@ hipError_t launch_quad_count(const int32_t *ptr, const int32_t *idx, int64_t nb,
                              int32_t nr, int32_t *cnt, hipStream_t st)
 {
     if (nr <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_quad_count, dim3((unsigned)((nr + kThreads - 1) / kThreads)),
+    hipLaunchKernelGGL(k_quad_count,
+                       dim3((unsigned)((nr + kQuadRowsPerBlock - 1) / kQuadRowsPerBlock)),
                        dim3(kThreads), 0, st, ptr, idx, nb, row0, nr, cnt);
     return hipGetLastError();
 }
@@ -1461,7 +1491,8 @@ hipError_t quad_fill_t(const int32_t *ptr, const int32_t *idx, const void *val, 
 {
     using V = typename Types<P>::V;
     if (nr <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_quad_fill<P>), dim3((unsigned)((nr + kThreads - 1) / kThreads)),
+    hipLaunchKernelGGL((k_quad_fill<P>),
+                       dim3((unsigned)((nr + kQuadRowsPerBlock - 1) / kQuadRowsPerBlock)),
                        dim3(kThreads), 0, st, ptr, idx, (const V *)val, nb, row0, nr, qptr, qb,
                        qidx, (V *)qval);
     return hipGetLastError();

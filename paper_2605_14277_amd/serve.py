@@ -109,12 +109,16 @@ class Server:
 
     def __init__(self, seq_capacity, inf_capacity, nnz_capacity, max_games: int = 256,
                  precision: str = "fp32_acc64", check_every: int = 10, workers: int = 8,
-                 device: int = 0, async_admission: bool = True):
+                 device: int = 0, async_admission: bool = True, tiling: dict | None = None):
         # asynchronous admission: a request's copies to the device overlap
         # the iterations of the requests already running
         self.batch = Batch(seq_capacity, inf_capacity, nnz_capacity, max_games=max_games,
                            precision=precision, mode="alternating", check_every=check_every,
                            device=device, async_admission=async_admission)
+        if tiling is not None:
+            # product tiling of every launch (stream form 3 builds each
+            # admitted game's quad copy when it joins)
+            self.batch.tiling = tiling
         self.precision = precision
         self.check_every = check_every
         self.workers = workers

@@ -42,8 +42,12 @@ def _requests(pool, n, mean_gap, seed):
     return out
 
 
+QUADS = {"items": [16, 16], "rows": [256, 256], "vec": [3, 3], "perm": [1, 1]}
+
+
+@pytest.mark.parametrize("tiling", [None, QUADS], ids=["elements", "quads"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_acc64"])
-def test_served_results_equal_alone(cfr, games, precision):
+def test_served_results_equal_alone(cfr, games, precision, tiling):
     from paper_2605_14277_amd import serve
     pool = [games["cfg1"], games["stops"], games["s2d3"], games["perfect"], gg.cfg2_literal()]
     reqs = _requests(pool, 20, 0.004, seed=3)
@@ -51,7 +55,7 @@ def test_served_results_equal_alone(cfr, games, precision):
     units = sorted((cfr.Batch.game_size(g) for g in pool), key=lambda u: -u[4])
     cap = np.sum(units[:3], axis=0)
     srv = serve.Server([cap[0], cap[1]], [cap[2], cap[3]], int(cap[4]), max_games=4,
-                       precision=precision, check_every=10, workers=4)
+                       precision=precision, check_every=10, workers=4, tiling=tiling)
     out = srv.serve(reqs, keep_strategies=True)
     srv.close()
     overlaps = sum(1 for i in range(len(out)) for j in range(i + 1, len(out))
@@ -68,6 +72,8 @@ def test_served_results_equal_alone(cfr, games, precision):
         else:
             assert o["iterations"] == 150
         solo = cfr.Solver(r["game"], precision=precision)
+        if tiling is not None:
+            solo.tiling = tiling
         solo.step(o["iterations"], r["variant"], "alternating")
         for p in range(2):
             assert np.array_equal(o["strategy"][p], solo.strategy(p, "average")), (k, p)
