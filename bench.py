@@ -301,6 +301,12 @@ def bench_serving(args, torch):
     # product tiling of the serving loop and of the one-at-a-time solves
     tiling = parse_tiling(args.serve_tiling)
     log(f"[bench] product tiling {tiling}")
+    if 3 in tiling["vec"]:
+        # quad copies built with the prepared games (host, worker threads)
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(max_workers=16) as ex:
+            list(ex.map(lambda p: p.prepare_quads(tiling["perm"]), prepared))
+        log(f"[bench] quad copies of the pool built in {time.perf_counter() - t0:.1f}s")
     # one game at a time: each distinct request solved alone once
     service = {}
     t0 = time.perf_counter()

@@ -284,7 +284,8 @@ int cfr_destroy(cfr_solver *s);
  *
  * Storage: one device workspace with per-player arenas of sequence and
  * decision-point indices and an arena of payoff nonzeros.  A game takes
- * n_seq + 1 sequence indices and n_inf + 1 decision-point indices per
+ * n_seq + 1 sequence indices rounded up to a multiple of four (so that every
+ * game starts at a multiple of four) and n_inf + 1 decision-point indices per
  * player and nnz nonzeros (cfr_batch_game_size); cfr_batch_add fails with
  * CFR_ENOMEM when no free range or slot fits, and cfr_batch_remove returns
  * the ranges.  Checks: every check_every iterations the average strategy
@@ -367,6 +368,16 @@ int cfr_batch_add(cfr_batch *b, const cfr_game_desc *game, const cfr_game_params
  * everything it needs and may be added any number of times.               */
 typedef struct cfr_prepared cfr_prepared;
 int cfr_prepare(const cfr_game_desc *game, int precision, cfr_prepared **out);
+/* Builds, on the host, the quad copies (stream form 3 of the tiling) of
+ * both products of a prepared game, product w in column order perm[w] (0:
+ * as numbered, 1: first-touch), in page-locked memory (ordinary memory if
+ * that fails).  A batch whose product w is in stream form 3 with that
+ * column order then copies them at cfr_batch_add_prepared instead of
+ * building them on the device when the game joins.  Host only; may run on
+ * a worker thread, but not while the same prepared game is being added.
+ * Replaces quads built before.  Errors: CFR_EINVAL (null, perm not 0/1),
+ * CFR_ENOMEM (host allocation).                                           */
+int cfr_prepare_quads(cfr_prepared *p, const int perm[2]);
 /* Index units of a prepared game, as cfr_batch_game_size.                 */
 int cfr_prepared_size(const cfr_prepared *p, int64_t *out);
 /* As cfr_batch_add; CFR_EINVAL if the batch's precision differs.          */

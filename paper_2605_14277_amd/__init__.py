@@ -124,6 +124,7 @@ _lib.cfr_batch_destroy.argtypes = [C.c_void_p]
 _lib.cfr_prepare.argtypes = [_P(cfr_game_desc), C.c_int, _P(C.c_void_p)]
 _lib.cfr_batch_host_stats.argtypes = [C.c_void_p, _P(C.c_double)]
 _lib.cfr_prepared_size.argtypes = [C.c_void_p, _P(C.c_int64)]
+_lib.cfr_prepare_quads.argtypes = [C.c_void_p, _P(C.c_int)]
 _lib.cfr_batch_add_prepared.argtypes = [C.c_void_p, C.c_void_p, _P(cfr_game_params),
                                         _P(C.c_int64)]
 _lib.cfr_prepared_destroy.argtypes = [C.c_void_p]
@@ -137,7 +138,8 @@ for _f in ("cfr_options_default", "cfr_validate", "cfr_workspace_size", "cfr_cre
            "cfr_batch_exploitability", "cfr_batch_remove", "cfr_batch_get_tiling",
            "cfr_batch_set_tiling", "cfr_batch_tune", "cfr_batch_kernel_timing",
            "cfr_batch_kernel_stats", "cfr_batch_destroy", "cfr_prepare", "cfr_prepared_size",
-           "cfr_batch_add_prepared", "cfr_prepared_destroy", "cfr_batch_host_stats"):
+           "cfr_batch_add_prepared", "cfr_prepared_destroy", "cfr_batch_host_stats",
+           "cfr_prepare_quads"):
     getattr(_lib, _f).restype = C.c_int
 
 

@@ -752,8 +752,8 @@ int cfr_batch_game_size(const cfr_game_desc *game, int64_t *out)
     if (!out) return fail(CFR_EINVAL, "null output");
     int rc = validate_game(game, false);
     if (rc) return rc;
-    out[0] = game->player[0].n_seq + 1;
-    out[1] = game->player[1].n_seq + 1;
+    out[0] = cfr::seq_block(game->player[0].n_seq);
+    out[1] = cfr::seq_block(game->player[1].n_seq);
     out[2] = game->player[0].n_inf + 1;
     out[3] = game->player[1].n_inf + 1;
     out[4] = game->nnz;
@@ -890,7 +890,7 @@ int cfr_prepare(const cfr_game_desc *game, int precision, cfr_prepared **out)
             p->hg.val[w] = nullptr;
         }
         for (int q = 0; q < 2; ++q) {
-            p->units[q] = game->player[q].n_seq + 1;
+            p->units[q] = cfr::seq_block(game->player[q].n_seq);
             p->units[2 + q] = game->player[q].n_inf + 1;
         }
         p->units[4] = game->nnz;
@@ -900,6 +900,19 @@ int cfr_prepare(const cfr_game_desc *game, int precision, cfr_prepared **out)
         delete p;
         return fail(CFR_ENOMEM, std::string("host allocation failed: ") + ex.what());
     }
+}
+
+int cfr_prepare_quads(cfr_prepared *p, const int *perm)
+{
+    if (!p || !perm) return fail(CFR_EINVAL, "null argument");
+    for (int w = 0; w < 2; ++w)
+        if (perm[w] != 0 && perm[w] != 1) return fail(CFR_EINVAL, "perm must be 0 or 1");
+    try {
+        cfr::build_image_quads(p->hg, perm, true, p->img);
+    } catch (const std::exception &ex) {
+        return fail(CFR_ENOMEM, std::string("host allocation failed: ") + ex.what());
+    }
+    return CFR_OK;
 }
 
 int cfr_prepared_size(const cfr_prepared *p, int64_t *out)

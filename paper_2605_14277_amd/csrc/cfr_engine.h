@@ -99,8 +99,26 @@ struct GameImage {
     char *base = nullptr;
     std::shared_ptr<void> pinned;
     std::vector<char> plain;
+    // Quad copies of the products (stream form 3) in the game's local
+    // numbering, built on the host for one column order per product: row
+    // pointers, quad words (local aligned group | mask << kQuadMaskShift)
+    // and four values per quad, in a buffer of their own.
+    struct Quads {
+        bool built[2] = {false, false};
+        int perm[2] = {0, 0};  // column order they were built in
+        int64_t nq[2] = {0, 0};
+        std::vector<int32_t> qptr[2];  // host row pointers (partitioning)
+        size_t ptr[2] = {0, 0}, idx[2] = {0, 0}, val[2] = {0, 0};  // offsets in the buffer
+        bool locked = false;
+        char *base = nullptr;
+        std::shared_ptr<void> pinned;
+        std::vector<char> plain;
+    } quads;
 };
 void build_image(const HostGame &hg, int prec, bool pinned, bool borrow, GameImage &img);
+// Builds img.quads for both products (perm[w]: 0 identity, 1 first-touch
+// column order).
+void build_image_quads(const HostGame &hg, const int perm[2], bool pinned, GameImage &img);
 
 // Per-game constants of the regret minimiser and the stopping rule.
 struct GameParams {

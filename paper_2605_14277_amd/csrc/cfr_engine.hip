@@ -552,6 +552,88 @@ void build_image(const HostGame &hg, int prec, bool pinned, bool borrow, GameIma
     }
 }
 
+// The quads of one product, host side: the same rule as the device build
+// (a quad is a maximal run of consecutive nonzeros of a row, in row order,
+// whose columns increase and share one aligned group of four).
+void build_image_quads(const HostGame &hg, const int perm[2], bool pinned, GameImage &img)
+{
+    GameImage::Quads &Q = img.quads;
+    const size_t V = value_bytes(img.prec);
+    std::vector<int32_t> cols;
+    // pass 1: quad counts (row pointers), with each product's column order
+    for (int w = 0; w < 2; ++w) {
+        const int q = 1 - w;
+        const std::vector<int32_t> &rp = hg.ptr[w];
+        const int32_t *ix = img.idx_src[w];
+        const int32_t *pos = (const int32_t *)(img.base + img.pl[q].pos);
+        Q.perm[w] = perm[w] ? 1 : 0;
+        std::vector<int32_t> &qp = Q.qptr[w];
+        qp.assign(rp.size(), 0);
+        for (size_t r = 0; r + 1 < rp.size(); ++r) {
+            int32_t c = 0, prev = -1;
+            for (int32_t e = rp[r]; e < rp[r + 1]; ++e) {
+                const int32_t col = Q.perm[w] ? pos[ix[e]] : ix[e];
+                if (e == rp[r] || (col >> 2) != (prev >> 2) || col <= prev) ++c;
+                prev = col;
+            }
+            qp[r + 1] = qp[r] + c;
+        }
+        Q.nq[w] = qp.back();
+    }
+    size_t cur = 0;
+    auto take = [&](size_t bytes) {
+        cur = (cur + 255) & ~(size_t)255;
+        const size_t at = cur;
+        cur += bytes;
+        return at;
+    };
+    for (int w = 0; w < 2; ++w) {
+        Q.ptr[w] = take(4 * Q.qptr[w].size());
+        Q.idx[w] = take(4 * (size_t)Q.nq[w]);
+        Q.val[w] = take(4 * V * (size_t)Q.nq[w]);
+    }
+    const size_t bytes = std::max<size_t>((cur + 255) & ~(size_t)255, 256);
+    Q.pinned = pinned ? pinned_buffer(bytes) : nullptr;
+    Q.locked = Q.pinned != nullptr;
+    if (Q.locked) {
+        Q.base = (char *)Q.pinned.get();
+    } else {
+        Q.plain.assign(bytes, 0);
+        Q.base = Q.plain.data();
+    }
+    // pass 2: the quads
+    for (int w = 0; w < 2; ++w) {
+        const int q = 1 - w;
+        const std::vector<int32_t> &rp = hg.ptr[w];
+        const int32_t *ix = img.idx_src[w];
+        const int32_t *pos = (const int32_t *)(img.base + img.pl[q].pos);
+        std::memcpy(Q.base + Q.ptr[w], Q.qptr[w].data(), 4 * Q.qptr[w].size());
+        uint32_t *qi = (uint32_t *)(Q.base + Q.idx[w]);
+        char *qv = Q.base + Q.val[w];
+        const char *vs = (const char *)img.val_src[w];
+        int64_t k = 0;
+        for (size_t r = 0; r + 1 < rp.size(); ++r) {
+            uint32_t mask = 0;
+            int32_t prev = -1;
+            for (int32_t e = rp[r]; e <= rp[r + 1]; ++e) {
+                const bool end = e == rp[r + 1];
+                const int32_t col = end ? 0 : (Q.perm[w] ? pos[ix[e]] : ix[e]);
+                if (mask != 0 && (end || (col >> 2) != (prev >> 2) || col <= prev)) {
+                    qi[k] = (uint32_t)(prev >> 2) | (mask << kQuadMaskShift);
+                    ++k;
+                    mask = 0;
+                }
+                if (end) break;
+                if (mask == 0) std::memset(qv + 4 * V * (size_t)k, 0, 4 * V);
+                std::memcpy(qv + V * (4 * (size_t)k + (size_t)(col & 3)), vs + V * (size_t)e, V);
+                mask |= 1u << (col & 3);
+                prev = col;
+            }
+        }
+        Q.built[w] = true;
+    }
+}
+
 Capacity lone_capacity(const HostGame &hg, int items_csr, int rows_csr, int items_csc,
                        int rows_csc)
 {
@@ -559,7 +641,7 @@ Capacity lone_capacity(const HostGame &hg, int items_csr, int rows_csr, int item
     c.slots = 1;
     for (int p = 0; p < 2; ++p) {
         const PlayerPlan &pl = hg.pl[p];
-        c.seq[p] = (int64_t)pl.n_seq + 1;
+        c.seq[p] = seq_block(pl.n_seq);
         c.inf[p] = (int64_t)pl.n_inf + 1;
         c.t_up[p] = 0;
         c.t_down[p] = 0;
@@ -860,7 +942,10 @@ int Engine::grow_quads(int which, int64_t need)
 {
     QuadStore &Q = quad[which];
     const size_t V = value_bytes(prec);
-    const int64_t ncap = std::max<int64_t>(need, Q.cap + Q.cap / 2);
+    int64_t ncap = std::max<int64_t>(need, Q.cap + Q.cap / 2);
+    // a batch starts with room for many games (each growth waits for both
+    // streams and copies the store): min(kQuadStoreMin, its nonzero capacity)
+    if (!lone) ncap = std::max<int64_t>(ncap, std::min<int64_t>(kQuadStoreMin, cap.nnz));
     uint32_t *ni = nullptr;
     void *nv = nullptr;
     hipError_t e = hipMalloc((void **)&ni, 4 * (size_t)ncap);
@@ -872,7 +957,10 @@ int Engine::grow_quads(int which, int64_t need)
         return fail(CFR_ENOMEM, "cannot allocate the quad stream of a product");
     }
     if (Q.cap > 0) {
-        e = hipMemcpyAsync(ni, Q.idx, 4 * (size_t)Q.cap, hipMemcpyDeviceToDevice, st);
+        // admission copies may still be writing into the old buffers
+        if (up_st) e = hipStreamSynchronize(up_st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(ni, Q.idx, 4 * (size_t)Q.cap, hipMemcpyDeviceToDevice, st);
         if (e == hipSuccess)
             e = hipMemcpyAsync(nv, Q.val, 4 * V * (size_t)Q.cap, hipMemcpyDeviceToDevice, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -1042,7 +1130,7 @@ int Engine::add(const HostGame &hg, const GameImage &img, const GameParams &gp, 
     int64_t sb[2] = {-1, -1}, ib[2] = {-1, -1}, nb = -1;
     bool ok = true;
     for (int p = 0; p < 2 && ok; ++p) {
-        sb[p] = seq_alloc[p].take((int64_t)hg.pl[p].n_seq + 1);
+        sb[p] = seq_alloc[p].take(seq_block(hg.pl[p].n_seq));
         if (sb[p] < 0) ok = false;
         else {
             ib[p] = inf_alloc[p].take((int64_t)hg.pl[p].n_inf + 1);
@@ -1055,7 +1143,7 @@ int Engine::add(const HostGame &hg, const GameImage &img, const GameParams &gp, 
     }
     if (!ok) {
         for (int p = 0; p < 2; ++p) {
-            if (sb[p] >= 0) seq_alloc[p].give(sb[p], (int64_t)hg.pl[p].n_seq + 1);
+            if (sb[p] >= 0) seq_alloc[p].give(sb[p], seq_block(hg.pl[p].n_seq));
             if (ib[p] >= 0) inf_alloc[p].give(ib[p], (int64_t)hg.pl[p].n_inf + 1);
         }
         return fail(CFR_ENOMEM, "the game does not fit the free device capacity");
@@ -1151,6 +1239,41 @@ int Engine::add(const HostGame &hg, const GameImage &img, const GameParams &gp, 
         if (perm_on[w]) CHECK(launch_remap(idx[w] + nb, hg.nnz, dp[1 - w].pos, ups));
         CHECK(cp((char *)val[w] + V * (size_t)nb, img.val_src[w], V * (size_t)hg.nnz));
     }
+    // quad copies built with the image, when they match the product's
+    // stream form and column order: copied like the rest (game starts are
+    // multiples of four, so only the group index moves)
+    for (int w = 0; w < 2; ++w) {
+        const GameImage::Quads &IQ = img.quads;
+        if (vec[w] != 3 || !IQ.built[w] || IQ.perm[w] != perm_on[w]) continue;
+        QuadStore &Q = quad[w];
+        if (!Q.ptr) {
+            if (hipMalloc((void **)&Q.ptr, 4 * (size_t)std::max<int64_t>(cap.seq[w], 1)) !=
+                hipSuccess) {
+                Q.ptr = nullptr;
+                (void)hipGetLastError();
+                continue;  // built on the device when the game joins
+            }
+        }
+        const int64_t nq = IQ.nq[w];
+        int64_t qb = 0;
+        if (nq > 0) {
+            qb = Q.alloc.take(nq);
+            if (qb < 0) {
+                if (grow_quads(w, std::max<int64_t>(Q.cap + nq, 2 * Q.cap))) continue;
+                qb = Q.alloc.take(nq);
+                if (qb < 0) continue;
+            }
+        }
+        const int32_t nr = (int32_t)IQ.qptr[w].size() - 1;
+        const char *QB = IQ.base;
+        CHECK(cp(Q.ptr + sb[w], QB + IQ.ptr[w], 4 * ((size_t)nr + 1)));
+        CHECK(cp(Q.idx + qb, QB + IQ.idx[w], 4 * (size_t)nq));
+        CHECK(launch_add_offset((int32_t *)(Q.idx + qb), nq, (int32_t)(sb[1 - w] / 4), ups));
+        CHECK(cp((char *)Q.val + 4 * V * (size_t)qb, QB + IQ.val[w], 4 * V * (size_t)nq));
+        s.qb[w] = qb;
+        s.nq[w] = nq;
+        s.qptr[w] = IQ.qptr[w];
+    }
     // the game's scalars: t = 0, its constants (from page-locked staging
     // when there is some)
     {
@@ -1232,7 +1355,7 @@ void Engine::remove(int k)
         s.up_ev = nullptr;
     }
     for (int p = 0; p < 2; ++p) {
-        seq_alloc[p].give(s.sb[p], (int64_t)s.n_seq[p] + 1);
+        seq_alloc[p].give(s.sb[p], seq_block(s.n_seq[p]));
         inf_alloc[p].give(s.ib[p], (int64_t)s.n_inf[p] + 1);
     }
     if (s.nnz > 0) nnz_alloc.give(s.nb, s.nnz);

@@ -196,6 +196,11 @@ constexpr int kQuadMaskShift = 28;
 constexpr uint32_t kQuadIndexMask = (1u << kQuadMaskShift) - 1;
 constexpr int kQuadItems = 16;  // the only items value of stream form 3 (1024 quads a block)
 constexpr int kVecPad = 4;      // readable entries past the end of every gathered vector
+constexpr int64_t kQuadStoreMin = (int64_t)1 << 26;  // first quad store of a batch (quads)
+// A game's block of sequence indices (n_seq + 1 with the sentinel) is
+// rounded up to a multiple of four, so every game starts at a multiple of
+// four and its local aligned groups of four columns are global ones.
+__host__ __device__ constexpr int64_t seq_block(int64_t n_seq) { return (n_seq + 1 + 3) & ~(int64_t)3; }
 // Stream elements one block of the product may hold under stream form vec.
 __host__ __device__ constexpr int spmv_block_cap_v(int items, int vec)
 {

@@ -30,7 +30,7 @@ from . import (AVG, CFR_ENOMEM, PRECISIONS, VARIANTS, Batch, CfrError, GameArray
 class Prepared:
     """A game prepared on the host for batches of one precision."""
 
-    def __init__(self, game, precision: str = "fp32_acc64"):
+    def __init__(self, game, precision: str = "fp32_acc64", quads=None):
         arrays = GameArrays(game)
         self.precision = precision
         self.n_seq = list(arrays.n_seq)
@@ -42,6 +42,15 @@ class Prepared:
         _check(_lib.cfr_prepared_size(h, units.ctypes.data_as(C.POINTER(C.c_int64))),
                "cfr_prepared_size")
         self.units = units
+        if quads is not None:
+            self.prepare_quads(quads)
+
+    def prepare_quads(self, perm):
+        """Quad copies of both products (stream form 3) in column orders
+        perm = (A y, A^T x) (0: as numbered, 1: first-touch), built here on
+        the host so that admission only copies them."""
+        arr = (C.c_int * 2)(int(perm[0]), int(perm[1]))
+        _check(_lib.cfr_prepare_quads(self.h, arr), "cfr_prepare_quads")
 
     def close(self):
         if getattr(self, "h", None):
@@ -115,10 +124,13 @@ class Server:
         self.batch = Batch(seq_capacity, inf_capacity, nnz_capacity, max_games=max_games,
                            precision=precision, mode="alternating", check_every=check_every,
                            device=device, async_admission=async_admission)
+        # column orders of the quad copies that arriving requests get built
+        # on the worker threads (stream form 3 on some product), else None
+        self.quad_perm = None
         if tiling is not None:
-            # product tiling of every launch (stream form 3 builds each
-            # admitted game's quad copy when it joins)
             self.batch.tiling = tiling
+            if 3 in tiling["vec"]:
+                self.quad_perm = tuple(int(v) for v in tiling["perm"])
         self.precision = precision
         self.check_every = check_every
         self.workers = workers
@@ -148,7 +160,8 @@ class Server:
                     if "prepared" in r:
                         futures[k] = prepared[r["prepared"]]
                     else:
-                        futures[k] = pool.submit(Prepared, r["game"], self.precision)
+                        futures[k] = pool.submit(Prepared, r["game"], self.precision,
+                                                 self.quad_perm)
                     waiting.append(k)
                     next_arrival += 1
                 # admit in arrival order while the head fits

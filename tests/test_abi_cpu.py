@@ -180,7 +180,10 @@ def test_batch_defaults_and_game_size(cfr, games):
     assert gp.variant == cfr.VARIANTS["pcfr+"] and gp.target_exploitability == 0
     g = games["stops"]
     u = cfr.cfr_batch_game_size(cfr.GameArrays(g))
-    assert list(u) == [g.n_seq[0] + 1, g.n_seq[1] + 1, g.n_inf[0] + 1, g.n_inf[1] + 1, g.nnz]
+    # sequence blocks are rounded up to a multiple of four
+    r4 = lambda n: -(-n // 4) * 4
+    assert list(u) == [r4(g.n_seq[0] + 1), r4(g.n_seq[1] + 1), g.n_inf[0] + 1, g.n_inf[1] + 1,
+                       g.nnz]
 
 
 def _batch_opts(cfr, seq, inf, nnz, **kw):
@@ -247,6 +250,13 @@ def test_prepare_without_device(cfr, games):
         p = serve.Prepared(g, prec)
         assert list(p.units) == list(cfr.cfr_batch_game_size(cfr.GameArrays(g)))
         p.close()
+    # host-built quad copies need no device either
+    p = serve.Prepared(g, "fp32_acc64", quads=(1, 0))
+    p.prepare_quads((0, 1))
+    with pytest.raises(cfr.CfrError) as ei:
+        p.prepare_quads((2, 0))
+    assert ei.value.code == cfr.CFR_EINVAL
+    p.close()
     import copy
     g2 = copy.copy(games["cfg1"])
     g2.col_idx = np.array(g2.col_idx, dtype=np.int32, copy=True)

@@ -285,15 +285,20 @@ def test_chain_top_down_pass_equals_level_by_level(cfr, mix, precision):
             assert np.array_equal(a, b), (name, precision)
 
 
-@pytest.mark.parametrize("tiling", [None, QUADS], ids=["elements", "quads"])
+@pytest.mark.parametrize("tiling", [None, QUADS, dict(QUADS, perm=[1, 1])],
+                         ids=["elements", "quads", "quads-from-images"])
 def test_asynchronous_admission(cfr, mix, tiling):
     """Admission copies run on their own stream: a game added while others
     iterate joins at the next check, one added to an idle batch at once, and
-    every game still equals the same game solved alone."""
+    every game still equals the same game solved alone.  With quads, the
+    prepared games carry host-built quad copies in first-touch column order:
+    a product in that order copies them, the other (A y in identity order
+    under QUADS) builds its own on the device."""
     from paper_2605_14277_amd import serve
     pool = {name: (g, v) for name, g, v in mix}
     names = ("cfg1", "stops", "s2d3", "cfg2_d8")
-    preps = {n: serve.Prepared(pool[n][0], "fp64") for n in names}
+    preps = {n: serve.Prepared(pool[n][0], "fp64", quads=(1, 1) if tiling else None)
+             for n in names}
     units = np.sum([preps[n].units for n in names], axis=0)
     b = cfr.Batch([units[0], units[1]], [units[2], units[3]], int(units[4]), max_games=4,
                   precision="fp64", check_every=10, async_admission=True)
