@@ -427,8 +427,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        log("bench.py measures one GPU only: this build has no multi-GPU path "
-            "(the sharding design is described in DESIGN.md). Run with --gpus 1.")
+        log("bench.py measures one GPU only: the solver runs on a single GPU and "
+            "has no multi-GPU path. Run with --gpus 1.")
         sys.exit(2)
 
     import torch
