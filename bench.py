@@ -524,26 +524,29 @@ def main():
     s.kernel_timing(False)
     product_bytes = [st[3] for st in stats]
     stats.sort(reverse=True)
-    tot, kname, nl, by = stats[0]
+    tot, kname, nl, by_format = stats[0]
     avg_ms = tot / nl
-    achieved = by / (avg_ms * 1e-3) / 1e9
     digest = kernel_source_digest()
     traffic = measured_traffic(kname, digest, tiling)
     e = s.exploitability("average")
-    log(f"[bench] {kname}: {nl} launches, {avg_ms * 1e3:.1f} us avg, {achieved:.0f} GB/s "
-        f"(algorithmic); expl after {s.iteration} it = {e['expl']:.4g}")
 
     vbytes = 8 if precision == "fp64" else 4
     abytes = 4 if precision == "fp32" else 8
-    alg = algorithmic_bytes_per_iteration(g, vbytes, abytes, variant in ("pcfr+", "pcfr"),
-                                          product_bytes)
-    # what the element stream (index + value per nonzero) would have to move
-    # for the same product: the rate at which this launch does the work of
-    # the plain sparse format
+    # algorithmic bytes: each nonzero's index and value (the element stream),
+    # the row pointers, the gathered vector once and the output once, for
+    # every stream form; the bytes the launch's own format moves (fewer with
+    # quads) are reported beside them
+    alg = algorithmic_bytes_per_iteration(g, vbytes, abytes, variant in ("pcfr+", "pcfr"))
+    alg_format = algorithmic_bytes_per_iteration(g, vbytes, abytes, variant in ("pcfr+", "pcfr"),
+                                                 product_bytes)
     w = 0 if kname == "spmv_csr" else 1
     n_rows, n_cols = g.n_seq[w], g.n_seq[1 - w]
-    by_elem = g.nnz * (4 + vbytes) + 4 * (n_rows + 1) + vbytes * (n_cols + n_rows)
-    elem_gbs = by_elem / (avg_ms * 1e-3) / 1e9
+    by = float(g.nnz * (4 + vbytes) + 4 * (n_rows + 1) + vbytes * (n_cols + n_rows))
+    achieved = by / (avg_ms * 1e-3) / 1e9
+    format_gbs = by_format / (avg_ms * 1e-3) / 1e9
+    log(f"[bench] {kname}: {nl} launches, {avg_ms * 1e3:.1f} us avg, {achieved:.0f} GB/s "
+        f"algorithmic ({format_gbs:.0f} GB/s of its own format's bytes); expl after "
+        f"{s.iteration} it = {e['expl']:.4g}")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -574,12 +577,13 @@ def main():
         "algorithmic_gb_per_iter": alg / 1e9,
         "iteration_gbs": alg / (ms_per_step * 1e-3) / 1e9,
         "iteration_hbm_frac": alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "format_gb_per_iter": alg_format / 1e9,
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "avg_launch_us": avg_ms * 1e3,
                      "bytes_per_launch": by, "stream_form": tiling["vec"][w],
-                     "element_stream_bytes_per_launch": by_elem,
-                     "element_stream_equiv_gbs": elem_gbs},
+                     "format_bytes_per_launch": by_format, "format_gbs": format_gbs,
+                     "format_frac": format_gbs / HBM_PEAK_GBS},
         "cpu_baseline": cpu,
         "expl_average": e["expl"],
     }
