@@ -191,8 +191,10 @@ __device__ void begin_iteration(Scalars *sc)
 // gather fetches the four input entries.  Absent positions stage -0.0,
 // which leaves every sum unchanged (x + -0.0 == x exactly, signed zeros
 // included), so the row sums are exactly those of the nonzeros in row
-// order.  Row pointers and block extents count quads; staging slot 4*q + k
-// holds position k of quad q.
+// order.  Row pointers and block extents count quads.  In the sequential
+// order staging slot 4*q + k holds position k of quad q; otherwise slot q
+// holds quad q's sum (its positions added in order), so rows are reduced
+// over a quarter of the slots.
 //
 // Each table entry gives a block's rows, nonzeros and game in one scalar
 // load.  The loads of a block are all issued
@@ -265,7 +267,10 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(
     int32_t per = 1;  // staging slots per stream element
     if (VEC == 3) {
         constexpr int NQ = ITEMS / 4;
-        per = 4;
+        // the sequential (FP64) order stages every position; otherwise a
+        // quad's positions (one row, in order) are summed here and the
+        // quad is staged as one value
+        per = SEQ ? 4 : 1;
         if (n > 0) {
             uint32_t qd[NQ];
             V v4[NQ][4];
@@ -283,13 +288,22 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(
 #pragma unroll
             for (int j = 0; j < NQ; ++j) {
                 const int32_t qi = j * kSpmvThreads + tid;
-                L o[4];
+                if (SEQ) {
+                    L o[4];
 #pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    o[k] = (qi < n && ((qd[j] >> (kQuadMaskShift + k)) & 1u))
-                               ? (L)((C)v4[j][k] * (C)gx[j][k])
-                               : (L)(-0.0);
-                store4(&prod[4 * qi], o);
+                    for (int k = 0; k < 4; ++k)
+                        o[k] = (qi < n && ((qd[j] >> (kQuadMaskShift + k)) & 1u))
+                                   ? (L)((C)v4[j][k] * (C)gx[j][k])
+                                   : (L)(-0.0);
+                    store4(&prod[4 * qi], o);
+                } else {
+                    C qs = (C)(-0.0);
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if ((qd[j] >> (kQuadMaskShift + k)) & 1u)
+                            qs = qs + (C)v4[j][k] * (C)gx[j][k];
+                    prod[qi] = (L)qs;  // lanes past the block stage a value no row reads
+                }
             }
         }
     } else if (VEC == 2) {
