@@ -17,6 +17,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -42,9 +43,13 @@ def kernel_source_digest() -> str:
     start = text.index("// SEQ: every row is summed strictly left to right")
     end = text.index("// ----", start)
     h = hashlib.sha256(text[start:end].encode())
+    # the definitions of the constants and macros the kernel uses
+    defs = re.compile(r"^\s*(constexpr\s+\S+\s+(kSpmv\w*|kStreamPad|kQuadMaskShift|"
+                      r"kQuadIndexMask)\s*=|#define\s+CFR_SPMV\w*|#ifndef\s+CFR_SPMV\w*|"
+                      r"__host__ __device__ constexpr int spmv_block_cap\(int items\))")
     with open(os.path.join(csrc, "cfr_internal.h")) as fh:
         for line in fh:
-            if "SPMV" in line or "kSpmv" in line:
+            if defs.match(line):
                 h.update(line.encode())
     return h.hexdigest()[:16]
 
@@ -469,7 +474,7 @@ def main():
         s.step(3, variant, mode)
         for perm in (0, 1):
             for vec in (0, 1, 2, 3):
-                for items in ((16,) if vec == 3 else (4, 8, 16)):
+                for items in ((8, 16) if vec == 3 else (4, 8, 16)):
                     for rows in (64, 128, 256):
                         s.tiling = {"items": [items, items], "rows": [rows, rows],
                                     "vec": [vec, vec], "perm": [perm, perm]}

@@ -240,8 +240,9 @@ int cfr_set_state(cfr_solver *s, const void *in, size_t len);
  * reads consecutive elements; 0: one 4-byte load per element; 3: quads, a
  * copy of the matrix in which each element is a run of at most four
  * nonzeros of a row whose columns share one aligned group of four, stored
- * as one index and four values and gathered with one 16-byte load; only
- * with 16 nonzeros per thread; the library allocates this copy itself, on
+ * as one index and four values and gathered with one 16-byte load (8 or
+ * 16 nonzeros per thread: a thread takes items/4 quads); the library
+ * allocates this copy itself, on
  * first use, outside any caller workspace, and frees it on destroy) and perm
  * (1: before the product, the
  * gathered strategy is copied into the order in which the rows first use

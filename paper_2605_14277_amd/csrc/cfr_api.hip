@@ -177,8 +177,8 @@ int check_tiling(const cfr_spmv_tiling *t)
         if (t->rows[w] < 64 || t->rows[w] > cfr::kSpmvRowCap)
             return fail(CFR_EINVAL, "rows per block must be in [64, 256]");
         if (t->vec[w] < 0 || t->vec[w] > 3) return fail(CFR_EINVAL, "vec must be 0, 1, 2 or 3");
-        if (t->vec[w] == 3 && t->items[w] != cfr::kQuadItems)
-            return fail(CFR_EINVAL, "stream form 3 takes 16 nonzeros per thread");
+        if (t->vec[w] == 3 && t->items[w] < cfr::kQuadItemsMin)
+            return fail(CFR_EINVAL, "stream form 3 takes 8 or 16 nonzeros per thread");
         if (t->perm[w] != 0 && t->perm[w] != 1) return fail(CFR_EINVAL, "perm must be 0 or 1");
     }
     return CFR_OK;
@@ -253,7 +253,7 @@ int tune(cfr::Engine &e, int reps, cfr_spmv_tiling *chosen)
             for (int vec = 0; vec < 4; ++vec)
                 for (int items : kItems)
                     for (int rows : kRows) {
-                        if (vec == 3 && items != cfr::kQuadItems) continue;
+                        if (vec == 3 && items < cfr::kQuadItemsMin) continue;
                         e.repartition(w, items, rows, vec);
                         double ms = 0;
                         rc = e.time_spmv(w, reps, &ms);

@@ -661,8 +661,8 @@ Capacity lone_capacity(const HostGame &hg, int items_csr, int rows_csr, int item
     (void)rows_csr;
     (void)items_csc;
     (void)rows_csc;
-    c.t_csr = (int64_t)partition_rows(hg.ptr[0], spmv_block_cap(4), 64).size() - 1;
-    c.t_csc = (int64_t)partition_rows(hg.ptr[1], spmv_block_cap(4), 64).size() - 1;
+    c.t_csr = (int64_t)partition_rows(hg.ptr[0], kMinBlockCap, 64).size() - 1;
+    c.t_csc = (int64_t)partition_rows(hg.ptr[1], kMinBlockCap, 64).size() - 1;
     return c;
 }
 
@@ -671,11 +671,12 @@ void bound_tables(Capacity &c)
     // A game's product blocks: two consecutive blocks together exceed the
     // nonzero cap unless the row cap closed the first, so a game with z
     // nonzeros and n rows has at most 2 z / cap + n / row_cap + 2 blocks
-    // (smallest tiling: cap 1024 nonzeros, 64 rows).  Range blocks: one per
+    // (smallest tiling: kMinBlockCap stream elements, each holding at least
+    // one nonzero, and 64 rows).  Range blocks: one per
     // kRangeBlock indices plus one partial block per (game, level), and a
     // game has at most as many levels as decision points.
     for (int w = 0; w < 2; ++w) {
-        const int64_t t = 2 * c.nnz / spmv_block_cap(4) + c.seq[w] / 64 + 2 * c.slots + 1;
+        const int64_t t = 2 * c.nnz / kMinBlockCap + c.seq[w] / 64 + 2 * c.slots + 1;
         if (w == 0) c.t_csr = t;
         else c.t_csc = t;
     }
@@ -1385,7 +1386,7 @@ bool Engine::tables_in_bounds(const Tables &T) const
         const std::vector<SpmvBlock> &v = w == 0 ? T.h_csr : T.h_csc;
         const int cap_nnz = spmv_block_cap_v(items[w], vec[w]);
         const bool quads = vec[w] == 3;
-        if (quads && (items[w] != kQuadItems || !quad[w].idx)) {
+        if (quads && !quad[w].idx) {
             for (const SpmvBlock &b : v)
                 if (b.n > 0) return false;
         }

@@ -194,7 +194,12 @@ constexpr int kStreamPad = 4;  // readable elements past the end of the index/va
 // Stream form 3 (quads): element = quad index | presence mask << kQuadMaskShift
 constexpr int kQuadMaskShift = 28;
 constexpr uint32_t kQuadIndexMask = (1u << kQuadMaskShift) - 1;
-constexpr int kQuadItems = 16;  // the only items value of stream form 3 (1024 quads a block)
+// Smallest block capacity (stream elements) of any tiling: quads at 8
+// nonzeros per thread (512 a block; stream form 3 takes 8 or 16); element
+// tiling caps are larger, and a block never holds more elements than
+// nonzeros, so partitions at this cap bound the blocks of every tiling.
+constexpr int kQuadItemsMin = 8;
+constexpr int kMinBlockCap = kSpmvThreads * kQuadItemsMin / 4;
 constexpr int kVecPad = 4;      // readable entries past the end of every gathered vector
 constexpr int64_t kQuadStoreMin = (int64_t)1 << 26;  // first quad store of a batch (quads)
 // A game's block of sequence indices (n_seq + 1 with the sentinel) is
