@@ -213,7 +213,8 @@ def test_tiling_and_tuner(cfr, mix):
                    {"items": [16, 8], "rows": [256, 128], "vec": [2, 2], "perm": [0, 1]},
                    {"items": [4, 16], "rows": [64, 256], "vec": [2, 0], "perm": [1, 0]},
                    {"items": [16, 16], "rows": [256, 64], "vec": [3, 3], "perm": [0, 1]},
-                   {"items": [16, 8], "rows": [128, 256], "vec": [3, 2], "perm": [1, 1]}, "tune"):
+                   {"items": [16, 8], "rows": [128, 256], "vec": [3, 2], "perm": [1, 1]},
+                   {"items": [8, 8], "rows": [64, 256], "vec": [3, 3], "perm": [1, 0]}, "tune"):
         b = make_batch(cfr, games, max_games=len(mix), precision="fp64")
         ids = [b.add(g, v) for _, g, v in mix]
         if tiling == "tune":

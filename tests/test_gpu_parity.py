@@ -313,7 +313,8 @@ def test_quads_fp64_equal_elementwise(cfr, oracle_mod, games, name):
         g = games[name] if name in games else gg.make_config(name)
     say(f"case: {name} quads vs elements, fp64, nnz={g.nnz}")
     out = []
-    for tiling in (None, QUADS, dict(QUADS, perm=[1, 0], rows=[64, 256])):
+    for tiling in (None, QUADS, dict(QUADS, perm=[1, 0], rows=[64, 256]),
+                   dict(QUADS, items=[8, 8])):
         gpu = cfr.Solver(g, precision="fp64")
         if tiling is not None:
             gpu.tiling = tiling
