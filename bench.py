@@ -409,7 +409,7 @@ def main():
     ap.add_argument("--pool", type=int, default=64, help="serve: distinct games")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="serve: device budget")
     ap.add_argument("--max-games", type=int, default=256, help="serve: game slots")
-    ap.add_argument("--plain-stride", type=int, default=0,
+    ap.add_argument("--plain-stride", type=int, default=16,
                     help="batch: also solve every k-th game alone with vanilla CFR (0: skip)")
     ap.add_argument("--variant", default=None)
     ap.add_argument("--mode", default=None)

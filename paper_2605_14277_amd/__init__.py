@@ -430,6 +430,25 @@ def cfr_batch_destroy(h):
 
 # ---- convenience wrapper --------------------------------------------------------
 
+class _Untuned:
+    """A Solver or Batch seen by the tuning cache: its tiling, and the plain
+    autotuner (so the cache does not recurse into itself)."""
+
+    def __init__(self, obj, tune_fn):
+        self._obj, self._tune = obj, tune_fn
+
+    @property
+    def tiling(self):
+        return self._obj.tiling
+
+    @tiling.setter
+    def tiling(self, t):
+        self._obj.tiling = t
+
+    def tune(self, reps):
+        return self._tune(self._obj.h, reps)
+
+
 class Solver:
     """One game on one GPU.  Device memory comes from a torch uint8 tensor;
     work is enqueued on torch's current stream of that device."""
@@ -442,6 +461,8 @@ class Solver:
         self.torch = torch
         self.arrays = GameArrays(game, with_csc=with_csc)
         self.n_seq = list(self.arrays.n_seq)
+        self.precision = precision
+        self.nnz = int(game.nnz)
         o = cfr_options_default()
         o.precision = PRECISIONS[precision]
         o.dcfr_alpha, o.dcfr_beta, o.dcfr_gamma = float(alpha), float(beta), float(gamma)
@@ -502,7 +523,14 @@ class Solver:
     def tiling(self, t: dict):
         cfr_set_tiling(self.h, t)
 
-    def tune(self, reps: int = 10) -> dict:
+    def tune(self, reps: int = 10, cache: str | None = None) -> dict:
+        """Autotunes the product tiling; with `cache` (a JSON file path), a
+        tiling stored there for this game's size bucket is taken instead,
+        and a new choice is stored."""
+        if cache is not None:
+            from .tuning import size_key, tune_cached
+            key = size_key("solver", self.precision, self.nnz, self.n_seq, 1, LIB_PATH)
+            return tune_cached(_Untuned(self, cfr_tune), key, cache, reps)[0]
         return cfr_tune(self.h, reps)
 
     def close(self):
@@ -552,7 +580,9 @@ class Batch:
         self.opts = o
         self.workspace_bytes = cfr_batch_workspace_size(o)
         self.h = cfr_batch_create(o)
+        self.precision = precision
         self.n_seq = {}
+        self.nnz = {}
 
     @staticmethod
     def game_size(game) -> np.ndarray:
@@ -570,6 +600,7 @@ class Batch:
         gp.max_iterations = int(max_iterations)
         gid = cfr_batch_add(self.h, arrays, gp)
         self.n_seq[gid] = list(arrays.n_seq)
+        self.nnz[gid] = int(game.nnz)
         return gid
 
     def run(self, n: int) -> int:
@@ -589,6 +620,7 @@ class Batch:
     def remove(self, gid: int):
         cfr_batch_remove(self.h, gid)
         self.n_seq.pop(gid, None)
+        self.nnz.pop(gid, None)
 
     @property
     def tiling(self) -> dict:
@@ -598,7 +630,17 @@ class Batch:
     def tiling(self, t: dict):
         cfr_batch_set_tiling(self.h, t)
 
-    def tune(self, reps: int = 10) -> dict:
+    def tune(self, reps: int = 10, cache: str | None = None) -> dict:
+        """Autotunes the product tiling on the games held; with `cache` (a
+        JSON file path), a tiling stored there for this batch's size bucket
+        (total nonzeros and sequences, game count) is taken instead, and a
+        new choice is stored."""
+        if cache is not None:
+            from .tuning import size_key, tune_cached
+            nnz = sum(self.nnz.values())
+            seq = [sum(v[p] for v in self.n_seq.values()) for p in range(2)]
+            key = size_key("batch", self.precision, nnz, seq, len(self.n_seq), LIB_PATH)
+            return tune_cached(_Untuned(self, cfr_batch_tune), key, cache, reps)[0]
         return cfr_batch_tune(self.h, reps)
 
     def kernel_timing(self, enable: bool):

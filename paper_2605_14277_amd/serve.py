@@ -77,6 +77,7 @@ def add_prepared(batch: Batch, prep: Prepared, variant: str, target: float = 0.0
     _check(_lib.cfr_batch_add_prepared(batch.h, prep.h, C.byref(gp), C.byref(gid)),
            "cfr_batch_add_prepared")
     batch.n_seq[int(gid.value)] = list(prep.n_seq)
+    batch.nnz[int(gid.value)] = int(prep.units[4])
     return int(gid.value)
 
 

@@ -267,3 +267,38 @@ def test_prepare_without_device(cfr, games):
         rc = cfr._lib.cfr_prepare(C.byref(bad.desc), 0, C.byref(h))
         cfr._check(rc, "cfr_prepare")
     assert ei.value.code == cfr.CFR_EINVAL
+
+
+def test_tuning_cache_by_size_bucket(tmp_path):
+    """The tuning cache stores one tiling per size bucket and hands it back
+    without timing anything; another bucket, precision or kind tunes anew."""
+    from paper_2605_14277_amd import LIB_PATH
+    from paper_2605_14277_amd.tuning import size_key, tune_cached
+
+    class Fake:
+        def __init__(self, choice):
+            self.tiling, self.choice, self.calls = None, choice, 0
+
+        def tune(self, reps):
+            self.calls += 1
+            self.tiling = dict(self.choice)
+            return self.tiling
+
+    path = str(tmp_path / "tiling.json")
+    t1 = {"items": [16, 16], "rows": [256, 256], "vec": [3, 3], "perm": [0, 1]}
+    t2 = {"items": [8, 8], "rows": [128, 128], "vec": [2, 2], "perm": [1, 1]}
+    k = size_key("solver", "fp32_acc64", 100_555_072, [1_218_369, 3_648_993], 1, LIB_PATH)
+    # within the same powers of two: the same bucket
+    assert k == size_key("solver", "fp32_acc64", 1.1e8, [1.3e6, 3.5e6], 1, LIB_PATH)
+    assert k != size_key("solver", "fp64", 100_555_072, [1_218_369, 3_648_993], 1, LIB_PATH)
+    assert k != size_key("batch", "fp32_acc64", 100_555_072, [1_218_369, 3_648_993], 1, LIB_PATH)
+    assert k != size_key("solver", "fp32_acc64", 4e8, [1_218_369, 3_648_993], 1, LIB_PATH)
+    a = Fake(t1)
+    assert tune_cached(a, k, path, 3) == (t1, False) and a.calls == 1
+    b = Fake(t2)
+    assert tune_cached(b, k, path, 3) == (t1, True) and b.calls == 0 and b.tiling == t1
+    k2 = size_key("solver", "fp64", 100_555_072, [1_218_369, 3_648_993], 1, LIB_PATH)
+    c = Fake(t2)
+    assert tune_cached(c, k2, path, 3) == (t2, False) and c.calls == 1
+    import json
+    assert json.load(open(path)) == {k: t1, k2: t2}

@@ -254,6 +254,30 @@ def test_stream_load_forms_agree(cfr, mix, precision):
             assert np.array_equal(a, c)
 
 
+def test_tuning_cache(cfr, tmp_path):
+    """A tiling tuned once for a size bucket is taken by the next solver or
+    batch of that bucket."""
+    g = gg.cfg2_literal()
+    path = str(tmp_path / "tiling.json")
+    s = cfr.Solver(g, precision="fp32_acc64")
+    first = s.tune(reps=2, cache=path)
+    s.close()
+    s = cfr.Solver(g, precision="fp32_acc64")
+    assert s.tune(reps=2, cache=path) == first and s.tiling == first
+    s.close()
+    games = [g, g]
+    b = make_batch(cfr, games, max_games=2)
+    for x in games:
+        b.add(x, "cfr+")
+    tb = b.tune(reps=2, cache=path)
+    b.close()
+    b = make_batch(cfr, games, max_games=2)
+    for x in games:
+        b.add(x, "cfr+")
+    assert b.tune(reps=2, cache=path) == tb and b.tiling == tb
+    b.close()
+
+
 def test_single_solver_tune(cfr, oracle_mod):
     g = gg.cfg2_literal()
     s = cfr.Solver(g, precision="fp64")
