@@ -418,8 +418,9 @@ int cfr_batch_kernel_stats(cfr_batch *b, int kernel, int64_t *launches, double *
 /* Host seconds and calls spent so far by the batch's runtime: out[0..6]
  * seconds in table builds, graph captures, evaluations (including their
  * wait for the stream), iteration enqueues, game additions, removals and
- * quad-copy builds (stream form 3; part of the table builds); out[7..13]
- * the matching call counts.  For reports.                                 */
+ * quad-copy work (stream form 3: device builds, part of the table builds,
+ * and copies of prepared quads, part of the additions); out[7..13] the
+ * matching call counts.  For reports.                                     */
 int cfr_batch_host_stats(cfr_batch *b, double *out);
 
 int cfr_batch_destroy(cfr_batch *b);

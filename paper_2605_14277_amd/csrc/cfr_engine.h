@@ -291,7 +291,7 @@ struct Engine {
         kHostEnqueue,
         kHostAdd,
         kHostRemove,
-        kHostQuads,  // quad-copy builds (inside table builds)
+        kHostQuads,  // quad-copy work (device builds in table builds, prepared copies in adds)
         kHostN
     };
     double host_s[kHostN] = {0, 0, 0, 0, 0, 0, 0};

@@ -1246,6 +1246,7 @@ int Engine::add(const HostGame &hg, const GameImage &img, const GameParams &gp, 
     for (int w = 0; w < 2; ++w) {
         const GameImage::Quads &IQ = img.quads;
         if (vec[w] != 3 || !IQ.built[w] || IQ.perm[w] != perm_on[w]) continue;
+        HostTimer qtimer(&host_s[kHostQuads], &host_n[kHostQuads]);
         QuadStore &Q = quad[w];
         if (!Q.ptr) {
             if (hipMalloc((void **)&Q.ptr, 4 * (size_t)std::max<int64_t>(cap.seq[w], 1)) !=
