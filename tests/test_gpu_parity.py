@@ -299,6 +299,22 @@ def test_long_rows_quads(cfr, oracle_mod, cols):
     compare_fp64(gpu, orc, tol=1e-12, what=f"3x{cols}-quads")
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_acc64"])
+def test_quads_without_nonzeros(cfr, oracle_mod, precision):
+    """A game with no payoff nonzeros has no quads: every block of both
+    products is empty and writes zero utilities."""
+    g = gg.matrix_game(np.zeros((3, 4)))
+    assert g.nnz == 0
+    gpu = cfr.Solver(g, precision=precision)
+    gpu.tiling = QUADS
+    orc = oracle_mod.Oracle(g)
+    gpu.step(20, "dcfr", "alternating")
+    orc.step(20, "dcfr", "alternating")
+    for p in range(2):
+        assert np.allclose(gpu.strategy(p, "average"), orc.strategy(p, "average"), atol=1e-6)
+    assert gpu.exploitability("average")["expl"] == 0.0
+
+
 @pytest.mark.parametrize("name", ["stops", "cfg2_d8", "showdown", "cfg2"])
 def test_quads_fp64_equal_elementwise(cfr, oracle_mod, games, name):
     """Absent quad positions add -0.0, which leaves every FP64 row sum exactly
