@@ -125,12 +125,13 @@ def copy_probe(torch, nbytes: int = 1600 << 20, reps: int = 5):
 
 
 def parse_tiling(text: str) -> dict:
-    """'items_Ay,items_ATx:rows_Ay,rows_ATx[:vec_Ay,vec_ATx[:perm_Ay,perm_ATx]]'."""
+    """'items_Ay,items_ATx:rows_Ay,rows_ATx[:vec_Ay,vec_ATx[:perm_Ay,perm_ATx[:xcd_Ay,xcd_ATx]]]'."""
     parts = text.split(":")
     return {"items": [int(v) for v in parts[0].split(",")],
             "rows": [int(v) for v in parts[1].split(",")],
             "vec": [int(v) for v in parts[2].split(",")] if len(parts) > 2 else [1, 1],
-            "perm": [int(v) for v in parts[3].split(",")] if len(parts) > 3 else [0, 0]}
+            "perm": [int(v) for v in parts[3].split(",")] if len(parts) > 3 else [0, 0],
+            "xcd": [int(v) for v in parts[4].split(",")] if len(parts) > 4 else [1, 1]}
 
 
 def solve_alone(cfr, g, variant, target, max_it, K, precision, tiling=None):
@@ -422,7 +423,7 @@ def main():
                     help="keep the default product tiling instead of running the autotuner")
     ap.add_argument("--tiling", default=None,
                     help="fixed product tiling 'items_Ay,items_ATx:rows_Ay,rows_ATx:vec_Ay,vec_ATx:"
-                         "perm_Ay,perm_ATx' (skips the autotuner)")
+                         "perm_Ay,perm_ATx:xcd_Ay,xcd_ATx' (skips the autotuner)")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle time for the CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -248,15 +248,18 @@ int cfr_set_state(cfr_solver *s, const void *in, size_t len);
  * gathered strategy is copied into the order in which the rows first use
  * its entries, and the product gathers from that copy, so each row's
  * gathers touch consecutive entries; the index stream is renumbered once
- * when the flag changes).  Rows longer than one block's capacity are
- * summed by a tree in every order; every other row keeps its summation
- * order under every choice (quads add -0.0 at absent positions, which
- * changes no sum).                                                       */
+ * when the flag changes) and xcd (the order blocks are launched in, see
+ * below).  Rows longer than one block's capacity are summed by a tree in
+ * every order; every other row keeps its summation order under every
+ * choice (quads add -0.0 at absent positions, which changes no sum).     */
 typedef struct cfr_spmv_tiling {
     int items[2];
     int rows[2];
     int vec[2];
     int perm[2];
+    int xcd[2]; /* 1: blocks launched so that each XCD takes a contiguous
+                   range of them (neighbouring rows share its L2); 0: in
+                   table order                                            */
 } cfr_spmv_tiling;
 
 /* Reads / sets the solver's tiling (CFR_EINVAL outside the ranges above).  */
@@ -265,7 +268,8 @@ int cfr_set_tiling(cfr_solver *s, const cfr_spmv_tiling *t);
 
 /* Autotuner: times every supported tiling of each product on this game
  * (reps launches each, HIP events on the solver's stream), keeps the
- * fastest and writes it to *chosen (may be NULL).  Overwrites only the
+ * fastest (then times its other block order), and writes it to *chosen
+ * (may be NULL).  Overwrites only the
  * products' outputs, which every iteration recomputes first.  Waits for
  * the stream.                                                              */
 int cfr_tune(cfr_solver *s, int reps, cfr_spmv_tiling *chosen);

@@ -58,7 +58,7 @@ class cfr_options(C.Structure):
 
 class cfr_spmv_tiling(C.Structure):
     _fields_ = [("items", C.c_int * 2), ("rows", C.c_int * 2), ("vec", C.c_int * 2),
-                ("perm", C.c_int * 2)]
+                ("perm", C.c_int * 2), ("xcd", C.c_int * 2)]
 
 
 class cfr_batch_options(C.Structure):
@@ -278,7 +278,8 @@ def cfr_set_state(h, state: bytes):
 
 def _tiling_dict(t: cfr_spmv_tiling) -> dict:
     return {"items": [int(t.items[0]), int(t.items[1])], "rows": [int(t.rows[0]), int(t.rows[1])],
-            "vec": [int(t.vec[0]), int(t.vec[1])], "perm": [int(t.perm[0]), int(t.perm[1])]}
+            "vec": [int(t.vec[0]), int(t.vec[1])], "perm": [int(t.perm[0]), int(t.perm[1])],
+            "xcd": [int(t.xcd[0]), int(t.xcd[1])]}
 
 
 def _tiling_struct(d: dict) -> cfr_spmv_tiling:
@@ -288,6 +289,7 @@ def _tiling_struct(d: dict) -> cfr_spmv_tiling:
         t.rows[w] = int(d["rows"][w])
         t.vec[w] = int(d.get("vec", [1, 1])[w])
         t.perm[w] = int(d.get("perm", [0, 0])[w])
+        t.xcd[w] = int(d.get("xcd", [1, 1])[w])
     return t
 
 

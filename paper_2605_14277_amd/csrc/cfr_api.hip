@@ -180,6 +180,7 @@ int check_tiling(const cfr_spmv_tiling *t)
         if (t->vec[w] == 3 && t->items[w] < cfr::kQuadItemsMin)
             return fail(CFR_EINVAL, "stream form 3 takes 8 or 16 nonzeros per thread");
         if (t->perm[w] != 0 && t->perm[w] != 1) return fail(CFR_EINVAL, "perm must be 0 or 1");
+        if (t->xcd[w] != 0 && t->xcd[w] != 1) return fail(CFR_EINVAL, "xcd must be 0 or 1");
     }
     return CFR_OK;
 }
@@ -216,6 +217,7 @@ void get_tiling(const cfr::Engine &e, cfr_spmv_tiling *t)
         t->rows[w] = e.rows[w];
         t->vec[w] = e.vec[w];
         t->perm[w] = e.perm_on[w];
+        t->xcd[w] = e.xcd_remap[w];
     }
 }
 
@@ -224,6 +226,10 @@ int set_tiling(cfr::Engine &e, const cfr_spmv_tiling *t)
     for (int w = 0; w < 2; ++w) {
         int rc = e.set_perm(w, t->perm[w]);
         if (rc) return rc;
+        if (e.xcd_remap[w] != t->xcd[w]) {
+            e.xcd_remap[w] = t->xcd[w];
+            e.drop_graph();
+        }
         e.repartition(w, t->items[w], t->rows[w], t->vec[w]);
     }
     return CFR_OK;
@@ -270,6 +276,20 @@ int tune(cfr::Engine &e, int reps, cfr_spmv_tiling *chosen)
         int rc = e.set_perm(w, bp);
         if (rc) return rc;
         e.repartition(w, bi, br, bv);
+        // the block order of the winner, with the same hysteresis
+        {
+            double cur = 0, alt = 0;
+            rc = e.time_spmv(w, reps, &cur);
+            if (rc) return rc;
+            e.xcd_remap[w] ^= 1;
+            e.drop_graph();
+            rc = e.time_spmv(w, reps, &alt);
+            if (rc) return rc;
+            if (!(alt < 0.98 * cur)) {
+                e.xcd_remap[w] ^= 1;
+                e.drop_graph();
+            }
+        }
     }
     if (chosen) get_tiling(e, chosen);
     return CFR_OK;

@@ -246,7 +246,7 @@ struct Engine {
     int rows[2] = {kSpmvRowCap, kSpmvRowCap};
     int vec[2] = {1, 1};  // 16-byte stream loads in the products
     int perm_on[2] = {0, 0};  // the product gathers a first-touch-ordered copy
-    int xcd_remap = 1;
+    int xcd_remap[2] = {1, 1};  // per product: XCD-contiguous block order
     int device = 0;
     bool use_graph = true;
     bool lone = false;  // a single game: shallow levels may run as one launch

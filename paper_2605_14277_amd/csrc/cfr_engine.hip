@@ -1586,9 +1586,7 @@ hipError_t Engine::spmv(const Tables &T, int which, const void *xin, void *yout,
         xin = dp[q].xp;
     }
     const bool quads = vec[which] == 3;
-    // quads: the launch order of the blocks as they are (the XCD-contiguous
-    // remap measured ~1.5% slower on the large game in this form)
-    const int remap = quads ? 0 : xcd_remap;
+    const int remap = xcd_remap[which];
     const int32_t *rp = quads ? quad[which].ptr : ptr[which];
     const int32_t *ix = quads ? (const int32_t *)quad[which].idx : idx[which];
     const void *vl = quads ? quad[which].val : val[which];

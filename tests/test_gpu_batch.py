@@ -143,7 +143,7 @@ def test_targets_stop_games_at_checks(cfr, mix):
     b.close()
 
 
-QUADS = {"items": [16, 16], "rows": [256, 256], "vec": [3, 3], "perm": [0, 1]}
+QUADS = {"items": [16, 16], "rows": [256, 256], "vec": [3, 3], "perm": [0, 1], "xcd": [1, 0]}
 
 
 @pytest.mark.parametrize("tiling", [None, QUADS], ids=["elements", "quads"])
@@ -207,14 +207,16 @@ def test_tiling_and_tuner(cfr, mix):
     here exceeds the smallest block capacity)."""
     games = [g for _, g, _ in mix]
     out = []
-    for tiling in (None, {"items": [4, 8], "rows": [64, 128], "vec": [0, 1], "perm": [1, 0]},
-                   {"items": [16, 4], "rows": [256, 64], "vec": [1, 0], "perm": [0, 1]},
-                   {"items": [8, 8], "rows": [128, 128], "vec": [1, 1], "perm": [1, 1]},
-                   {"items": [16, 8], "rows": [256, 128], "vec": [2, 2], "perm": [0, 1]},
-                   {"items": [4, 16], "rows": [64, 256], "vec": [2, 0], "perm": [1, 0]},
-                   {"items": [16, 16], "rows": [256, 64], "vec": [3, 3], "perm": [0, 1]},
-                   {"items": [16, 8], "rows": [128, 256], "vec": [3, 2], "perm": [1, 1]},
-                   {"items": [8, 8], "rows": [64, 256], "vec": [3, 3], "perm": [1, 0]}, "tune"):
+    for tiling in (None,
+                   {"items": [4, 8], "rows": [64, 128], "vec": [0, 1], "perm": [1, 0], "xcd": [1, 0]},
+                   {"items": [16, 4], "rows": [256, 64], "vec": [1, 0], "perm": [0, 1], "xcd": [0, 1]},
+                   {"items": [8, 8], "rows": [128, 128], "vec": [1, 1], "perm": [1, 1], "xcd": [1, 1]},
+                   {"items": [16, 8], "rows": [256, 128], "vec": [2, 2], "perm": [0, 1], "xcd": [0, 0]},
+                   {"items": [4, 16], "rows": [64, 256], "vec": [2, 0], "perm": [1, 0], "xcd": [1, 0]},
+                   {"items": [16, 16], "rows": [256, 64], "vec": [3, 3], "perm": [0, 1], "xcd": [0, 1]},
+                   {"items": [16, 8], "rows": [128, 256], "vec": [3, 2], "perm": [1, 1], "xcd": [1, 1]},
+                   {"items": [8, 8], "rows": [64, 256], "vec": [3, 3], "perm": [1, 0], "xcd": [0, 0]},
+                   "tune"):
         b = make_batch(cfr, games, max_games=len(mix), precision="fp64")
         ids = [b.add(g, v) for _, g, v in mix]
         if tiling == "tune":
@@ -224,6 +226,7 @@ def test_tiling_and_tuner(cfr, mix):
             assert all(64 <= r <= 256 for r in chosen["rows"])
             assert all(v in (0, 1, 2, 3) for v in chosen["vec"])
             assert all(v in (0, 1) for v in chosen["perm"])
+            assert all(v in (0, 1) for v in chosen["xcd"])
         elif tiling is not None:
             b.tiling = tiling
             assert b.tiling == tiling

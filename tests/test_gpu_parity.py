@@ -280,7 +280,7 @@ def test_long_rows(cfr, oracle_mod, cols):
     compare_fp64(gpu, orc, tol=1e-12, what=f"3x{cols}")
 
 
-QUADS = {"items": [16, 16], "rows": [256, 128], "vec": [3, 3], "perm": [0, 1]}
+QUADS = {"items": [16, 16], "rows": [256, 128], "vec": [3, 3], "perm": [0, 1], "xcd": [1, 1]}
 
 
 @pytest.mark.parametrize("cols", [1023, 4096, 4100, 9000])

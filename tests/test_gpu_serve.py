@@ -42,7 +42,7 @@ def _requests(pool, n, mean_gap, seed):
     return out
 
 
-QUADS = {"items": [16, 16], "rows": [256, 256], "vec": [3, 3], "perm": [1, 1]}
+QUADS = {"items": [16, 16], "rows": [256, 256], "vec": [3, 3], "perm": [1, 1], "xcd": [0, 0]}
 
 
 @pytest.mark.parametrize("tiling", [None, QUADS], ids=["elements", "quads"])
