@@ -300,12 +300,19 @@ def bench_serving(args, torch):
     gaps = rng.exponential(1.0, size=n)
     budget = int(args.budget_gb * 1e9)
     mix = np.sum([p.units for p in prepared], axis=0) / args.pool
-    seq, inf, nz = serve.capacities_for_bytes(budget, mix, args.max_games, precision)
+    tiling = parse_tiling(args.serve_tiling)
+    quads = 3 in tiling["vec"]
+    # with quads, part of the budget goes to the quad stores (about 0.3 quads
+    # per nonzero for the games of this distribution, per product)
+    ws_budget = int(budget * (0.55 if quads else 1.0))
+    seq, inf, nz = serve.capacities_for_bytes(ws_budget, mix, args.max_games, precision)
+    vb = 8 if precision == "fp64" else 4
+    qcap = int(0.3 * nz) if quads else 0
     log(f"[bench] device budget {budget / 1e9:.0f} GB -> capacity {nz:.3e} nonzeros, "
-        f"{args.max_games} slots")
+        f"{args.max_games} slots" + (f", {qcap:.3e} quads per product "
+                                     f"({2 * qcap * (4 + 4 * vb) / 1e9:.0f} GB)" if quads else ""))
 
     # product tiling of the serving loop and of the one-at-a-time solves
-    tiling = parse_tiling(args.serve_tiling)
     log(f"[bench] product tiling {tiling}")
     if 3 in tiling["vec"]:
         # quad copies built with the prepared games (host, worker threads)
@@ -332,7 +339,7 @@ def bench_serving(args, torch):
                  "target": float(rel[k] * ranges[which[k]]), "max_iterations": max_it}
                 for k in range(n)]
         srv = serve.Server(seq, inf, nz, max_games=args.max_games, precision=precision,
-                           check_every=K, tiling=tiling)
+                           check_every=K, tiling=tiling, quad_capacity=qcap)
         t0 = time.perf_counter()
         out = srv.serve(reqs, prepared=prepared)
         host = srv.batch.host_stats()

@@ -321,6 +321,14 @@ typedef struct cfr_batch_options {
                                   added while others iterate joins at the
                                   next check, so its copies overlap one check
                                   period of the others.                     */
+    int64_t quad_capacity;     /* quads per product of the store that stream
+                                  form 3 uses, allocated at creation outside
+                                  the workspace (quad_capacity * (4 + 4 value
+                                  bytes) per product, plus a row pointer per
+                                  sequence index); 0: allocated when that form
+                                  is first used (min(2^26, nnz_capacity)) and
+                                  grown by doubling, each growth waiting for
+                                  the streams and copying the store.        */
 } cfr_batch_options;
 
 typedef struct cfr_game_params {

@@ -66,7 +66,8 @@ class cfr_batch_options(C.Structure):
                 ("max_games", C.c_int64), ("seq_capacity", C.c_int64 * 2),
                 ("inf_capacity", C.c_int64 * 2), ("nnz_capacity", C.c_int64),
                 ("check_every", C.c_int64), ("stream", C.c_void_p), ("device", C.c_int),
-                ("use_graph", C.c_int), ("down_pass", C.c_int), ("async_admission", C.c_int)]
+                ("use_graph", C.c_int), ("down_pass", C.c_int), ("async_admission", C.c_int),
+                ("quad_capacity", C.c_int64)]
 
 
 class cfr_game_params(C.Structure):
@@ -558,7 +559,7 @@ class Batch:
                  precision: str = "fp32_acc64", mode: str = "alternating",
                  check_every: int = 10, device: int = 0, use_graph: bool = True, stream=None,
                  spmv_order: str = "default", down_pass: str = "default",
-                 async_admission: bool = False):
+                 async_admission: bool = False, quad_capacity: int = 0):
         import torch
         o = cfr_batch_options_default()
         o.precision = PRECISIONS[precision]
@@ -574,6 +575,7 @@ class Batch:
         o.use_graph = int(bool(use_graph))
         o.down_pass = DOWN_PASS[down_pass]
         o.async_admission = int(bool(async_admission))
+        o.quad_capacity = int(quad_capacity)
         dev = torch.device("cuda", int(device))
         if stream is None:
             stream = torch.cuda.current_stream(dev)

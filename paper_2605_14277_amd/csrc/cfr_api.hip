@@ -800,6 +800,8 @@ static int batch_capacity(const cfr_batch_options *opt, cfr::Capacity &c)
     if (opt->check_every < 1) return fail(CFR_EINVAL, "check_every must be >= 1");
     if (opt->down_pass != CFR_DOWN_DEFAULT && opt->down_pass != CFR_DOWN_LEVELS)
         return fail(CFR_EINVAL, "unknown top-down pass");
+    if (opt->quad_capacity < 0 || opt->quad_capacity > ((int64_t)1 << 40))
+        return fail(CFR_EINVAL, "quad capacity out of range");
     c.slots = opt->max_games;
     for (int p = 0; p < 2; ++p) {
         c.seq[p] = opt->seq_capacity[p];
@@ -842,6 +844,7 @@ int cfr_batch_create(const cfr_batch_options *opt, cfr_batch **out)
         e.mode = opt->mode;
         e.check_every = opt->check_every;
         rc = e.init(c, opt->precision, opt->device, (hipStream_t)opt->stream, nullptr, 0);
+        if (rc == CFR_OK && opt->quad_capacity > 0) rc = e.reserve_quads(opt->quad_capacity);
         if (rc) {
             e.release();
             delete b;

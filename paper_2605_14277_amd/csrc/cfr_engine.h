@@ -334,6 +334,10 @@ struct Engine {
     int ensure_quads(const std::vector<int> &set);
     void drop_quads(Slot &s, int which);
     int grow_quads(int which, int64_t need);
+    // Allocates both products' quad stores with room for n quads each (and
+    // their row pointers); growth then starts from there.
+    int reserve_quads(int64_t n);
+    int64_t quad_reserved = 0;  // 0: first store min(kQuadStoreMin, nonzero capacity)
 
     std::vector<int> active_set() const;
     int build_tables(Tables &T, char *region, const std::vector<int> &set);

@@ -946,7 +946,8 @@ int Engine::grow_quads(int which, int64_t need)
     int64_t ncap = std::max<int64_t>(need, Q.cap + Q.cap / 2);
     // a batch starts with room for many games (each growth waits for both
     // streams and copies the store): min(kQuadStoreMin, its nonzero capacity)
-    if (!lone) ncap = std::max<int64_t>(ncap, std::min<int64_t>(kQuadStoreMin, cap.nnz));
+    if (!lone && quad_reserved == 0)
+        ncap = std::max<int64_t>(ncap, std::min<int64_t>(kQuadStoreMin, cap.nnz));
     uint32_t *ni = nullptr;
     void *nv = nullptr;
     hipError_t e = hipMalloc((void **)&ni, 4 * (size_t)ncap);
@@ -981,6 +982,27 @@ int Engine::grow_quads(int which, int64_t need)
     Q.cap = ncap;
     Q.alloc.cap = ncap;
     drop_graph();
+    return CFR_OK;
+}
+
+int Engine::reserve_quads(int64_t n)
+{
+    quad_reserved = n;
+    for (int w = 0; w < 2; ++w) {
+        QuadStore &Q = quad[w];
+        if (!Q.ptr) {
+            if (hipMalloc((void **)&Q.ptr, 4 * (size_t)std::max<int64_t>(cap.seq[w], 1)) !=
+                hipSuccess) {
+                Q.ptr = nullptr;
+                (void)hipGetLastError();
+                return fail(CFR_ENOMEM, "cannot allocate the quad row pointers of a product");
+            }
+        }
+        if (Q.cap < n) {
+            int rc = grow_quads(w, n);
+            if (rc) return rc;
+        }
+    }
     return CFR_OK;
 }
 

@@ -119,12 +119,14 @@ class Server:
 
     def __init__(self, seq_capacity, inf_capacity, nnz_capacity, max_games: int = 256,
                  precision: str = "fp32_acc64", check_every: int = 10, workers: int = 8,
-                 device: int = 0, async_admission: bool = True, tiling: dict | None = None):
+                 device: int = 0, async_admission: bool = True, tiling: dict | None = None,
+                 quad_capacity: int = 0):
         # asynchronous admission: a request's copies to the device overlap
         # the iterations of the requests already running
         self.batch = Batch(seq_capacity, inf_capacity, nnz_capacity, max_games=max_games,
                            precision=precision, mode="alternating", check_every=check_every,
-                           device=device, async_admission=async_admission)
+                           device=device, async_admission=async_admission,
+                           quad_capacity=quad_capacity)
         # column orders of the quad copies that arriving requests get built
         # on the worker threads (stream form 3 on some product), else None
         self.quad_perm = None

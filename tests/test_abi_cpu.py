@@ -212,7 +212,8 @@ def test_batch_workspace_linear_in_capacity(cfr):
     assert 16 <= per_nnz < 17
 
 
-@pytest.mark.parametrize("field,value", [("precision", 9), ("mode", 3), ("max_games", 0),
+@pytest.mark.parametrize("field,value", [("quad_capacity", -1), ("precision", 9), ("mode", 3),
+                                         ("max_games", 0),
                                          ("check_every", 0), ("nnz_capacity", -1),
                                          ("spmv_order", 5)])
 def test_batch_bad_options_rejected(cfr, field, value):

@@ -328,8 +328,10 @@ def test_asynchronous_admission(cfr, mix, tiling):
     preps = {n: serve.Prepared(pool[n][0], "fp64", quads=(1, 1) if tiling else None)
              for n in names}
     units = np.sum([preps[n].units for n in names], axis=0)
+    # with quads from images, a store reserved at creation (then grown)
     b = cfr.Batch([units[0], units[1]], [units[2], units[3]], int(units[4]), max_games=4,
-                  precision="fp64", check_every=10, async_admission=True)
+                  precision="fp64", check_every=10, async_admission=True,
+                  quad_capacity=1000 if tiling is not None and tiling["perm"] == [1, 1] else 0)
     if tiling is not None:
         b.tiling = tiling
     g1 = serve.add_prepared(b, preps["cfg1"], pool["cfg1"][1])
