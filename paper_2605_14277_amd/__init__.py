@@ -35,6 +35,12 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with "
                       "`python paper_2605_14277_amd/build.py` (there is no fallback path)")
 
+# torch brings its own HIP runtime.  Loaded first, it also serves the
+# library's libamdhip64 dependency, so the process has one runtime; if the
+# library were loaded first, it would bind the system runtime, torch would
+# then start a second one, and the library would find no device.
+import torch  # noqa: E402,F401
+
 
 class cfr_player_desc(C.Structure):
     _fields_ = [("n_seq", C.c_int64), ("n_inf", C.c_int64),
