@@ -142,7 +142,7 @@ __device__ __forceinline__ void store4(double *p, const double (&o)[4])
 // Per-iteration scalars
 // ---------------------------------------------------------------------------
 
-__device__ void begin_iteration(Scalars *sc)
+__device__ __forceinline__ void begin_iteration(Scalars *sc)
 {
     double t = sc->t + 1.0;
     sc->t = t;
@@ -163,6 +163,14 @@ __device__ void begin_iteration(Scalars *sc)
     double ta = pow(t, sc->alpha), tb = pow(t, sc->beta);
     sc->dpos = ta / (ta + 1.0);
     sc->dneg = tb / (tb + 1.0);
+}
+
+// Out of line, one copy per product kernel family: a called function is
+// compiled under its callers' register budget only when they all share it.
+template <bool QUADS>
+__device__ __noinline__ void begin_iteration_in(Scalars *sc)
+{
+    begin_iteration(sc);
 }
 
 // ---------------------------------------------------------------------------
@@ -202,7 +210,7 @@ __device__ void begin_iteration(Scalars *sc)
 // ignore it): index/value stream and row pointers in one round, gathers in
 // the next; the reduction then reads only LDS.
 template <int P, bool SEQ, int ITEMS, int VEC>
-__global__ __launch_bounds__(kSpmvThreads) void k_spmv(
+__device__ __forceinline__ void spmv_blocks(
     int32_t n_blk, const SpmvBlock *__restrict__ tab, const int32_t *__restrict__ ptr,
     const int32_t *__restrict__ idx, const typename Types<P>::V *__restrict__ val,
     const typename Types<P>::V *__restrict__ xin, typename Types<P>::V *__restrict__ yout,
@@ -213,7 +221,10 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(
     // products staged in LDS: the compute type, or the value type when the
     // FP32 modes are built to stage them compactly
     using L = typename std::conditional<(CFR_SPMV_LDS_VALUE != 0) && P != CFR_FP64, V, C>::type;
-    constexpr int kCap = kSpmvThreads * ITEMS;  // staged products per block
+    // staged products per block; summed quads take one slot each, so that
+    // form needs a quarter of the space (and leaves LDS out of the
+    // occupancy limit)
+    constexpr int kCap = VEC == 3 && !SEQ ? kSpmvThreads * ITEMS / 4 : kSpmvThreads * ITEMS;
     __shared__ L prod[kCap];
     __shared__ int32_t s_ptr[kSpmvRowCap + 1];
     __shared__ C red[kSpmvThreads];
@@ -229,7 +240,8 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(
     if (bid >= n_blk) return;
     const int tid = threadIdx.x;
     const SpmvBlock bk = tab[bid];
-    if (begin && bk.begin && tid == 0) begin_iteration(sc + bk.slot);
+    if (begin && bk.begin && tid == 0)
+        begin_iteration_in<VEC == 3 && !SEQ && P != CFR_FP64>(sc + bk.slot);
     const int32_t rb = bk.row0, nr = bk.nr, n = bk.n, p0 = bk.p0;
     const int64_t e0 = bk.e0;
 
@@ -477,6 +489,30 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(
         if (lane == 0) yout[rb + r] = (V)acc;
     }
 }
+
+#define CFR_SPMV_PARAMS(P)                                                                    \
+    int32_t n_blk, const SpmvBlock *__restrict__ tab, const int32_t *__restrict__ ptr,        \
+        const int32_t *__restrict__ idx, const typename Types<P>::V *__restrict__ val,        \
+        const typename Types<P>::V *__restrict__ xin, typename Types<P>::V *__restrict__ yout, \
+        int xcd_remap, int begin, Scalars *sc
+
+template <int P, bool SEQ, int ITEMS, int VEC>
+__global__ __launch_bounds__(kSpmvThreads) void k_spmv(CFR_SPMV_PARAMS(P))
+{
+    spmv_blocks<P, SEQ, ITEMS, VEC>(n_blk, tab, ptr, idx, val, xin, yout, xcd_remap, begin, sc);
+}
+
+// Summed quads with FP32 values.  Left to itself the compiler gives this
+// form more than 100 SGPRs, which allows seven waves per SIMD; it fits in
+// eight (at most 64 VGPRs, a few SGPRs kept in VGPR lanes), which keeps more
+// of the stream in flight, so the bound asks for eight.  The other forms
+// keep the compiler's choice (eight would spill VGPRs to memory there).
+template <int P, int ITEMS>
+__global__ __launch_bounds__(kSpmvThreads, 8) void k_spmv_quads(CFR_SPMV_PARAMS(P))
+{
+    spmv_blocks<P, false, ITEMS, 3>(n_blk, tab, ptr, idx, val, xin, yout, xcd_remap, begin, sc);
+}
+#undef CFR_SPMV_PARAMS
 
 // ---------------------------------------------------------------------------
 // ObserveUtility for one level, fused with the variant and regret matching
@@ -1184,9 +1220,14 @@ hipError_t spmv_launch(const SpmvBlock *tab, int32_t n_tab, const int32_t *ptr, 
 {
     using V = typename Types<P>::V;
     unsigned grid = xcd_remap ? (unsigned)(((n_tab + 7) / 8) * 8) : (unsigned)n_tab;
-    hipLaunchKernelGGL((k_spmv<P, SEQ, ITEMS, VEC>), dim3(grid), dim3(kSpmvThreads), 0, st, n_tab,
-                       tab, ptr, idx, (const V *)val, (const V *)xin, (V *)yout, xcd_remap, begin,
-                       sc);
+    if constexpr (VEC == 3 && !SEQ && P != CFR_FP64)
+        hipLaunchKernelGGL((k_spmv_quads<P, ITEMS>), dim3(grid), dim3(kSpmvThreads), 0, st, n_tab,
+                           tab, ptr, idx, (const V *)val, (const V *)xin, (V *)yout, xcd_remap,
+                           begin, sc);
+    else
+        hipLaunchKernelGGL((k_spmv<P, SEQ, ITEMS, VEC>), dim3(grid), dim3(kSpmvThreads), 0, st,
+                           n_tab, tab, ptr, idx, (const V *)val, (const V *)xin, (V *)yout,
+                           xcd_remap, begin, sc);
     return hipGetLastError();
 }
 
