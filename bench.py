@@ -596,7 +596,11 @@ def main():
                      "traffic": traffic, "avg_launch_us": avg_ms * 1e3,
                      "bytes_per_launch": by, "stream_form": tiling["vec"][w],
                      "format_bytes_per_launch": by_format, "format_gbs": format_gbs,
-                     "format_frac": format_gbs / HBM_PEAK_GBS},
+                     "format_frac": format_gbs / HBM_PEAK_GBS,
+                     "basis": "achieved/frac: element-stream bytes (index + value per nonzero, "
+                              "row pointers, gathered vector, output) per kernel-only HIP-event "
+                              "time; format_*: the bytes of the stream form the launch reads "
+                              "(quads move fewer, so frac can pass 1 while format_frac < 1)"},
         "cpu_baseline": cpu,
         "expl_average": e["expl"],
     }

@@ -207,9 +207,11 @@ int cfr_exploitability(cfr_solver *s, int kind, double *out);
 /* Iterations completed so far (host counter; the device holds its own).   */
 int cfr_iteration(cfr_solver *s, int64_t *t);
 
-/* Enables (1) or disables (0) per-kernel timing with HIP events recorded on
- * the solver's stream around every payoff-product launch, and resets the
- * accumulated statistics.  Graph replay is bypassed while enabled.         */
+/* Enables (1) or disables (0) per-kernel timing of every payoff-product
+ * launch with a pair of HIP events that the launch itself sets to the
+ * kernel's start and end times (hipExtLaunchKernel; the span a profiler's
+ * kernel trace reports), and resets the accumulated statistics.  Graph
+ * replay is bypassed while enabled.                                        */
 int cfr_kernel_timing(cfr_solver *s, int enable);
 
 /* Accumulated launches and total milliseconds of one timed kernel class

@@ -1617,10 +1617,8 @@ hipError_t Engine::spmv(const Tables &T, int which, const void *xin, void *yout,
         hipError_t e = hipEventCreate(&a);
         if (e == hipSuccess) e = hipEventCreate(&b);
         if (e != hipSuccess) return e;
-        (void)hipEventRecord(a, s);
         e = launch_spmv(prec, items[which], vec[which], tab, n, rp, ix, vl, xin, yout, remap,
-                        sequential(), begin ? 1 : 0, sc, s);
-        (void)hipEventRecord(b, s);
+                        sequential(), begin ? 1 : 0, sc, s, a, b);
         events[which].emplace_back(a, b);
         launches[which]++;
         return e;

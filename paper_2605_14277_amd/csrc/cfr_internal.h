@@ -104,11 +104,13 @@ struct DevPlayer {
 // per thread of the kernel instance (the block partition must hold at most
 // spmv_block_cap(items) nonzeros per block, or one row); vec: 16-byte
 // stream loads.  The index and value arrays must be readable three elements
-// past the last nonzero.
+// past the last nonzero.  start/stop (both or neither): events the launch
+// sets to the kernel's own start and end times (not to be used under graph
+// capture).
 hipError_t launch_spmv(int prec, int items, int vec, const SpmvBlock *tab, int32_t n_tab,
                        const int32_t *ptr, const int32_t *idx, const void *val, const void *xin,
                        void *yout, int xcd_remap, int sequential, int begin, Scalars *sc,
-                       hipStream_t st);
+                       hipStream_t st, hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 // ObserveUtility on the decision points of `tab` (one level), fused with the
 // variant's post-step and regret matching; kind 0 generic, 1 fast, 2 fast
 // without children; root: the level under the empty sequence, whose

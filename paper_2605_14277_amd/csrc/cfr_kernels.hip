@@ -33,6 +33,8 @@
 // iterates do not depend on which other games share its launches.
 #include "cfr_internal.h"
 
+#include <hip/hip_ext.h>
+
 #include <cfloat>
 #include <type_traits>
 
@@ -1216,36 +1218,48 @@ Kids<P> kids(const DevPlayer &p)
 template <int P, bool SEQ, int ITEMS, int VEC>
 hipError_t spmv_launch(const SpmvBlock *tab, int32_t n_tab, const int32_t *ptr, const int32_t *idx,
                        const void *val, const void *xin, void *yout, int xcd_remap, int begin,
-                       Scalars *sc, hipStream_t st)
+                       Scalars *sc, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
 {
     using V = typename Types<P>::V;
     unsigned grid = xcd_remap ? (unsigned)(((n_tab + 7) / 8) * 8) : (unsigned)n_tab;
+    // With events, the launch itself sets them to the kernel's start and end
+    // (what a profiler's kernel trace reads), not the stream's progress
+    // around it.
+#define CFR_SPMV_GO(KERNEL)                                                                   \
+    do {                                                                                      \
+        if (ev0)                                                                              \
+            hipExtLaunchKernelGGL(KERNEL, dim3(grid), dim3(kSpmvThreads), 0, st, ev0, ev1, 0u, \
+                                  n_tab, tab, ptr, idx, (const V *)val, (const V *)xin,       \
+                                  (V *)yout, xcd_remap, begin, sc);                           \
+        else                                                                                  \
+            hipLaunchKernelGGL(KERNEL, dim3(grid), dim3(kSpmvThreads), 0, st, n_tab, tab, ptr, \
+                               idx, (const V *)val, (const V *)xin, (V *)yout, xcd_remap,     \
+                               begin, sc);                                                    \
+    } while (0)
     if constexpr (VEC == 3 && !SEQ && P != CFR_FP64)
-        hipLaunchKernelGGL((k_spmv_quads<P, ITEMS>), dim3(grid), dim3(kSpmvThreads), 0, st, n_tab,
-                           tab, ptr, idx, (const V *)val, (const V *)xin, (V *)yout, xcd_remap,
-                           begin, sc);
+        CFR_SPMV_GO((k_spmv_quads<P, ITEMS>));
     else
-        hipLaunchKernelGGL((k_spmv<P, SEQ, ITEMS, VEC>), dim3(grid), dim3(kSpmvThreads), 0, st,
-                           n_tab, tab, ptr, idx, (const V *)val, (const V *)xin, (V *)yout,
-                           xcd_remap, begin, sc);
+        CFR_SPMV_GO((k_spmv<P, SEQ, ITEMS, VEC>));
+#undef CFR_SPMV_GO
     return hipGetLastError();
 }
 
 template <int P, bool SEQ, int VEC>
 hipError_t spmv_items(int items, const SpmvBlock *tab, int32_t n_tab, const int32_t *ptr,
                       const int32_t *idx, const void *val, const void *xin, void *yout,
-                      int xcd_remap, int begin, Scalars *sc, hipStream_t st)
+                      int xcd_remap, int begin, Scalars *sc, hipStream_t st, hipEvent_t ev0,
+                      hipEvent_t ev1)
 {
     switch (items) {
     case 4:
         return spmv_launch<P, SEQ, 4, VEC>(tab, n_tab, ptr, idx, val, xin, yout, xcd_remap, begin,
-                                           sc, st);
+                                           sc, st, ev0, ev1);
     case 8:
         return spmv_launch<P, SEQ, 8, VEC>(tab, n_tab, ptr, idx, val, xin, yout, xcd_remap, begin,
-                                           sc, st);
+                                           sc, st, ev0, ev1);
     case 16:
         return spmv_launch<P, SEQ, 16, VEC>(tab, n_tab, ptr, idx, val, xin, yout, xcd_remap, begin,
-                                            sc, st);
+                                            sc, st, ev0, ev1);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1253,23 +1267,28 @@ hipError_t spmv_items(int items, const SpmvBlock *tab, int32_t n_tab, const int3
 template <int P>
 hipError_t spmv_t(int items, int vec, const SpmvBlock *tab, int32_t n_tab, const int32_t *ptr,
                   const int32_t *idx, const void *val, const void *xin, void *yout, int xcd_remap,
-                  int sequential, int begin, Scalars *sc, hipStream_t st)
+                  int sequential, int begin, Scalars *sc, hipStream_t st, hipEvent_t ev0,
+                  hipEvent_t ev1)
 {
-    if (n_tab <= 0) return hipSuccess;
+    if (n_tab <= 0) {
+        // nothing to launch: the events still mark this point of the stream
+        if (ev0 && hipEventRecord(ev0, st) == hipSuccess) return hipEventRecord(ev1, st);
+        return hipSuccess;
+    }
 #define CFR_SPMV_VEC(SQ)                                                                      \
     switch (vec) {                                                                            \
     case 0:                                                                                   \
         return spmv_items<P, SQ, 0>(items, tab, n_tab, ptr, idx, val, xin, yout, xcd_remap,   \
-                                    begin, sc, st);                                           \
+                                    begin, sc, st, ev0, ev1);                                 \
     case 1:                                                                                   \
         return spmv_items<P, SQ, 1>(items, tab, n_tab, ptr, idx, val, xin, yout, xcd_remap,   \
-                                    begin, sc, st);                                           \
+                                    begin, sc, st, ev0, ev1);                                 \
     case 2:                                                                                   \
         return spmv_items<P, SQ, 2>(items, tab, n_tab, ptr, idx, val, xin, yout, xcd_remap,   \
-                                    begin, sc, st);                                           \
+                                    begin, sc, st, ev0, ev1);                                 \
     case 3:                                                                                   \
         return spmv_items<P, SQ, 3>(items, tab, n_tab, ptr, idx, val, xin, yout, xcd_remap,   \
-                                    begin, sc, st);                                           \
+                                    begin, sc, st, ev0, ev1);                                 \
     default: return hipErrorInvalidValue;                                                     \
     }
     if (sequential) {
@@ -1453,10 +1472,10 @@ hipError_t dot_t(const RangeBlock *tab, int32_t n_tab, const void *a, const void
 hipError_t launch_spmv(int prec, int items, int vec, const SpmvBlock *tab, int32_t n_tab,
                        const int32_t *ptr, const int32_t *idx, const void *val, const void *xin,
                        void *yout, int xcd_remap, int sequential, int begin, Scalars *sc,
-                       hipStream_t st)
+                       hipStream_t st, hipEvent_t start, hipEvent_t stop)
 {
     CFR_DISPATCH(prec, spmv_t<P>(items, vec, tab, n_tab, ptr, idx, val, xin, yout, xcd_remap,
-                                 sequential, begin, sc, st));
+                                 sequential, begin, sc, st, start, stop));
 }
 
 hipError_t launch_up(int prec, int variant, int kind, int root, const RangeBlock *tab,
