@@ -394,13 +394,87 @@ def bench_serving(args, torch):
     print(json.dumps(out), flush=True)
 
 
+# Game sizes of the size sweep: (terminals, depth, terminal window)
+SIZE_TREES = ((1e3, 6, 900, 1100), (1e4, 8, 9000, 11000), (1e5, 10, 96000, 106000))
+SIZE_SIGNALS = (8, 16, 32)
+
+
+def bench_sizes(args, torch):
+    """Iterations/s against game size: the large game's generator at about
+    1e3, 1e4 and 1e5 terminals with 8, 16 and 32 signals (5e4 to 1e8 payoff
+    nonzeros), DCFR(1.5, 0, 2) alternating, FP32 values with FP64
+    accumulators, autotuned tiling, graph replay; beside each the
+    single-threaded FP64 oracle on a bounded sample of the same solve."""
+    import gamegen as gg
+    import paper_2605_14277_amd as cfr
+
+    variant, mode, precision = "dcfr", "alternating", args.precision or "fp32_acc64"
+    vbytes = 8 if precision == "fp64" else 4
+    budget = min(args.cpu_budget, 3.0)
+    rows = []
+    for T, depth, lo, hi in SIZE_TREES:
+        for S in SIZE_SIGNALS:
+            g = gg.showdown_sized(S, depth, lo, hi, f"sizes-T{T:.0e}-S{S}")
+            s = cfr.Solver(g, precision=precision, device=0)
+            tiling = s.tune(reps=5)
+            s.step(args.warmup, variant, mode)
+            torch.cuda.synchronize()
+            # about 0.3 s of timed iterations
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s.stream)
+            s.step(20, variant, mode)
+            e1.record(s.stream)
+            torch.cuda.synchronize()
+            k = int(min(5000, max(50, 0.3 / max(e0.elapsed_time(e1) / 20 * 1e-3, 1e-9))))
+            e0.record(s.stream)
+            s.step(k, variant, mode)
+            e1.record(s.stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / k
+            s.kernel_timing(True)
+            s.step(20, variant, mode)
+            torch.cuda.synchronize()
+            prod = []
+            for w in (0, 1):
+                n, tot, _ = s.kernel_stats(w)
+                rr, cc = g.n_seq[w], g.n_seq[1 - w]
+                by = float(g.nnz * (4 + vbytes) + 4 * (rr + 1) + vbytes * (cc + rr))
+                prod.append((tot / n, by))
+            s.kernel_timing(False)
+            slow_ms, slow_by = max(prod)
+            s.close()
+            n_cpu, el = cpu_baseline(g, variant, mode, budget)
+            row = {"terminals": g.tree.n_terminals, "S": S, "depth": depth,
+                   "nnz": int(g.nnz), "n_seq": [int(v) for v in g.n_seq],
+                   "gpu_iters_per_s": 1e3 / ms, "nnz_iters_per_s": g.nnz * 1e3 / ms,
+                   "product_us": slow_ms * 1e3,
+                   "product_gbs": slow_by / (slow_ms * 1e-3) / 1e9,
+                   "cpu_iters_per_s": n_cpu / el, "speedup": (1e3 / ms) / (n_cpu / el),
+                   "tiling": tiling}
+            rows.append(row)
+            log(f"[sizes] T~{T:.0e} S={S:2d}: nnz {g.nnz:.3e}, GPU {row['gpu_iters_per_s']:9.0f} it/s "
+                f"({row['nnz_iters_per_s']:.2e} nnz*it/s, slower product {row['product_us']:.1f} us "
+                f"= {row['product_gbs']:.0f} GB/s), oracle {row['cpu_iters_per_s']:9.1f} it/s, "
+                f"x{row['speedup']:.1f}")
+    out = {"metric": "GPU iterations/s over the single-threaded CPU oracle's, by game size",
+           "value": rows[-1]["speedup"], "unit": "x", "n_gpus": 1, "steps": None,
+           "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32+f64acc" if precision == "fp32_acc64" else precision, "data": "synthetic",
+           "config": {"workload": "large-game generator at ~1e3/1e4/1e5 terminals x 8/16/32 "
+                                  "signals, dcfr, alternating", "cpu_budget_s": budget,
+                      "cpu_cores": 1},
+           "sizes": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--config", default="cfg3",
-                    choices=["cfg1", "cfg2", "cfg2_d8", "cfg3", "batch", "serve"])
+                    choices=["cfg1", "cfg2", "cfg2_d8", "cfg3", "batch", "serve", "sizes"])
     ap.add_argument("--games", type=int, default=256, help="batch: number of games")
     ap.add_argument("--check-every", type=int, default=10, help="batch: iterations per check")
     ap.add_argument("--max-iterations", type=int, default=2000, help="batch: iteration limit")
@@ -454,6 +528,9 @@ def main():
         return
     if args.config == "serve":
         bench_serving(args, torch)
+        return
+    if args.config == "sizes":
+        bench_sizes(args, torch)
         return
 
     import gamegen as gg

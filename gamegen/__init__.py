@@ -588,6 +588,14 @@ def _seed_select(start, lo, hi, S, max_depth, blo, bhi, p_stop, kind, name):
     return g
 
 
+def showdown_sized(S: int, max_depth: int, t_lo: int, t_hi: int, name: str,
+                   start: int = 3000) -> Game:
+    """The large game's generator (branching U{2,3,4}, no stop, showdown
+    payoffs) at another size: S signals, the given depth, the first seed
+    >= start whose tree has t_lo..t_hi terminals."""
+    return _seed_select(start, t_lo, t_hi, S, max_depth, 2, 4, 0.0, "showdown", name)
+
+
 def cfg2() -> Game:
     """Medium game: 13 signals, branching U{2,3}, stop 0.15 per non-root
     node, maximum depth 13 (the depth that reaches ~2e4 terminals),

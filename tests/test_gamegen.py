@@ -87,3 +87,16 @@ def test_showdown_ties_not_stored():
     # every terminal contributes S*(S-1) nonzeros: ties are exact zeros
     assert g.nnz == g.tree.n_terminals * 4 * 3
     assert np.all(g.val != 0.0)
+
+
+@pytest.mark.parametrize("S,depth,lo,hi", [(8, 6, 900, 1100), (16, 8, 9000, 11000)])
+def test_showdown_sized(S, depth, lo, hi):
+    """The size sweep's games: the terminal count falls in the window, every
+    terminal contributes one nonzero per ordered pair of distinct signals
+    (ties are exact zeros and are not stored), and the draw is repeatable."""
+    g = gg.showdown_sized(S, depth, lo, hi, "sized")
+    T = g.tree.n_terminals
+    assert lo <= T <= hi
+    assert g.nnz == T * S * (S - 1)
+    h = gg.showdown_sized(S, depth, lo, hi, "sized")
+    assert np.array_equal(g.val, h.val) and np.array_equal(g.col_idx, h.col_idx)
