@@ -488,3 +488,19 @@ def test_checkpoint_resume_equals_uninterrupted(cfr, games, precision, variant):
     assert ei.value.code == cfr.CFR_EINVAL
     for x in (a, b, c, other):
         x.close()
+
+
+@pytest.mark.parametrize("avg", ["uniform", "linear", "quadratic", "pow_gamma"])
+@pytest.mark.parametrize("mode", MODES)
+def test_linear_cfr_and_averaging_weights(cfr, oracle_mod, games, avg, mode):
+    """Linear CFR as DCFR(1, 1, 1), under each averaging weight a caller can
+    set: the FP64 GPU path against the oracle run with the same parameters."""
+    g = games["cfg2_d8"] if "cfg2_d8" in games else gg.make_config("cfg2_d8")
+    say(f"case: cfg2_d8 dcfr(1,1,1) avg={avg} {mode}")
+    gpu = cfr.Solver(g, precision="fp64", alpha=1.0, beta=1.0, gamma=1.0, avg=avg)
+    orc = oracle_mod.Oracle(g, alpha=1.0, beta=1.0, gamma=1.0, avg=avg)
+    gpu.step(150, "dcfr", mode)
+    orc.step(150, "dcfr", mode)
+    compare_fp64(gpu, orc, tol=1e-9, what=f"lcfr-{avg}-{mode}")
+    gpu.close()
+    orc.close()
