@@ -504,3 +504,54 @@ def test_linear_cfr_and_averaging_weights(cfr, oracle_mod, games, avg, mode):
     compare_fp64(gpu, orc, tol=1e-9, what=f"lcfr-{avg}-{mode}")
     gpu.close()
     orc.close()
+
+
+def _wide_game(name):
+    """Public trees with wide nodes: up to 7 actions and 7 decision points
+    below a sequence (wide7), or up to 12 of both (wide12)."""
+    if name == "wide7":
+        return gg.public_game(7, S=3, max_depth=4, branch_lo=5, branch_hi=7, p_stop=0.0,
+                              payoff_kind="iid", name="wide7")
+    return gg.public_game(8, S=2, max_depth=3, branch_lo=9, branch_hi=12, p_stop=0.0,
+                          payoff_kind="iid", name="wide12")
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("name", ["wide7", "wide12"])
+def test_wide_decision_points_fp64(cfr, oracle_mod, name, variant):
+    """Decision points with more than four actions and sequences with more
+    than four decision points below them take the generic sweep instance
+    (child values read in chunks; above eight actions, the values are
+    recomputed instead of held): FP64 within 1e-9 of the oracle, both
+    schedules, best responses included."""
+    g = _wide_game(name)
+    for mode in MODES:
+        say(f"case: {name} {variant} {mode} fp64 nnz={g.nnz}")
+        gpu, orc = run_pair(cfr, oracle_mod, g, variant, mode, 200)
+        compare_fp64(gpu, orc, tol=1e-9, what=f"{name}-{variant}-{mode}")
+        gpu.close()
+        orc.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_acc64"])
+def test_wide_games_batched_equal_alone(cfr, precision):
+    """The wide games in one batch with a narrow one: each equals the same
+    game solved alone bit for bit."""
+    games = [_wide_game("wide7"), _wide_game("wide12"), gg.make_config("cfg2_d8")]
+    sizes = np.sum([cfr.Batch.game_size(g) for g in games], axis=0)
+    b = cfr.Batch([int(sizes[0]), int(sizes[1])], [int(sizes[2]), int(sizes[3])], int(sizes[4]),
+                  max_games=4,
+                  precision=precision, mode="alternating", check_every=10)
+    ids = [b.add(g, "pcfr+") for g in games]
+    b.run(60)
+    for gid, g in zip(ids, games):
+        solo = cfr.Solver(g, precision=precision)
+        solo.step(60, "pcfr+", "alternating")
+        for p in range(2):
+            for kind in ("current", "average"):
+                assert np.array_equal(b.strategy(gid, p, kind), solo.strategy(p, kind)), \
+                    (g.name, p, kind)
+        for kind in ("current", "average"):
+            assert b.exploitability(gid, kind)["expl"] == solo.exploitability(kind)["expl"]
+        solo.close()
+    b.close()
