@@ -655,27 +655,79 @@ __device__ __forceinline__ void up_infoset(
         return;
     }
 
-    // large decision points: recompute instead of holding every action
+    // large decision points: recompute instead of holding every action.
+    // The actions go in groups of four: a group's per-action loads
+    // (payoff, slot count or child range, strategy, regret) are issued
+    // together before its child sums, instead of one action after another;
+    // the arithmetic is the same, in the same order.
+    constexpr int kGroup = 4;
+    auto group_q = [&](int32_t g0, C (&q)[kGroup]) {
+        int32_t cnt[kGroup], c0[kGroup], c1[kGroup];
+#pragma unroll
+        for (int k = 0; k < kGroup; ++k) {
+            const int32_t a = g0 + k < a1 ? g0 + k : a1 - 1;
+            q[k] = usign * (C)g[a];
+            cnt[k] = (SL & kSlotsRead) ? (int)kd.ccount[a] : kFastKids + 1;
+            c0[k] = child_ptr[a];
+            c1[k] = child_ptr[a + 1];
+        }
+#pragma unroll
+        for (int k = 0; k < kGroup; ++k) {
+            const int32_t a = g0 + k;
+            if (a >= a1) continue;
+            if (cnt[k] <= kFastKids) {
+                for (int i = 0; i < cnt[k]; ++i) q[k] = q[k] + kd.cval[4 * (int64_t)a + i];
+            } else {
+                q[k] = child_sum<P>(q[k], c0[k], c1[k], child_idx, vinf);
+            }
+        }
+    };
     C V_ = 0;
-    for (int32_t a = a0; a < a1; ++a) V_ = V_ + (C)b[a] * cf_utility(a);
+    for (int32_t g0 = a0; g0 < a1; g0 += kGroup) {
+        C q[kGroup], bb[kGroup];
+#pragma unroll
+        for (int k = 0; k < kGroup; ++k) bb[k] = (C)b[g0 + k < a1 ? g0 + k : a1 - 1];
+        group_q(g0, q);
+#pragma unroll
+        for (int k = 0; k < kGroup; ++k)
+            if (g0 + k < a1) V_ = V_ + bb[k] * q[k];
+    }
     store_value(kd, cs, j, vinf, V_);
     C Z = 0;
-    for (int32_t a = a0; a < a1; ++a) {
-        C inst = cf_utility(a) - V_;
-        C rr = post_step<P, VAR>((C)r[a] + inst, dpos, dneg);
-        r[a] = (R)rr;
-        C zz = (C)(R)rr;
-        if (kPred) {
-            m[a] = (R)inst;
-            zz = zz + (C)(R)inst;
+    for (int32_t g0 = a0; g0 < a1; g0 += kGroup) {
+        C q[kGroup], rv[kGroup];
+#pragma unroll
+        for (int k = 0; k < kGroup; ++k) rv[k] = (C)r[g0 + k < a1 ? g0 + k : a1 - 1];
+        group_q(g0, q);
+#pragma unroll
+        for (int k = 0; k < kGroup; ++k) {
+            const int32_t a = g0 + k;
+            if (a >= a1) continue;
+            C inst = q[k] - V_;
+            C rr = post_step<P, VAR>(rv[k] + inst, dpos, dneg);
+            r[a] = (R)rr;
+            C zz = (C)(R)rr;
+            if (kPred) {
+                m[a] = (R)inst;
+                zz = zz + (C)(R)inst;
+            }
+            Z = Z + (zz > 0 ? zz : 0);
         }
-        Z = Z + (zz > 0 ? zz : 0);
     }
-    for (int32_t a = a0; a < a1; ++a) {
-        C zz = (C)r[a];
-        if (kPred) zz = zz + (C)m[a];
-        zz = zz > 0 ? zz : 0;
-        b[a] = (V)(Z > 0 ? zz / Z : (C)1 / (C)n);
+    for (int32_t g0 = a0; g0 < a1; g0 += kGroup) {
+        C zz[kGroup];
+#pragma unroll
+        for (int k = 0; k < kGroup; ++k) {
+            const int32_t a = g0 + k < a1 ? g0 + k : a1 - 1;
+            zz[k] = (C)r[a];
+            if (kPred) zz[k] = zz[k] + (C)m[a];
+        }
+#pragma unroll
+        for (int k = 0; k < kGroup; ++k) {
+            if (g0 + k >= a1) continue;
+            const C z = zz[k] > 0 ? zz[k] : 0;
+            b[g0 + k] = (V)(Z > 0 ? z / Z : (C)1 / (C)n);
+        }
     }
 }
 
