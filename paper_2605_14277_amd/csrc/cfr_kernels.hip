@@ -608,26 +608,44 @@ __device__ __forceinline__ void up_infoset(
     const int32_t n = a1 - a0;
     const int32_t cs = (SL & kSlotsWrite) ? kd.cslot[j] : -1;
 
-    auto cf_utility = [&](int32_t a) -> C {
-        C acc = usign * (C)g[a];
-        const int cnt = (SL & kSlotsRead) ? (int)kd.ccount[a] : kFastKids + 1;
-        if (cnt <= kFastKids) {
-            for (int i = 0; i < cnt; ++i) acc = acc + kd.cval[4 * (int64_t)a + i];
-            return acc;
+    // Counterfactual values of the actions g0 .. g0 + kGroup - 1 below a1
+    // (q[k]): the payoff plus the child decision points' values, added in
+    // order, from the action's value slots when it has at most kFastKids
+    // children, else from its child list.  The group's per-action loads
+    // (payoff, slot count, child range) are issued together before the
+    // child sums, instead of one action after another.
+    constexpr int kGroup = 4;
+    auto group_q = [&](int32_t g0, C *q) {
+        int32_t cnt[kGroup], c0[kGroup], c1[kGroup];
+#pragma unroll
+        for (int k = 0; k < kGroup; ++k) {
+            const int32_t a = g0 + k < a1 ? g0 + k : a1 - 1;
+            q[k] = usign * (C)g[a];
+            cnt[k] = (SL & kSlotsRead) ? (int)kd.ccount[a] : kFastKids + 1;
+            c0[k] = child_ptr[a];
+            c1[k] = child_ptr[a + 1];
         }
-        return child_sum<P>(acc, child_ptr[a], child_ptr[a + 1], child_idx, vinf);
+#pragma unroll
+        for (int k = 0; k < kGroup; ++k) {
+            const int32_t a = g0 + k;
+            if (a >= a1) continue;
+            if (cnt[k] <= kFastKids) {
+                for (int i = 0; i < cnt[k]; ++i) q[k] = q[k] + kd.cval[4 * (int64_t)a + i];
+            } else {
+                q[k] = child_sum<P>(q[k], c0[k], c1[k], child_idx, vinf);
+            }
+        }
     };
 
     if (n <= kMaxActs) {
+        static_assert(kMaxActs == 2 * kGroup, "two groups");
         C q[kMaxActs];
+        group_q(a0, q);
+        if (n > kGroup) group_q(a0 + kGroup, q + kGroup);
         C V_ = 0;
 #pragma unroll
-        for (int k = 0; k < kMaxActs; ++k) {
-            if (k < n) {
-                q[k] = cf_utility(a0 + k);
-                V_ = V_ + (C)b[a0 + k] * q[k];
-            }
-        }
+        for (int k = 0; k < kMaxActs; ++k)
+            if (k < n) V_ = V_ + (C)b[a0 + k] * q[k];
         store_value(kd, cs, j, vinf, V_);
         C z[kMaxActs];
         C Z = 0;
@@ -655,33 +673,9 @@ __device__ __forceinline__ void up_infoset(
         return;
     }
 
-    // large decision points: recompute instead of holding every action.
-    // The actions go in groups of four: a group's per-action loads
-    // (payoff, slot count or child range, strategy, regret) are issued
-    // together before its child sums, instead of one action after another;
-    // the arithmetic is the same, in the same order.
-    constexpr int kGroup = 4;
-    auto group_q = [&](int32_t g0, C (&q)[kGroup]) {
-        int32_t cnt[kGroup], c0[kGroup], c1[kGroup];
-#pragma unroll
-        for (int k = 0; k < kGroup; ++k) {
-            const int32_t a = g0 + k < a1 ? g0 + k : a1 - 1;
-            q[k] = usign * (C)g[a];
-            cnt[k] = (SL & kSlotsRead) ? (int)kd.ccount[a] : kFastKids + 1;
-            c0[k] = child_ptr[a];
-            c1[k] = child_ptr[a + 1];
-        }
-#pragma unroll
-        for (int k = 0; k < kGroup; ++k) {
-            const int32_t a = g0 + k;
-            if (a >= a1) continue;
-            if (cnt[k] <= kFastKids) {
-                for (int i = 0; i < cnt[k]; ++i) q[k] = q[k] + kd.cval[4 * (int64_t)a + i];
-            } else {
-                q[k] = child_sum<P>(q[k], c0[k], c1[k], child_idx, vinf);
-            }
-        }
-    };
+    // large decision points: recompute instead of holding every action,
+    // a group of actions at a time (strategies and regrets loaded together
+    // too); the arithmetic is the same, in the same order.
     C V_ = 0;
     for (int32_t g0 = a0; g0 < a1; g0 += kGroup) {
         C q[kGroup], bb[kGroup];
