@@ -5,7 +5,10 @@ the CPU-baseline leg of the benchmark.  The GPU library never imports,
 links or calls it.
 
 ``build()`` compiles ``cfr_oracle.c`` with gcc (no floating-point
-contraction) into ``liboracle.so`` next to this file.
+contraction) into ``liboracle.so`` next to this file, and the same source
+with ``-fopenmp`` into ``liboracle_omp.so``: the all-core build, which runs
+the same per-element arithmetic on every host core and gives bit-identical
+results (``Oracle(game, parallel=True)``).
 """
 from __future__ import annotations
 
@@ -18,6 +21,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "cfr_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+LIB_OMP = os.path.join(HERE, "liboracle_omp.so")
 
 VARIANTS = {"vanilla": 0, "cfr+": 1, "dcfr": 2, "pcfr+": 3, "pcfr": 4}
 MODES = {"simultaneous": 0, "alternating": 1}
@@ -26,24 +30,25 @@ AVG = {"default": 0, "uniform": 1, "linear": 2, "quadratic": 3, "pow_gamma": 4}
 
 
 def build(force: bool = True) -> str:
-    if force or not os.path.exists(LIB):
-        tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC",
-                               "-shared", SRC, "-o", tmp, "-lm"])
-        os.replace(tmp, LIB)
+    for lib, extra in ((LIB, []), (LIB_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(lib):
+            tmp = lib + ".tmp"
+            subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC",
+                                   "-shared", *extra, SRC, "-o", tmp, "-lm"])
+            os.replace(tmp, lib)
     return LIB
 
 
-_lib = None
+_libs = {}
 
 
-def _load():
-    global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(LIB):
-        build()
-    lib = C.CDLL(LIB)
+def _load(parallel: bool = False):
+    if parallel in _libs:
+        return _libs[parallel]
+    path = LIB_OMP if parallel else LIB
+    if not os.path.exists(path):
+        build(force=False)
+    lib = C.CDLL(path)
     i64, i32p, f64p, vp = C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.c_void_p
     lib.orc_create.restype = vp
     lib.orc_create.argtypes = [i64, i64, i32p, i32p, i64, i64, i32p, i32p,
@@ -67,8 +72,15 @@ def _load():
     lib.orc_total_weight.restype = C.c_double
     lib.orc_best_response_to.argtypes = [vp, C.c_int, f64p]
     lib.orc_best_response_to.restype = C.c_double
-    _lib = lib
+    lib.orc_threads.argtypes = []
+    lib.orc_threads.restype = C.c_int
+    _libs[parallel] = lib
     return lib
+
+
+def threads(parallel: bool = True) -> int:
+    """Host threads the oracle's loops run on (1 for the plain build)."""
+    return int(_load(parallel).orc_threads())
 
 
 def _ptr(a, ct):
@@ -76,11 +88,13 @@ def _ptr(a, ct):
 
 
 class Oracle:
-    """Plain FP64 sequence-form CFR on a game's arrays (caller's numbering)."""
+    """Plain FP64 sequence-form CFR on a game's arrays (caller's numbering).
+    parallel: the all-core build (same arithmetic, bit-identical results)."""
 
     def __init__(self, game, alpha: float = 1.5, beta: float = 0.0, gamma: float = 2.0,
-                 avg: str = "default", literal_pcfr: bool = False):
-        lib = _load()
+                 avg: str = "default", literal_pcfr: bool = False, parallel: bool = False):
+        lib = _load(parallel)
+        self.threads = int(lib.orc_threads())
         self._keep = []
 
         def arr(a, dt):

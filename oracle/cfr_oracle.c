@@ -47,11 +47,26 @@
  * at exactly zero; "current strategy" after T iterations is the strategy
  * regret matching gives from the regrets after iteration T.
  *
+ * All-core build.  Compiled with -fopenmp, the same arithmetic runs on every
+ * host core: each row of A y and each column of A^T x (the oracle then
+ * keeps its own transpose of A, built by a counting sort over the rows in
+ * ascending order, so every column is still summed in ascending row order
+ * from 0.0), the per-decision-point and per-sequence loops, and the sweeps
+ * one treeplex level at a time (deepest level first bottom-up, shallowest
+ * first top-down; the decision points of one level depend only on deeper or
+ * shallower levels).  Every stored value is computed by the same sequence of
+ * floating-point operations as in the plain build, so the two builds give
+ * bit-identical results (tested).  Without -fopenmp those blocks are not
+ * compiled and the plain loops below are the whole oracle.
+ *
  * Inputs are borrowed, not copied: the caller keeps the arrays alive for the
  * life of the solver.  Sequence 0 is the empty sequence.  Decision point j
  * owns sequences [first[j], first[j+1]); parent[j] < first[j].
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -77,6 +92,11 @@ typedef struct {
     double *v;      /* last value per decision point                      */
     double *vmax;   /* best-response value per decision point             */
     double *u_last; /* last observed utility (literal Algorithm 5 mode)   */
+#ifdef _OPENMP
+    int64_t n_levels;    /* decision levels (number of own earlier decisions) */
+    int64_t *lvl_ptr;    /* [n_levels+1] decision points of level l:          */
+    int32_t *lvl_inf;    /*   lvl_inf[lvl_ptr[l] .. lvl_ptr[l+1]), ascending  */
+#endif
 } orc_tfsdp;
 
 typedef struct {
@@ -88,6 +108,11 @@ typedef struct {
     double *g1;     /* A y       (length n_seq of player 1) */
     double *g2;     /* A^T x     (length n_seq of player 2) */
     double *xb1, *xb2;
+#ifdef _OPENMP
+    int64_t *col_ptr;  /* [n_seq2+1] transpose of A: column k's nonzeros   */
+    int32_t *row_idx;  /* [nnz]      in ascending row order                */
+    double *val_t;     /* [nnz]                                            */
+#endif
     double alpha, beta, gamma;
     int avg_kind, variant, mode, literal_pcfr, started;
     int64_t t;
@@ -120,6 +145,32 @@ static int tfsdp_init(orc_tfsdp *p, int64_t n_seq, int64_t n_inf,
     memcpy(fill, p->child_ptr, ((size_t)n_seq + 1) * sizeof(int64_t));
     for (int64_t j = 0; j < n_inf; ++j) p->child[fill[parent[j]]++] = (int32_t)j;
     free(fill);
+#ifdef _OPENMP
+    /* level of each decision point: 0 under the empty sequence, else one
+     * more than the level of the decision point owning its parent sequence
+     * (which comes earlier, since parent[j] < first[j]) */
+    int32_t *lvl = (int32_t *)calloc((size_t)(n_inf > 0 ? n_inf : 1), sizeof(int32_t));
+    int32_t *owner = (int32_t *)calloc((size_t)n_seq, sizeof(int32_t));
+    if (!lvl || !owner) return -1;
+    p->n_levels = 0;
+    for (int64_t j = 0; j < n_inf; ++j) {
+        for (int64_t a = first[j]; a < first[j + 1]; ++a) owner[a] = (int32_t)j;
+        lvl[j] = parent[j] == 0 ? 0 : lvl[owner[parent[j]]] + 1;
+        if (lvl[j] + 1 > p->n_levels) p->n_levels = lvl[j] + 1;
+    }
+    p->lvl_ptr = (int64_t *)calloc((size_t)p->n_levels + 1, sizeof(int64_t));
+    p->lvl_inf = (int32_t *)calloc((size_t)(n_inf > 0 ? n_inf : 1), sizeof(int32_t));
+    if (!p->lvl_ptr || !p->lvl_inf) return -1;
+    for (int64_t j = 0; j < n_inf; ++j) p->lvl_ptr[lvl[j] + 1] += 1;
+    for (int64_t l = 0; l < p->n_levels; ++l) p->lvl_ptr[l + 1] += p->lvl_ptr[l];
+    int64_t *at = (int64_t *)malloc(((size_t)p->n_levels + 1) * sizeof(int64_t));
+    if (!at) return -1;
+    memcpy(at, p->lvl_ptr, ((size_t)p->n_levels + 1) * sizeof(int64_t));
+    for (int64_t j = 0; j < n_inf; ++j) p->lvl_inf[at[lvl[j]]++] = (int32_t)j;
+    free(at);
+    free(lvl);
+    free(owner);
+#endif
     return 0;
 }
 
@@ -127,12 +178,16 @@ static void tfsdp_free(orc_tfsdp *p)
 {
     free(p->child_ptr); free(p->child); free(p->r); free(p->m); free(p->b);
     free(p->x); free(p->s); free(p->q); free(p->v); free(p->vmax); free(p->u_last);
+#ifdef _OPENMP
+    free(p->lvl_ptr); free(p->lvl_inf);
+#endif
 }
 
 /* Regret matching at every decision point (Algorithm 1, behavioural step):
  * b_j = (r_j + m_j)^+ / ||(r_j + m_j)^+||_1, uniform when the norm is 0.  */
 static void regret_matching(orc_tfsdp *p)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < p->n_inf; ++j) {
         int64_t a0 = p->first[j], a1 = p->first[j + 1];
         double Z = 0.0;
@@ -156,15 +211,27 @@ static void regret_matching(orc_tfsdp *p)
 static void sequence_form(orc_tfsdp *p)
 {
     p->x[0] = 1.0;
+#ifdef _OPENMP
+    for (int64_t l = 0; l < p->n_levels; ++l) {
+#pragma omp parallel for schedule(static)
+        for (int64_t i = p->lvl_ptr[l]; i < p->lvl_ptr[l + 1]; ++i) {
+            int64_t j = p->lvl_inf[i];
+            double xp = p->x[p->parent[j]];
+            for (int64_t a = p->first[j]; a < p->first[j + 1]; ++a) p->x[a] = xp * p->b[a];
+        }
+    }
+#else
     for (int64_t j = 0; j < p->n_inf; ++j) {
         double xp = p->x[p->parent[j]];
         for (int64_t a = p->first[j]; a < p->first[j + 1]; ++a) p->x[a] = xp * p->b[a];
     }
+#endif
 }
 
 /* g1 = A y, each row summed left to right. */
 static void payoff_rows(const orc_solver *o, const double *y, double *g1)
 {
+#pragma omp parallel for schedule(dynamic, 4096)
     for (int64_t i = 0; i < o->pl[0].n_seq; ++i) {
         double acc = 0.0;
         for (int64_t e = o->row_ptr[i]; e < o->row_ptr[i + 1]; ++e)
@@ -176,6 +243,17 @@ static void payoff_rows(const orc_solver *o, const double *y, double *g1)
 /* g2 = A^T x, scattered over rows in ascending order. */
 static void payoff_cols(const orc_solver *o, const double *x, double *g2)
 {
+#ifdef _OPENMP
+    /* the same additions per column, from the transpose */
+#pragma omp parallel for schedule(dynamic, 4096)
+    for (int64_t k = 0; k < o->pl[1].n_seq; ++k) {
+        double acc = 0.0;
+        for (int64_t e = o->col_ptr[k]; e < o->col_ptr[k + 1]; ++e)
+            acc = acc + o->val_t[e] * x[o->row_idx[e]];
+        g2[k] = acc;
+    }
+    return;
+#endif
     for (int64_t k = 0; k < o->pl[1].n_seq; ++k) g2[k] = 0.0;
     for (int64_t i = 0; i < o->pl[0].n_seq; ++i) {
         double xi = x[i];
@@ -199,43 +277,57 @@ static double cf_utility(const orc_tfsdp *p, const double *u, double sign,
 /* ObserveUtility (Algorithm 1) plus the variant's post-step.  With
  * keep_prediction the predictive variants store the instantaneous regret as
  * the next prediction; the literal Algorithm 5 mode re-derives it instead. */
+static void observe_one(orc_tfsdp *p, int64_t j, const double *u, double sign, int variant,
+                        double dpos, double dneg, int keep_prediction)
+{
+    int64_t a0 = p->first[j], a1 = p->first[j + 1];
+    for (int64_t a = a0; a < a1; ++a) p->q[a] = cf_utility(p, u, sign, a, p->v);
+    double V = 0.0;
+    for (int64_t a = a0; a < a1; ++a) V = V + p->b[a] * p->q[a];
+    p->v[j] = V;
+    for (int64_t a = a0; a < a1; ++a) {
+        double inst = p->q[a] - V;
+        double r = p->r[a] + inst;
+        switch (variant) {
+        case ORC_PLUS:
+            r = r > 0.0 ? r : 0.0;
+            break;
+        case ORC_DCFR:
+            if (r > 0.0) r = r * dpos;
+            else if (r < 0.0) r = r * dneg;
+            break;
+        case ORC_PCFR_PLUS:
+            r = r > 0.0 ? r : 0.0;
+            if (keep_prediction) p->m[a] = inst;
+            break;
+        case ORC_PCFR:
+            if (keep_prediction) p->m[a] = inst;
+            break;
+        default:
+            break;
+        }
+        p->r[a] = r;
+    }
+}
+
 static void observe(orc_tfsdp *p, const double *u, double sign, int variant,
                     double dpos, double dneg, int keep_prediction)
 {
-    for (int64_t j = p->n_inf - 1; j >= 0; --j) {
-        int64_t a0 = p->first[j], a1 = p->first[j + 1];
-        for (int64_t a = a0; a < a1; ++a) p->q[a] = cf_utility(p, u, sign, a, p->v);
-        double V = 0.0;
-        for (int64_t a = a0; a < a1; ++a) V = V + p->b[a] * p->q[a];
-        p->v[j] = V;
-        for (int64_t a = a0; a < a1; ++a) {
-            double inst = p->q[a] - V;
-            double r = p->r[a] + inst;
-            switch (variant) {
-            case ORC_PLUS:
-                r = r > 0.0 ? r : 0.0;
-                break;
-            case ORC_DCFR:
-                if (r > 0.0) r = r * dpos;
-                else if (r < 0.0) r = r * dneg;
-                break;
-            case ORC_PCFR_PLUS:
-                r = r > 0.0 ? r : 0.0;
-                if (keep_prediction) p->m[a] = inst;
-                break;
-            case ORC_PCFR:
-                if (keep_prediction) p->m[a] = inst;
-                break;
-            default:
-                break;
-            }
-            p->r[a] = r;
-        }
+#ifdef _OPENMP
+    for (int64_t l = p->n_levels - 1; l >= 0; --l) {
+#pragma omp parallel for schedule(static)
+        for (int64_t i = p->lvl_ptr[l]; i < p->lvl_ptr[l + 1]; ++i)
+            observe_one(p, p->lvl_inf[i], u, sign, variant, dpos, dneg, keep_prediction);
     }
+#else
+    for (int64_t j = p->n_inf - 1; j >= 0; --j)
+        observe_one(p, j, u, sign, variant, dpos, dneg, keep_prediction);
+#endif
 }
 
 static void accumulate_average(orc_tfsdp *p, double w)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t s = 0; s < p->n_seq; ++s) p->s[s] = p->s[s] + w * p->x[s];
 }
 
@@ -284,6 +376,18 @@ static double avg_weight(const orc_solver *o, double t)
     }
 }
 
+void orc_destroy(void *h);
+
+/* Threads the loops above run on (1 in the plain build). */
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 void *orc_create(int64_t n_seq1, int64_t n_inf1, const int32_t *par1, const int32_t *first1,
                  int64_t n_seq2, int64_t n_inf2, const int32_t *par2, const int32_t *first2,
                  int64_t nnz, const int64_t *row_ptr, const int32_t *col, const double *val,
@@ -304,6 +408,27 @@ void *orc_create(int64_t n_seq1, int64_t n_inf1, const int32_t *par1, const int3
     o->g2 = (double *)calloc((size_t)n_seq2, sizeof(double));
     o->xb1 = (double *)calloc((size_t)n_seq1, sizeof(double));
     o->xb2 = (double *)calloc((size_t)n_seq2, sizeof(double));
+#ifdef _OPENMP
+    o->col_ptr = (int64_t *)calloc((size_t)n_seq2 + 1, sizeof(int64_t));
+    o->row_idx = (int32_t *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t));
+    o->val_t = (double *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(double));
+    int64_t *at = (int64_t *)malloc(((size_t)n_seq2 + 1) * sizeof(int64_t));
+    if (!o->col_ptr || !o->row_idx || !o->val_t || !at) {
+        free(at);
+        orc_destroy(o);
+        return NULL;
+    }
+    for (int64_t e = 0; e < nnz; ++e) o->col_ptr[col[e] + 1] += 1;
+    for (int64_t k = 0; k < n_seq2; ++k) o->col_ptr[k + 1] += o->col_ptr[k];
+    memcpy(at, o->col_ptr, ((size_t)n_seq2 + 1) * sizeof(int64_t));
+    for (int64_t i = 0; i < n_seq1; ++i)
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            int64_t d = at[col[e]]++;
+            o->row_idx[d] = (int32_t)i;
+            o->val_t[d] = val[e];
+        }
+    free(at);
+#endif
     o->alpha = alpha;
     o->beta = beta;
     o->gamma = gamma;
@@ -324,6 +449,9 @@ void orc_destroy(void *h)
     tfsdp_free(&o->pl[0]);
     tfsdp_free(&o->pl[1]);
     free(o->g1); free(o->g2); free(o->xb1); free(o->xb2);
+#ifdef _OPENMP
+    free(o->col_ptr); free(o->row_idx); free(o->val_t);
+#endif
     free(o);
 }
 
@@ -378,6 +506,7 @@ static void profile(orc_solver *o, int player, int kind, double *out)
 {
     orc_tfsdp *p = &o->pl[player];
     if (kind == ORC_AVERAGE && o->W > 0.0) {
+#pragma omp parallel for schedule(static)
         for (int64_t s = 0; s < p->n_seq; ++s) out[s] = p->s[s] / o->W;
     } else {
         memcpy(out, p->x, (size_t)p->n_seq * sizeof(double));
@@ -431,16 +560,27 @@ int orc_last_observation(void *h, int player, double *q, double *v)
 /* Best-response value of a player facing the utility sign*u: bottom-up
  * max over actions of (own utility + values below), then the value at the
  * empty sequence. */
+static void best_response_one(orc_tfsdp *p, int64_t j, const double *u, double sign)
+{
+    double best = 0.0;
+    for (int64_t a = p->first[j]; a < p->first[j + 1]; ++a) {
+        double val = cf_utility(p, u, sign, a, p->vmax);
+        if (a == p->first[j] || val > best) best = val;
+    }
+    p->vmax[j] = best;
+}
+
 static double best_response(orc_tfsdp *p, const double *u, double sign)
 {
-    for (int64_t j = p->n_inf - 1; j >= 0; --j) {
-        double best = 0.0;
-        for (int64_t a = p->first[j]; a < p->first[j + 1]; ++a) {
-            double val = cf_utility(p, u, sign, a, p->vmax);
-            if (a == p->first[j] || val > best) best = val;
-        }
-        p->vmax[j] = best;
+#ifdef _OPENMP
+    for (int64_t l = p->n_levels - 1; l >= 0; --l) {
+#pragma omp parallel for schedule(static)
+        for (int64_t i = p->lvl_ptr[l]; i < p->lvl_ptr[l + 1]; ++i)
+            best_response_one(p, p->lvl_inf[i], u, sign);
     }
+#else
+    for (int64_t j = p->n_inf - 1; j >= 0; --j) best_response_one(p, j, u, sign);
+#endif
     return cf_utility(p, u, sign, 0, p->vmax);
 }
 

@@ -358,3 +358,35 @@ def test_exploitability_falls(oracle_mod, games):
     # the modern variants beat vanilla at equal iterations on this game
     for variant, e in finals.items():
         assert e < vals[2], (variant, e, vals[2])
+
+
+# --------------------------------------------------------------------------
+# The all-core build runs the same per-element arithmetic on every host core
+# (rows and columns of the payoff products, the sweeps one level at a time):
+# its results equal the plain build's bit for bit, so every pin above holds
+# for it too.
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("mode", MODES)
+def test_all_core_build_is_bit_identical(oracle_mod, games, variant, mode):
+    cases = [games["stops"], games["perfect"], gg.make_config("cfg2_d8"),
+             gg.public_game(5, S=4, max_depth=5, branch_lo=2, branch_hi=4, p_stop=0.2)]
+    for g in cases:
+        for literal in ((False, True) if variant in ("pcfr+", "pcfr") else (False,)):
+            a = oracle_mod.Oracle(g, literal_pcfr=literal)
+            b = oracle_mod.Oracle(g, literal_pcfr=literal, parallel=True)
+            for n in (1, 29):
+                a.step(n, variant, mode)
+                b.step(n, variant, mode)
+                for p in range(2):
+                    for kind in ("current", "average"):
+                        assert np.array_equal(a.strategy(p, kind), b.strategy(p, kind))
+                    assert np.array_equal(a.regrets(p), b.regrets(p))
+                    assert np.array_equal(a.prediction(p), b.prediction(p))
+                for kind in ("current", "average"):
+                    ea, eb = a.exploitability(kind), b.exploitability(kind)
+                    assert all(ea[k] == eb[k] for k in ea), (ea, eb)
+            y = np.random.default_rng(3).random(g.n_seq[1])
+            assert a.best_response_to(0, y) == b.best_response_to(0, y)
+    assert oracle_mod.threads(parallel=True) >= 1
