@@ -364,6 +364,21 @@ int cfr_batch_game_size(const cfr_game_desc *game, int64_t *out);
 /* Device bytes of a batch with these capacities.                         */
 int cfr_batch_workspace_size(const cfr_batch_options *opt, size_t *bytes);
 
+/* Index limits of a batch with these capacities (host only; no device).
+ * Value slots (a decision point's value stored beside its parent sequence,
+ * one dependent load fewer per sweep level) hold 4 * sequence + rank in an
+ * int32, so they are used only while a player's sequence capacity is at
+ * most 2^29; above it every level keeps its values in the plain per
+ * decision point array (same results).  A quad word (stream form 3) keeps a
+ * column's aligned group of four in 28 bits, so that form is refused
+ * (CFR_EINVAL from the tiling calls; skipped by the autotuner) while the
+ * column player's sequence capacity exceeds 2^30.  The same limits apply
+ * to a single solver, whose capacity is its game's sequence count plus
+ * one, rounded up to a multiple of four.
+ *   out[0], out[1]  1 if value slots are used for player 1 / player 2
+ *   out[2], out[3]  1 if stream form 3 is allowed for A y / for A^T x     */
+int cfr_batch_index_limits(const cfr_batch_options *opt, int *out);
+
 /* Allocates the batch's workspace (library-owned) on opt->device.        */
 int cfr_batch_create(const cfr_batch_options *opt, cfr_batch **out);
 

@@ -17,7 +17,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libcfr.so")
+# CFR_LIBRARY names another build of the same library (the address-sanitised
+# host build the CPU tests load); by default the in-tree libcfr.so.
+LIB_PATH = os.environ.get("CFR_LIBRARY") or os.path.join(_HERE, "libcfr.so")
 
 CFR_OK, CFR_EINVAL, CFR_ENOMEM, CFR_EDEVICE, CFR_ESTATE, CFR_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_acc64": 2}
@@ -113,6 +115,7 @@ _lib.cfr_batch_options_default.argtypes = [_P(cfr_batch_options)]
 _lib.cfr_game_params_default.argtypes = [_P(cfr_game_params)]
 _lib.cfr_batch_game_size.argtypes = [_P(cfr_game_desc), _P(C.c_int64)]
 _lib.cfr_batch_workspace_size.argtypes = [_P(cfr_batch_options), _P(C.c_size_t)]
+_lib.cfr_batch_index_limits.argtypes = [_P(cfr_batch_options), _P(C.c_int)]
 _lib.cfr_batch_create.argtypes = [_P(cfr_batch_options), _P(C.c_void_p)]
 _lib.cfr_batch_add.argtypes = [C.c_void_p, _P(cfr_game_desc), _P(cfr_game_params), _P(C.c_int64)]
 _lib.cfr_batch_run.argtypes = [C.c_void_p, C.c_int64, _P(C.c_int64)]
@@ -146,7 +149,7 @@ for _f in ("cfr_options_default", "cfr_validate", "cfr_workspace_size", "cfr_cre
            "cfr_batch_set_tiling", "cfr_batch_tune", "cfr_batch_kernel_timing",
            "cfr_batch_kernel_stats", "cfr_batch_destroy", "cfr_prepare", "cfr_prepared_size",
            "cfr_batch_add_prepared", "cfr_prepared_destroy", "cfr_batch_host_stats",
-           "cfr_prepare_quads"):
+           "cfr_prepare_quads", "cfr_batch_index_limits"):
     getattr(_lib, _f).restype = C.c_int
 
 
@@ -345,6 +348,12 @@ def cfr_batch_workspace_size(opts: cfr_batch_options) -> int:
     n = C.c_size_t(0)
     _check(_lib.cfr_batch_workspace_size(C.byref(opts), C.byref(n)), "cfr_batch_workspace_size")
     return int(n.value)
+
+
+def cfr_batch_index_limits(opts: cfr_batch_options) -> dict:
+    out = (C.c_int * 4)()
+    _check(_lib.cfr_batch_index_limits(C.byref(opts), out), "cfr_batch_index_limits")
+    return {"slots": [bool(out[0]), bool(out[1])], "quads": [bool(out[2]), bool(out[3])]}
 
 
 def cfr_batch_create(opts: cfr_batch_options) -> C.c_void_p:

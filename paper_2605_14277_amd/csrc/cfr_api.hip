@@ -209,6 +209,16 @@ int check_device(int device)
     return CFR_OK;
 }
 
+// Stream form 3 only where the column player's index space fits a quad word.
+int check_tiling_fits(const cfr::Engine &e, const cfr_spmv_tiling *t)
+{
+    for (int w = 0; w < 2; ++w)
+        if (t->vec[w] == 3 && !cfr::quads_fit(e.cap.seq[1 - w]))
+            return fail(CFR_EINVAL, "stream form 3 needs every column index below 2^30 (the "
+                                    "column player's sequence capacity is larger)");
+    return CFR_OK;
+}
+
 // Tiling choice shared by the solver and the batch.
 void get_tiling(const cfr::Engine &e, cfr_spmv_tiling *t)
 {
@@ -259,7 +269,9 @@ int tune(cfr::Engine &e, int reps, cfr_spmv_tiling *chosen)
             for (int vec = 0; vec < 4; ++vec)
                 for (int items : kItems)
                     for (int rows : kRows) {
-                        if (vec == 3 && items < cfr::kQuadItemsMin) continue;
+                        if (vec == 3 && (items < cfr::kQuadItemsMin ||
+                                         !cfr::quads_fit(e.cap.seq[1 - w])))
+                            continue;
                         e.repartition(w, items, rows, vec);
                         double ms = 0;
                         rc = e.time_spmv(w, reps, &ms);
@@ -703,6 +715,8 @@ int cfr_set_tiling(cfr_solver *s, const cfr_spmv_tiling *t)
     int rc = check_tiling(t);
     if (rc) return rc;
     try {
+        rc = check_tiling_fits(s->eng, t);
+        if (rc) return rc;
         DeviceGuard guard(s->eng.device);
         rc = s->eng.sync("tiling");
         if (rc) return rc;
@@ -822,6 +836,19 @@ int cfr_batch_workspace_size(const cfr_batch_options *opt, size_t *bytes)
     return CFR_OK;
 }
 
+int cfr_batch_index_limits(const cfr_batch_options *opt, int *out)
+{
+    if (!out) return fail(CFR_EINVAL, "null output");
+    cfr::Capacity c;
+    int rc = batch_capacity(opt, c);
+    if (rc) return rc;
+    out[0] = cfr::slots_fit(c.seq[0]) ? 1 : 0;
+    out[1] = cfr::slots_fit(c.seq[1]) ? 1 : 0;
+    out[2] = cfr::quads_fit(c.seq[1]) ? 1 : 0;
+    out[3] = cfr::quads_fit(c.seq[0]) ? 1 : 0;
+    return CFR_OK;
+}
+
 int cfr_batch_create(const cfr_batch_options *opt, cfr_batch **out)
 {
     if (!out) return fail(CFR_EINVAL, "null output");
@@ -930,6 +957,9 @@ int cfr_prepare_quads(cfr_prepared *p, const int *perm)
     if (!p || !perm) return fail(CFR_EINVAL, "null argument");
     for (int w = 0; w < 2; ++w)
         if (perm[w] != 0 && perm[w] != 1) return fail(CFR_EINVAL, "perm must be 0 or 1");
+    for (int w = 0; w < 2; ++w)
+        if (!cfr::quads_fit(cfr::seq_block(p->hg.pl[1 - w].n_seq)))
+            return fail(CFR_EINVAL, "stream form 3 needs every column index below 2^30");
     try {
         cfr::build_image_quads(p->hg, perm, true, p->img);
     } catch (const std::exception &ex) {
@@ -1086,6 +1116,8 @@ int cfr_batch_set_tiling(cfr_batch *b, const cfr_spmv_tiling *t)
     int rc = check_tiling(t);
     if (rc) return rc;
     try {
+        rc = check_tiling_fits(b->eng, t);
+        if (rc) return rc;
         DeviceGuard guard(b->eng.device);
         rc = b->eng.sync("tiling");
         if (rc) return rc;

@@ -1209,9 +1209,11 @@ int Engine::add(const HostGame &hg, const GameImage &img, const GameParams &gp, 
         // big levels write their values contiguously, since slot writes
         // scatter.  Levels that the one-launch shallow sweep covers, and
         // the one right below them, keep to the plain layout it reads.
+        // Slots need the player's whole index space below kSlotSeqLimit.
         s.lvl_slots[p].assign((size_t)pl.n_levels, 0);
         const int32_t top_low = lone ? pl.top_levels : 0;
-        for (int32_t L = 1; L < pl.n_levels; ++L)
+        const bool slots_ok = slots_fit(cap.seq[p]);
+        for (int32_t L = 1; L < pl.n_levels && slots_ok; ++L)
             if (pl.lvl_inf[L + 1] - pl.lvl_inf[L] <= kSlotLevelMax && L > top_low) {
                 s.lvl_slots[p][L] |= kSlotsWrite;
                 s.lvl_slots[p][L - 1] |= kSlotsRead;
@@ -1229,7 +1231,9 @@ int Engine::add(const HostGame &hg, const GameImage &img, const GameParams &gp, 
         CHECK(cp(d.child_idx + I, B + q.child_idx, 4 * ni));
         CHECK(launch_add_offset(d.child_idx + I, (int64_t)ni, I, ups));
         CHECK(cp(d.cslot + I, B + q.cslot, 4 * ni));
-        CHECK(launch_add_offset_nonneg(d.cslot + I, (int64_t)ni, 4 * S, ups));
+        // (read only on slot levels, which exist only when 4 * S fits)
+        if (slots_fit(cap.seq[p]))
+            CHECK(launch_add_offset_nonneg(d.cslot + I, (int64_t)ni, 4 * S, ups));
         CHECK(cp(d.ccount + S, B + q.ccount, n + 1));
         CHECK(cp((char *)d.b + V * (size_t)S, B + q.b0, V * (n + 1)));
         CHECK(cp((char *)d.x + V * (size_t)S, B + q.x0, V * (n + 1)));

@@ -203,6 +203,15 @@ constexpr uint32_t kQuadIndexMask = (1u << kQuadMaskShift) - 1;
 constexpr int kQuadItemsMin = 8;
 constexpr int kMinBlockCap = kSpmvThreads * kQuadItemsMin / 4;
 constexpr int kVecPad = 4;      // readable entries past the end of every gathered vector
+// Index limits of the device layout.  A value slot is 4 * sequence + rank in
+// an int32, so value slots are used only while a player's whole sequence
+// index space (every game of the engine) stays at or below 2^29; a quad word
+// keeps a column's aligned group of four in kQuadMaskShift bits, so stream
+// form 3 needs the column player's index space at or below 2^30.
+constexpr int64_t kSlotSeqLimit = (int64_t)1 << 29;
+constexpr int64_t kQuadColLimit = (int64_t)1 << (kQuadMaskShift + 2);
+inline bool slots_fit(int64_t seq_space) { return seq_space <= kSlotSeqLimit; }
+inline bool quads_fit(int64_t col_space) { return col_space <= kQuadColLimit; }
 constexpr int64_t kQuadStoreMin = (int64_t)1 << 26;  // first quad store of a batch (quads)
 // A game's block of sequence indices (n_seq + 1 with the sentinel) is
 // rounded up to a multiple of four, so every game starts at a multiple of

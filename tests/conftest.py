@@ -41,3 +41,11 @@ def tiny_games():
 @pytest.fixture(scope="session")
 def games():
     return tiny_games()
+
+
+def pytest_terminal_summary(terminalreporter):
+    from helpers import SESSION_REPORT
+    if SESSION_REPORT:
+        terminalreporter.write_sep("-", "errors against the FP64 oracle (FP32 modes)")
+        for line in SESSION_REPORT:
+            terminalreporter.write_line(line)

@@ -56,3 +56,14 @@ def rel_inf(a, ref):
     if ref.size == 0:
         return 0.0
     return float(np.max(np.abs(a - ref)) / max(1.0, float(np.max(np.abs(ref)))))
+
+
+# Lines printed at the end of a test session (pytest_terminal_summary in
+# conftest.py): the FP32 modes' errors against the FP64 oracle, so that
+# every reported FP32 result carries its error even under `pytest -q`.
+SESSION_REPORT = []
+
+
+def report(line: str):
+    print(line, flush=True)
+    SESSION_REPORT.append(line)

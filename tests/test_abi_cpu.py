@@ -212,6 +212,27 @@ def test_batch_workspace_linear_in_capacity(cfr):
     assert 16 <= per_nnz < 17
 
 
+def test_index_limits_at_the_boundaries(cfr):
+    """Value slots hold 4 * sequence + rank in an int32: used up to a
+    sequence capacity of 2^29, off above it.  Quad words keep the column's
+    group of four in 28 bits: stream form 3 allowed up to a column capacity
+    of 2^30, refused above it (per product: A y's columns are player 2's
+    sequences, A^T x's player 1's)."""
+    def lim(s1, s2):
+        return cfr.cfr_batch_index_limits(_batch_opts(cfr, [s1, s2], [10, 10], 1000))
+    assert lim(2**29 - 1, 2**29) == {"slots": [True, True], "quads": [True, True]}
+    assert lim(2**29 + 1, 2**29)["slots"] == [False, True]
+    assert lim(2**29, 2**29 + 4)["slots"] == [True, False]
+    assert lim(2**30, 2**30)["quads"] == [True, True]
+    assert lim(2**30, 2**30 + 1)["quads"] == [False, True]
+    assert lim(2**30 + 4, 2**30)["quads"] == [True, False]
+    assert lim(2**31 - 1, 2**31 - 1) == {"slots": [False, False], "quads": [False, False]}
+    # a capacity the index type cannot hold at all is refused
+    with pytest.raises(cfr.CfrError) as ei:
+        lim(2**31, 10)
+    assert ei.value.code == cfr.CFR_EINVAL
+
+
 @pytest.mark.parametrize("field,value", [("quad_capacity", -1), ("precision", 9), ("mode", 3),
                                          ("max_games", 0),
                                          ("check_every", 0), ("nnz_capacity", -1),
