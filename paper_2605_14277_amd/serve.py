@@ -9,7 +9,10 @@ requests in arrival order while they fit the batch's free slots and device
 ranges (``cfr_batch_add_prepared`` returns CFR_ENOMEM otherwise), runs one
 check period of every game in the batch (``cfr_batch_run``), and frees the
 games that met their stopping rule.  Admission at check boundaries keeps
-every game's iterates and checks identical to the game solved alone.
+every game's iterates and checks identical to the game solved alone.  A
+request that cannot be served (a malformed game, or one larger than the
+whole batch) is answered as rejected, with the library's error code, and
+the loop serves the others on.
 
 The device capacity is sized from a byte budget (``capacities_for_bytes``)
 with the index-unit proportions of the expected request mix.
@@ -137,6 +140,10 @@ class Server:
         self.precision = precision
         self.check_every = check_every
         self.workers = workers
+        # index units of the whole batch: a request larger than this in any
+        # unit can never be admitted and is rejected when it reaches the head
+        self.capacity = np.array([seq_capacity[0], seq_capacity[1], inf_capacity[0],
+                                  inf_capacity[1], nnz_capacity], dtype=np.int64)
 
     def serve(self, requests, keep_strategies: bool = False, prepared=None) -> list:
         """Serves `requests` in real time: a list of dicts with "arrival"
@@ -144,7 +151,12 @@ class Server:
         `prepared`, a list of Prepared games: "prepared"), "variant",
         "target" and "max_iterations".  Returns one record per request:
         arrival, admitted, finished, latency, iterations, expl,
-        reached_target (and the average strategies with keep_strategies)."""
+        reached_target, state (and the average strategies with
+        keep_strategies).  state is "done" for a solved request; a request
+        that cannot be served is answered with state "rejected" (its game is
+        malformed: the library's error code and message in "code" and
+        "error"; or it is larger than the whole batch: CFR_ENOMEM) and the
+        loop goes on serving the others."""
         n = len(requests)
         out = [None] * n
         futures = [None] * n
@@ -171,17 +183,34 @@ class Server:
                 while waiting:
                     k = waiting[0]
                     f = futures[k]
-                    prep = f if isinstance(f, Prepared) else (f.result() if f.done() else None)
-                    if prep is None:
+                    if not isinstance(f, Prepared) and not f.done():
                         break
                     r = requests[k]
+
+                    def reject(code, msg):
+                        waiting.popleft()
+                        now = clock() - t0
+                        out[k] = {"arrival": r["arrival"], "admitted": None, "finished": now,
+                                  "latency": now - r["arrival"], "iterations": 0, "expl": None,
+                                  "reached_target": 0, "state": "rejected", "code": code,
+                                  "error": msg}
+
+                    try:
+                        prep = f if isinstance(f, Prepared) else f.result()
+                    except CfrError as e:  # the game failed validation
+                        reject(e.code, str(e))
+                        continue
+                    if np.any(np.asarray(prep.units) > self.capacity):
+                        reject(CFR_ENOMEM, "the game is larger than the whole batch")
+                        continue
                     try:
                         gid = add_prepared(self.batch, prep, r["variant"], r["target"],
                                            r["max_iterations"])
                     except CfrError as e:
                         if e.code == CFR_ENOMEM and inflight:
-                            break
-                        raise
+                            break  # waits for games in flight to free space
+                        reject(e.code, str(e))
+                        continue
                     waiting.popleft()
                     # the prepared game stays referenced while its copies may run
                     inflight[gid] = (k, clock() - t0, prep)
@@ -196,7 +225,7 @@ class Server:
                         rec = {"arrival": requests[k]["arrival"], "admitted": admitted,
                                "finished": now, "latency": now - requests[k]["arrival"],
                                "iterations": st["iterations"], "expl": st["expl"],
-                               "reached_target": st["reached_target"]}
+                               "reached_target": st["reached_target"], "state": "done"}
                         if keep_strategies:
                             rec["strategy"] = [self.batch.strategy(gid, p, "average")
                                                for p in range(2)]

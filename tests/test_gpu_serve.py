@@ -3,9 +3,10 @@
 Requests arrive while others are iterating; they are prepared on worker
 threads, admitted at check boundaries as slots and device ranges free up,
 and freed when they meet their stopping rule.  Each result must be the same
-as the game solved alone (bit for bit: same iterates, same checks), and the
-requests must really share the device (admitted while others are in
-flight).
+as the game solved alone (bit for bit: same iterates, same checks) and match
+the FP64 oracle run for as many iterations, and the requests must really
+share the device (admitted while others are in flight).  Requests that
+cannot be served are rejected without disturbing the others.
 """
 import sys
 
@@ -79,6 +80,85 @@ def test_served_results_equal_alone(cfr, games, precision, tiling):
             assert np.array_equal(o["strategy"][p], solo.strategy(p, "average")), (k, p)
         assert solo.exploitability("average")["expl"] == o["expl"], k
         solo.close()
+        check_against_oracle(r, o, precision)
+
+
+def check_against_oracle(r, o, precision):
+    """A served result against the FP64 oracle run for the same number of
+    iterations: within 1e-9 (relative) in FP64 on both average strategies
+    and NashConv; within 1e-4 on exploitability in the FP32 modes."""
+    import oracle
+    from helpers import rel_inf
+    orc = oracle.Oracle(r["game"])
+    orc.step(o["iterations"], r["variant"], "alternating")
+    eo = orc.exploitability("average")
+    if precision == "fp64":
+        for p in range(2):
+            d = rel_inf(o["strategy"][p], orc.strategy(p, "average"))
+            assert d <= 1e-9, (p, d)
+        assert abs(2 * o["expl"] - eo["nash_conv"]) <= 1e-9 * max(1.0, abs(eo["nash_conv"]))
+    else:
+        assert abs(o["expl"] - eo["expl"]) <= 1e-4
+    orc.close()
+
+
+def _malformed(game):
+    """The game with one decision point given no action (cfr_prepare and
+    cfr_validate refuse it with CFR_EINVAL)."""
+    import copy
+    g = copy.deepcopy(game)
+    f = g.inf_first_seq[0].copy()
+    f[1] = f[0]
+    g.inf_first_seq[0] = f
+    return g
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_acc64"])
+def test_served_stream_with_cap_malformed_and_oversized_requests(cfr, games, precision):
+    """A stream in which one request stops on its iteration limit while
+    others run (a target it cannot reach), one game is malformed and one is
+    larger than the whole batch: the two are answered as rejected
+    (CFR_EINVAL, CFR_ENOMEM) while the loop keeps serving, and every served
+    result equals the game solved alone bit for bit and the FP64 oracle."""
+    from paper_2605_14277_amd import serve
+    pool = [games["cfg1"], games["stops"], games["s2d3"], games["perfect"]]
+    reqs = _requests(pool, 14, 0.003, seed=11)
+    # never reachable: stops on its 150-iteration limit
+    reqs[3]["target"] = 1e-12
+    big = gg.cfg2_literal()
+    units = sorted((cfr.Batch.game_size(g) for g in pool), key=lambda u: -u[4])
+    cap = np.sum(units[:3], axis=0)
+    assert np.any(cfr.Batch.game_size(big) > cap)
+    bad = dict(reqs[5], game=_malformed(reqs[5]["game"]))
+    over = dict(reqs[8], game=big)
+    reqs[5], reqs[8] = bad, over
+    srv = serve.Server([cap[0], cap[1]], [cap[2], cap[3]], int(cap[4]), max_games=4,
+                       precision=precision, check_every=10, workers=4)
+    out = srv.serve(reqs, keep_strategies=True)
+    srv.close()
+    assert out[5]["state"] == "rejected" and out[5]["code"] == cfr.CFR_EINVAL, out[5]
+    assert out[8]["state"] == "rejected" and out[8]["code"] == cfr.CFR_ENOMEM, out[8]
+    assert out[3]["state"] == "done" and out[3]["iterations"] == 150
+    assert not out[3]["reached_target"]
+    served = [k for k in range(len(reqs)) if k not in (5, 8)]
+    overlaps = sum(1 for i in served for j in served if i < j and
+                   out[i]["admitted"] < out[j]["finished"] and
+                   out[j]["admitted"] < out[i]["finished"])
+    assert overlaps > 0
+    # the capped request shared the device with others while it ran
+    assert any(out[3]["admitted"] < out[j]["finished"] and out[j]["admitted"] < out[3]["finished"]
+               for j in served if j != 3)
+    for k in served:
+        r, o = reqs[k], out[k]
+        assert o["state"] == "done"
+        solo = cfr.Solver(r["game"], precision=precision)
+        solo.step(o["iterations"], r["variant"], "alternating")
+        for p in range(2):
+            assert np.array_equal(o["strategy"][p], solo.strategy(p, "average")), (k, p)
+        assert solo.exploitability("average")["expl"] == o["expl"], k
+        solo.close()
+        check_against_oracle(r, o, precision)
+    say(f"  {precision}: {len(served)} served ({overlaps} overlapping pairs), 2 rejected")
 
 
 def test_prepared_game_reuse_and_precision_check(cfr, games):
