@@ -650,6 +650,14 @@ def batch_game(spec: dict) -> Game:
     return g
 
 
+def batch_games(specs: list, workers: int = 16) -> list:
+    """batch_game for every spec, on a pool of threads (each game draws from
+    its own seed, so the games do not depend on the pool)."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=max(1, workers)) as ex:
+        return list(ex.map(batch_game, specs))
+
+
 def payoff_range(g: Game) -> float:
     """max - min of the terminal payoffs before chance weighting."""
     if g.payoff_kind == "showdown":

@@ -96,6 +96,14 @@ enum { CFR_SPMV_DEFAULT = 0, CFR_SPMV_SEQUENTIAL = 1, CFR_SPMV_PARALLEL = 2 };
  * than 16; otherwise, and with LEVELS, one launch per level.             */
 enum { CFR_DOWN_DEFAULT = 0, CFR_DOWN_LEVELS = 1 };
 
+/* Bottom-up pass of a single solver.  DEFAULT: two adjacent levels run as
+ * one launch wherever the upper level's decision points have at most 4
+ * actions and at most 16 decision points below them and the lower level has
+ * at most 4 actions per decision point, 4 decision points below each action
+ * and at most 2^18 decision points (the same operations in the same order
+ * as two launches, so identical results); LEVELS: one launch per level.  */
+enum { CFR_UP_DEFAULT = 0, CFR_UP_LEVELS = 1 };
+
 /* Averaging weight w_t.  DEFAULT: 1 (vanilla, PCFR), t (CFR+), t^gamma
  * (DCFR; the paper's quadratic weighting with gamma = 2), t^2 (PCFR+).   */
 enum { CFR_AVG_DEFAULT = 0, CFR_AVG_UNIFORM = 1, CFR_AVG_LINEAR = 2,
@@ -150,6 +158,7 @@ typedef struct cfr_options {
     int use_graph;          /* 1: replay a captured HIP graph per iteration  */
     int spmv_order;         /* CFR_SPMV_*                                    */
     int down_pass;          /* CFR_DOWN_*                                    */
+    int up_pass;            /* CFR_UP_*                                      */
 } cfr_options;
 
 typedef struct cfr_solver cfr_solver;

@@ -29,6 +29,7 @@ KINDS = {"current": 0, "average": 1}
 AVG = {"default": 0, "uniform": 1, "linear": 2, "quadratic": 3, "pow_gamma": 4}
 SPMV_ORDER = {"default": 0, "sequential": 1, "parallel": 2}
 DOWN_PASS = {"default": 0, "levels": 1}
+UP_PASS = {"default": 0, "levels": 1}
 GAME_STATES = {0: "active", 1: "waiting", 2: "done"}
 ERRORS = {CFR_EINVAL: "EINVAL", CFR_ENOMEM: "ENOMEM", CFR_EDEVICE: "EDEVICE",
           CFR_ESTATE: "ESTATE", CFR_EUNSUPPORTED: "EUNSUPPORTED"}
@@ -61,7 +62,7 @@ class cfr_options(C.Structure):
     _fields_ = [("precision", C.c_int), ("dcfr_alpha", C.c_double), ("dcfr_beta", C.c_double),
                 ("dcfr_gamma", C.c_double), ("avg_weight", C.c_int), ("stream", C.c_void_p),
                 ("device", C.c_int), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
-                ("use_graph", C.c_int), ("spmv_order", C.c_int), ("down_pass", C.c_int)]
+                ("use_graph", C.c_int), ("spmv_order", C.c_int), ("down_pass", C.c_int), ("up_pass", C.c_int)]
 
 
 class cfr_spmv_tiling(C.Structure):
@@ -474,7 +475,8 @@ class Solver:
     def __init__(self, game, precision: str = "fp64", device: int = 0, alpha: float = 1.5,
                  beta: float = 0.0, gamma: float = 2.0, avg: str = "default",
                  use_graph: bool = True, stream=None, with_csc: bool = True,
-                 spmv_order: str = "default", down_pass: str = "default"):
+                 spmv_order: str = "default", down_pass: str = "default",
+                 up_pass: str = "default"):
         import torch
         self.torch = torch
         self.arrays = GameArrays(game, with_csc=with_csc)
@@ -489,6 +491,7 @@ class Solver:
         o.use_graph = int(bool(use_graph))
         o.spmv_order = SPMV_ORDER[spmv_order]
         o.down_pass = DOWN_PASS[down_pass]
+        o.up_pass = UP_PASS[up_pass]
         dev = torch.device("cuda", int(device))
         if stream is None:
             stream = torch.cuda.current_stream(dev)

@@ -148,6 +148,8 @@ int check_options(const cfr_options *o)
         return fail(CFR_EINVAL, "unknown summation order");
     if (o->down_pass != CFR_DOWN_DEFAULT && o->down_pass != CFR_DOWN_LEVELS)
         return fail(CFR_EINVAL, "unknown top-down pass");
+    if (o->up_pass != CFR_UP_DEFAULT && o->up_pass != CFR_UP_LEVELS)
+        return fail(CFR_EINVAL, "unknown bottom-up pass");
     if (!std::isfinite(o->dcfr_alpha) || !std::isfinite(o->dcfr_beta) ||
         !std::isfinite(o->dcfr_gamma))
         return fail(CFR_EINVAL, "DCFR exponents must be finite");
@@ -433,6 +435,7 @@ int cfr_create(const cfr_game_desc *game, const cfr_options *opt, cfr_solver **o
         e.spmv_order = opt->spmv_order;
         e.use_graph = opt->use_graph != 0;
         e.down_pass = opt->down_pass;
+        e.up_pass = opt->up_pass;
         e.lone = true;
         {
             cfr::HostGame hg;

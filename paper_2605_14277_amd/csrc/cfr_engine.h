@@ -48,6 +48,7 @@ struct PlayerPlan {
     std::vector<int32_t> lvl_inf;     // [n_levels+1]
     std::vector<int32_t> lvl_seq;     // [n_levels+1]
     std::vector<uint8_t> lvl_kind;    // [n_levels] 0 generic, 1 fast, 2 fast without children
+    std::vector<uint8_t> lvl_pair;    // [n_levels] 1: levels L-1 and L fit one two-level launch
     int32_t top_levels = 0, n_roots = 0;
     std::vector<int32_t> top_off;     // [top_levels*(n_roots+1)]
     std::vector<int32_t> top_list;    // decision points of the shallow levels by level, then root
@@ -183,6 +184,7 @@ struct Slot {
     int64_t sb[2] = {0, 0}, ib[2] = {0, 0}, nb = 0, nnz = 0;
     std::vector<int32_t> lvl_inf[2], lvl_seq[2];
     std::vector<uint8_t> lvl_kind[2];
+    std::vector<uint8_t> lvl_pair[2];
     std::vector<uint8_t> lvl_slots[2];   // per level: kSlotsWrite | kSlotsRead
     std::vector<int32_t> ptr[2];         // local row pointers of csr / csc (re-partitioning)
     int64_t qb[2] = {-1, -1};            // first quad of the game's stream-form-3 copy (-1: none)
@@ -251,6 +253,7 @@ struct Engine {
     bool use_graph = true;
     bool lone = false;  // a single game: shallow levels may run as one launch
     int down_pass = CFR_DOWN_DEFAULT;  // top-down pass: one launch, or one per level
+    int up_pass = CFR_UP_DEFAULT;      // bottom-up pass of a lone game: two-level launches
     hipStream_t st = nullptr;
     hipStream_t cap_st = nullptr;  // private stream used only to capture graphs
     hipStream_t up_st = nullptr;   // admission copies (asynchronous admission)

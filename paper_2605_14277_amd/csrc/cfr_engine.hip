@@ -121,6 +121,19 @@ void plan_player(const cfr_player_desc &d, bool lone, PlayerPlan &pl)
                 else if (kids > 0 && pl.lvl_kind[lv] == 2) pl.lvl_kind[lv] = 1;
             }
         }
+    // levels that can share a launch with the level above them: the lower
+    // level on the fast path and at most kPairLevelMax decision points, every
+    // upper decision point with at most kFastActs actions and kPairKids
+    // decision points below them
+    pl.lvl_pair.assign((size_t)n_levels, 0);
+    for (int32_t lv = 1; lv < n_levels; ++lv) {
+        bool ok = pl.lvl_kind[lv] != 0 && pl.lvl_inf[lv + 1] - pl.lvl_inf[lv] <= kPairLevelMax;
+        for (int32_t k = pl.lvl_inf[lv - 1]; k < pl.lvl_inf[lv] && ok; ++k) {
+            const int32_t a0 = pl.inf_first[k], a1 = pl.inf_first[k + 1];
+            ok = a1 - a0 <= kFastActs && pl.child_ptr[a1] - pl.child_ptr[a0] <= kPairKids;
+        }
+        pl.lvl_pair[lv] = ok ? 1 : 0;
+    }
     // A lone game may run its whole sweep as one launch per root subtree,
     // when every root decision point's share of every level is at most
     // kTopMaxGroup decision points (one pass of the block).  The levels of
@@ -1204,6 +1217,7 @@ int Engine::add(const HostGame &hg, const GameImage &img, const GameParams &gp, 
         s.lvl_inf[p] = pl.lvl_inf;
         s.lvl_seq[p] = pl.lvl_seq;
         s.lvl_kind[p] = pl.lvl_kind;
+        s.lvl_pair[p] = pl.lvl_pair;
         // Small levels store their values in the parent's slots and the
         // level above reads them from there (one dependent load fewer);
         // big levels write their values contiguously, since slot writes
@@ -1639,13 +1653,30 @@ hipError_t Engine::sweeps(const Tables &T, int p, double usign, hipStream_t s)
     const bool top = lone && d.top_levels > 0;
     const int low = top ? d.top_levels : 0;
     // ObserveUtility, deepest level first (level 0's launch also does its
-    // top-down step)
-    for (int L = maxL - 1; L >= low; --L)
-        for (const Tables::Up &u : T.up_l[p][(size_t)L])
+    // top-down step); a lone game runs pairs of adjacent levels that fit the
+    // two-level launch as one launch each
+    const bool pairs = lone && up_pass == CFR_UP_DEFAULT && !slots.empty() && slots[0].live;
+    for (int L = maxL - 1; L >= low;) {
+        const auto &lo = T.up_l[p][(size_t)L];
+        if (pairs && L - 1 >= low && slots[0].lvl_pair[p][(size_t)L] && lo.size() == 1 &&
+            T.up_l[p][(size_t)L - 1].size() == 1) {
+            const Slot &g = slots[0];
+            const Tables::Up &up = T.up_l[p][(size_t)L - 1][0];
+            if ((e = launch_up_pair(prec, up.variant, g.lvl_kind[p][(size_t)L],
+                                    g.lvl_slots[p][(size_t)L] & kSlotsRead,
+                                    g.lvl_slots[p][(size_t)L - 1] & kSlotsWrite, L - 1 == 0 ? 1 : 0,
+                                    up.direct, d, usign, sc, s)) != hipSuccess)
+                return e;
+            L -= 2;
+            continue;
+        }
+        for (const Tables::Up &u : lo)
             if ((e = launch_up(prec, u.variant, u.kind, L == 0 ? 1 : 0, T.up[p] + u.off, u.n,
                                &u.direct, d,
                                usign, sc, s)) != hipSuccess)
                 return e;
+        --L;
+    }
     if (top) {
         // the shallow levels of the lone game, both directions, one launch
         if ((e = launch_top(prec, slots[0].gp.variant, d, usign, 1, sc, s)) != hipSuccess) return e;

@@ -120,6 +120,16 @@ hipError_t launch_spmv(int prec, int items, int vec, const SpmvBlock *tab, int32
 hipError_t launch_up(int prec, int variant, int kind, int root, const RangeBlock *tab,
                      int32_t n_tab, const RangeBlock *direct, const DevPlayer &p, double usign,
                      const Scalars *sc, hipStream_t st);
+// Levels U and U+1 of one game's ObserveUtility in one launch: `upper` is
+// level U's range (one game); every decision point of U has at most
+// kFastActs actions and at most kPairKids decision points below them, and
+// level U+1 is on the fast path (child_kind 1, or 2 with nothing below
+// it).  child_reads_slots: level U+1 reads its children's values from
+// slots; upper_writes_slots: level U stores its values in slots; root:
+// level U is level 0 (its top-down step is done too).
+hipError_t launch_up_pair(int prec, int variant, int child_kind, int child_reads_slots,
+                          int upper_writes_slots, int root, const RangeBlock &upper,
+                          const DevPlayer &p, double usign, const Scalars *sc, hipStream_t st);
 // Top-down pass over the sequences of `tab` (one level).
 hipError_t launch_down(int prec, const RangeBlock *tab, int32_t n_tab, const DevPlayer &p,
                        int average, const Scalars *sc, hipStream_t st);
@@ -233,6 +243,8 @@ constexpr int kDownAllMaxDepth = 16;  // longest parent chain of the one-launch 
 constexpr int kSlotsWrite = 1;  // the level's decision points store values in parent slots
 constexpr int kSlotsRead = 2;   // the level reads its children's values from slots
 constexpr int32_t kSlotLevelMax = 262144;  // largest level (per game) that writes slots
+constexpr int kPairKids = 16;       // two-level launch: decision points below an upper one
+constexpr int32_t kPairLevelMax = 262144;  // largest lower level (per game) of a two-level launch
 constexpr int kFastActs = 4;        // fast sweep path: actions per decision point
 constexpr int kFastKids = 4;        // fast sweep path: decision points below a sequence
 constexpr int kTopThreads = 1024;   // threads of the shallow-level block

@@ -733,8 +733,8 @@ __device__ __forceinline__ void up_infoset(
 // child counts and values when the block reads slots; otherwise child ids;
 // child values.  The arithmetic and its order are exactly those of
 // up_infoset (children in ascending order).
-template <int P, int VAR, int NC, int SL>
-__device__ __forceinline__ void up_infoset_fast(
+template <int P, int VAR, int NC, int SL, bool STORE = true>
+__device__ __forceinline__ typename Types<P>::C up_infoset_fast(
     int32_t j, const int32_t *__restrict__ inf_first, const int32_t *__restrict__ child_ptr,
     const int32_t *__restrict__ child_idx, const typename Types<P>::V *__restrict__ g,
     typename Types<P>::C usign, typename Types<P>::C *__restrict__ vinf,
@@ -750,7 +750,7 @@ __device__ __forceinline__ void up_infoset_fast(
     static_assert(NC == 0 || NC == 4, "child values are read as slots of four");
     constexpr bool kPred = VAR == CFR_PCFR_PLUS || VAR == CFR_PCFR;
     const int32_t a0 = inf_first[j], a1 = inf_first[j + 1];
-    const int32_t cs = (SL & kSlotsWrite) ? kd.cslot[j] : -1;
+    const int32_t cs = (STORE && (SL & kSlotsWrite)) ? kd.cslot[j] : -1;
     const int32_t n = a1 - a0;
     V gv[NA], bv[NA];
     R rv[NA], mv[NA];
@@ -810,7 +810,7 @@ __device__ __forceinline__ void up_infoset_fast(
             V_ = V_ + (C)bv[k] * acc;
         }
     }
-    store_value(kd, cs, j, vinf, V_);
+    if (STORE) store_value(kd, cs, j, vinf, V_);
     C z[NA];
     C Z = 0;
 #pragma unroll
@@ -833,6 +833,7 @@ __device__ __forceinline__ void up_infoset_fast(
 #pragma unroll
     for (int k = 0; k < NA; ++k)
         if (k < n) b[a0 + k] = (V)(Z > 0 ? z[k] / Z : (C)1 / (C)n);
+    return V_;
 }
 
 // One decision point of NextStrategy's top-down pass, accumulating the
@@ -939,6 +940,114 @@ __global__ __launch_bounds__(kThreads) void k_up(
     case kSlotsRead: level(std::integral_constant<int, kSlotsRead>()); break;
     default: level(std::integral_constant<int, kSlotsWrite | kSlotsRead>()); break;
     }
+    if (ROOT) down_infoset<P>(j, inf_first, seq_par, b, x, s, (R)gs->w, 1, true);
+}
+
+// Two adjacent levels of ObserveUtility in one launch (one game's levels U
+// and U+1, every decision point of U with at most kFastActs actions and at
+// most kPairKids decision points below them, level U+1 on the fast path).
+// A group of kPairKids lanes, four groups to a wave, owns one decision point
+// j of level U: lane i takes the i-th decision point below j (its actions'
+// child lists one after another, ascending) and runs its ObserveUtility,
+// regret update and regret matching exactly as level U+1's own launch
+// would, keeping its value in a register instead of storing it.  The group
+// then reads its lanes' values across lanes in ascending order, and every
+// lane of the group computes j: each action's own utility plus the values
+// below it added in that order, the value, the regret update and regret
+// matching; the group's first lane stores.  The sums and their order are
+// those of two separate launches, so every result is bit for bit the same;
+// the launch between the two levels is gone.  Control flow is uniform over
+// a group, so every lane a cross-lane read takes from is active.
+constexpr int kPairGroups = kThreads / kPairKids;  // decision points of level U per block
+static_assert(64 % kPairKids == 0, "a group lies inside one wave");
+
+template <int P, int VAR, int NC, int SLC, int SLU, bool ROOT>
+__global__ __launch_bounds__(kThreads) void k_up_pair(
+    const int32_t *__restrict__ inf_first, const int32_t *__restrict__ child_ptr,
+    const int32_t *__restrict__ child_idx, const typename Types<P>::V *__restrict__ g,
+    typename Types<P>::C usign, typename Types<P>::C *__restrict__ vinf,
+    typename Types<P>::V *__restrict__ b, typename Types<P>::R *__restrict__ r,
+    typename Types<P>::R *__restrict__ m, const Scalars *__restrict__ sc,
+    const int32_t *__restrict__ seq_par, typename Types<P>::V *__restrict__ x,
+    typename Types<P>::R *__restrict__ s, Kids<P> kd, RangeBlock dr)
+{
+    using V = typename Types<P>::V;
+    using R = typename Types<P>::R;
+    using C = typename Types<P>::C;
+    constexpr int NA = kFastActs;
+    constexpr bool kPred = VAR == CFR_PCFR_PLUS || VAR == CFR_PCFR;
+    const int lane = (int)(threadIdx.x % kPairKids);
+    const int first_lane = (int)(threadIdx.x % 64) - lane;
+    const int32_t j = dr.lo + (int32_t)(blockIdx.x * kPairGroups + threadIdx.x / kPairKids);
+    if (j >= dr.hi) return;  // a whole group
+    const Scalars *gs = sc + dr.slot;
+    C dpos = 1, dneg = 1;
+    if (VAR == CFR_DCFR) {
+        dpos = (C)gs->dpos;
+        dneg = (C)gs->dneg;
+    }
+    const int32_t a0 = inf_first[j], a1 = inf_first[j + 1];
+    const int32_t n = a1 - a0;
+    // child list bounds of j's actions (kb[k] .. kb[k+1]: action k's)
+    int32_t kb[NA + 1];
+#pragma unroll
+    for (int k = 0; k <= NA; ++k) kb[k] = child_ptr[a0 + (k < n ? k : n)];
+    const int32_t cp0 = kb[0], nk = kb[NA] - cp0;
+    // level U+1: this lane's decision point
+    C vc = 0;
+    if (lane < nk)
+        vc = up_infoset_fast<P, VAR, NC, SLC, false>(child_idx[cp0 + lane], inf_first, child_ptr,
+                                                     child_idx, g, usign, vinf, b, r, m, dpos,
+                                                     dneg, kd);
+    // level U: decision point j, in every lane of the group
+    V gv[NA], bv[NA];
+    R rv[NA], mv[NA];
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+        const int32_t a = a0 + (k < n ? k : 0);
+        gv[k] = g[a];
+        bv[k] = b[a];
+        rv[k] = r[a];
+        if (kPred) mv[k] = m[a];
+    }
+    C q[NA];
+#pragma unroll
+    for (int k = 0; k < NA; ++k) q[k] = usign * (C)gv[k];
+#pragma unroll
+    for (int i = 0; i < kPairKids; ++i) {
+        const C v = __shfl(vc, first_lane + i, 64);
+#pragma unroll
+        for (int k = 0; k < NA; ++k)
+            if (k < n && cp0 + i >= kb[k] && cp0 + i < kb[k + 1]) q[k] = q[k] + v;
+    }
+    C V_ = 0;
+#pragma unroll
+    for (int k = 0; k < NA; ++k)
+        if (k < n) V_ = V_ + (C)bv[k] * q[k];
+    if (lane != 0) return;
+    store_value(kd, (SLU & kSlotsWrite) ? kd.cslot[j] : -1, j, vinf, V_);
+    C z[NA];
+    C Z = 0;
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+        if (k < n) {
+            const int32_t a = a0 + k;
+            C inst = q[k] - V_;
+            C rr = post_step<P, VAR>((C)rv[k] + inst, dpos, dneg);
+            r[a] = (R)rr;
+            C zz = (C)(R)rr;
+            if (kPred) {
+                m[a] = (R)inst;
+                zz = zz + (C)(R)inst;
+            }
+            zz = zz > 0 ? zz : 0;
+            z[k] = zz;
+            Z = Z + zz;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NA; ++k)
+        if (k < n) b[a0 + k] = (V)(Z > 0 ? z[k] / Z : (C)1 / (C)n);
     if (ROOT) down_infoset<P>(j, inf_first, seq_par, b, x, s, (R)gs->w, 1, true);
 }
 
@@ -1421,6 +1530,69 @@ hipError_t up_dispatch(int variant, int kind, int root, const RangeBlock *tab, i
     }
 }
 
+template <int P, int VAR, int NC, int SLC, int SLU, bool ROOT>
+hipError_t pair_launch(const RangeBlock &dr, const DevPlayer &p, double usign, const Scalars *sc,
+                       hipStream_t st)
+{
+    using T = Types<P>;
+    const unsigned grid = (unsigned)((dr.hi - dr.lo + kPairGroups - 1) / kPairGroups);
+    hipLaunchKernelGGL((k_up_pair<P, VAR, NC, SLC, SLU, ROOT>), dim3(grid), dim3(kThreads), 0, st,
+                       p.inf_first, p.child_ptr, p.child_idx, (const typename T::V *)p.g,
+                       (typename T::C)usign, (typename T::C *)p.vinf, (typename T::V *)p.b,
+                       (typename T::R *)p.r, (typename T::R *)p.m, sc, p.seq_par,
+                       (typename T::V *)p.x, (typename T::R *)p.s, kids<P>(p), dr);
+    return hipGetLastError();
+}
+
+template <int P, int VAR, int NC>
+hipError_t pair_flags(int child_reads_slots, int upper_writes_slots, int root,
+                      const RangeBlock &dr, const DevPlayer &p, double usign, const Scalars *sc,
+                      hipStream_t st)
+{
+    const int f = (child_reads_slots ? 1 : 0) | (upper_writes_slots && !root ? 2 : 0);
+    if (root) {
+        if (f & 1) return pair_launch<P, VAR, NC, kSlotsRead, 0, true>(dr, p, usign, sc, st);
+        return pair_launch<P, VAR, NC, 0, 0, true>(dr, p, usign, sc, st);
+    }
+    switch (f) {
+    case 0: return pair_launch<P, VAR, NC, 0, 0, false>(dr, p, usign, sc, st);
+    case 1: return pair_launch<P, VAR, NC, kSlotsRead, 0, false>(dr, p, usign, sc, st);
+    case 2: return pair_launch<P, VAR, NC, 0, kSlotsWrite, false>(dr, p, usign, sc, st);
+    default: return pair_launch<P, VAR, NC, kSlotsRead, kSlotsWrite, false>(dr, p, usign, sc, st);
+    }
+}
+
+template <int P, int VAR>
+hipError_t pair_t(int child_kind, int child_reads_slots, int upper_writes_slots, int root,
+                  const RangeBlock &dr, const DevPlayer &p, double usign, const Scalars *sc,
+                  hipStream_t st)
+{
+    if (dr.hi <= dr.lo) return hipSuccess;
+    // NC = 0 only for a lower level with nothing below it, whose decision
+    // points read no child values (so no slot flag applies)
+    if (child_kind == 2)
+        return pair_flags<P, VAR, 0>(0, upper_writes_slots, root, dr, p, usign, sc, st);
+    return pair_flags<P, VAR, kFastKids>(child_reads_slots, upper_writes_slots, root, dr, p, usign,
+                                         sc, st);
+}
+
+template <int P>
+hipError_t pair_dispatch(int variant, int child_kind, int child_reads_slots,
+                         int upper_writes_slots, int root, const RangeBlock &dr,
+                         const DevPlayer &p, double usign, const Scalars *sc, hipStream_t st)
+{
+#define CFR_PAIR_ARGS child_kind, child_reads_slots, upper_writes_slots, root, dr, p, usign, sc, st
+    switch (variant) {
+    case CFR_VANILLA: return pair_t<P, CFR_VANILLA>(CFR_PAIR_ARGS);
+    case CFR_PLUS: return pair_t<P, CFR_PLUS>(CFR_PAIR_ARGS);
+    case CFR_DCFR: return pair_t<P, CFR_DCFR>(CFR_PAIR_ARGS);
+    case CFR_PCFR_PLUS: return pair_t<P, CFR_PCFR_PLUS>(CFR_PAIR_ARGS);
+    case CFR_PCFR: return pair_t<P, CFR_PCFR>(CFR_PAIR_ARGS);
+    default: return hipErrorInvalidValue;
+    }
+#undef CFR_PAIR_ARGS
+}
+
 template <int P, int VAR>
 hipError_t top_t(const DevPlayer &p, double usign, int average, const Scalars *sc, hipStream_t st)
 {
@@ -1556,6 +1728,14 @@ hipError_t launch_up(int prec, int variant, int kind, int root, const RangeBlock
 {
     const RangeBlock dr = direct ? *direct : RangeBlock{0, 0, 0, 0};
     CFR_DISPATCH(prec, up_dispatch<P>(variant, kind, root, tab, n_tab, dr, p, usign, sc, st));
+}
+
+hipError_t launch_up_pair(int prec, int variant, int child_kind, int child_reads_slots,
+                          int upper_writes_slots, int root, const RangeBlock &upper,
+                          const DevPlayer &p, double usign, const Scalars *sc, hipStream_t st)
+{
+    CFR_DISPATCH(prec, pair_dispatch<P>(variant, child_kind, child_reads_slots,
+                                        upper_writes_slots, root, upper, p, usign, sc, st));
 }
 
 hipError_t launch_top(int prec, int variant, const DevPlayer &p, double usign, int average,
