@@ -96,13 +96,15 @@ enum { CFR_SPMV_DEFAULT = 0, CFR_SPMV_SEQUENTIAL = 1, CFR_SPMV_PARALLEL = 2 };
  * than 16; otherwise, and with LEVELS, one launch per level.             */
 enum { CFR_DOWN_DEFAULT = 0, CFR_DOWN_LEVELS = 1 };
 
-/* Bottom-up pass of a single solver.  DEFAULT: two adjacent levels run as
- * one launch wherever the upper level's decision points have at most 4
- * actions and at most 16 decision points below them and the lower level has
- * at most 4 actions per decision point, 4 decision points below each action
- * and at most 2^18 decision points (the same operations in the same order
- * as two launches, so identical results); LEVELS: one launch per level.  */
-enum { CFR_UP_DEFAULT = 0, CFR_UP_LEVELS = 1 };
+/* Bottom-up pass of a single solver.  DEFAULT and LEVELS: one launch per
+ * level.  PAIRS: two adjacent levels run as one launch wherever the upper
+ * level's decision points have at most 4 actions and at most 16 decision
+ * points below them and the lower level has at most 4 actions per decision
+ * point, 4 decision points below each action and at most 2^18 decision
+ * points (the same operations in the same order as two launches, so
+ * identical results; it chains more dependent memory rounds than two
+ * launches cost, and measured slower on the medium and large games).     */
+enum { CFR_UP_DEFAULT = 0, CFR_UP_LEVELS = 1, CFR_UP_PAIRS = 2 };
 
 /* Averaging weight w_t.  DEFAULT: 1 (vanilla, PCFR), t (CFR+), t^gamma
  * (DCFR; the paper's quadratic weighting with gamma = 2), t^2 (PCFR+).   */

@@ -29,7 +29,7 @@ KINDS = {"current": 0, "average": 1}
 AVG = {"default": 0, "uniform": 1, "linear": 2, "quadratic": 3, "pow_gamma": 4}
 SPMV_ORDER = {"default": 0, "sequential": 1, "parallel": 2}
 DOWN_PASS = {"default": 0, "levels": 1}
-UP_PASS = {"default": 0, "levels": 1}
+UP_PASS = {"default": 0, "levels": 1, "pairs": 2}
 GAME_STATES = {0: "active", 1: "waiting", 2: "done"}
 ERRORS = {CFR_EINVAL: "EINVAL", CFR_ENOMEM: "ENOMEM", CFR_EDEVICE: "EDEVICE",
           CFR_ESTATE: "ESTATE", CFR_EUNSUPPORTED: "EUNSUPPORTED"}

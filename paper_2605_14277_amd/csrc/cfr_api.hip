@@ -148,7 +148,7 @@ int check_options(const cfr_options *o)
         return fail(CFR_EINVAL, "unknown summation order");
     if (o->down_pass != CFR_DOWN_DEFAULT && o->down_pass != CFR_DOWN_LEVELS)
         return fail(CFR_EINVAL, "unknown top-down pass");
-    if (o->up_pass != CFR_UP_DEFAULT && o->up_pass != CFR_UP_LEVELS)
+    if (o->up_pass != CFR_UP_DEFAULT && o->up_pass != CFR_UP_LEVELS && o->up_pass != CFR_UP_PAIRS)
         return fail(CFR_EINVAL, "unknown bottom-up pass");
     if (!std::isfinite(o->dcfr_alpha) || !std::isfinite(o->dcfr_beta) ||
         !std::isfinite(o->dcfr_gamma))

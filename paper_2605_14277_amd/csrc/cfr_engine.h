@@ -253,7 +253,7 @@ struct Engine {
     bool use_graph = true;
     bool lone = false;  // a single game: shallow levels may run as one launch
     int down_pass = CFR_DOWN_DEFAULT;  // top-down pass: one launch, or one per level
-    int up_pass = CFR_UP_DEFAULT;      // bottom-up pass of a lone game: two-level launches
+    int up_pass = CFR_UP_DEFAULT;      // bottom-up pass of a lone game: per level, or pairs
     hipStream_t st = nullptr;
     hipStream_t cap_st = nullptr;  // private stream used only to capture graphs
     hipStream_t up_st = nullptr;   // admission copies (asynchronous admission)

@@ -1653,9 +1653,9 @@ hipError_t Engine::sweeps(const Tables &T, int p, double usign, hipStream_t s)
     const bool top = lone && d.top_levels > 0;
     const int low = top ? d.top_levels : 0;
     // ObserveUtility, deepest level first (level 0's launch also does its
-    // top-down step); a lone game runs pairs of adjacent levels that fit the
-    // two-level launch as one launch each
-    const bool pairs = lone && up_pass == CFR_UP_DEFAULT && !slots.empty() && slots[0].live;
+    // top-down step); with CFR_UP_PAIRS a lone game runs pairs of adjacent
+    // levels that fit the two-level launch as one launch each
+    const bool pairs = lone && up_pass == CFR_UP_PAIRS && !slots.empty() && slots[0].live;
     for (int L = maxL - 1; L >= low;) {
         const auto &lo = T.up_l[p][(size_t)L];
         if (pairs && L - 1 >= low && slots[0].lvl_pair[p][(size_t)L] && lo.size() == 1 &&

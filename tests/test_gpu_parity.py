@@ -625,14 +625,15 @@ def test_wide_games_batched_equal_alone(cfr, precision):
 @pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("mode", MODES)
 def test_two_level_launches_equal_level_by_level(cfr, oracle_mod, variant, mode):
-    """The medium game's bottom-up pass runs adjacent levels as one launch
-    (player 1: levels 6+5, 4+3, 2+1 and 0; player 2: 5+4, 3+2, 1+0, the
-    lowest pair including the root level's top-down step and the deepest
-    pairs a level with nothing below it).  In FP64 every iterate equals the
-    one-launch-per-level pass bit for bit, and both match the oracle."""
+    """With the two-level option the medium game's bottom-up pass runs
+    adjacent levels as one launch (player 1: levels 6+5, 4+3, 2+1 and 0;
+    player 2: 5+4, 3+2, 1+0, the lowest pair including the root level's
+    top-down step and the deepest pairs a level with nothing below it).  In
+    FP64 every iterate equals the default one-launch-per-level pass bit for
+    bit, and both match the oracle."""
     g = gg.cfg2()
-    fused = cfr.Solver(g, precision="fp64")
-    plain = cfr.Solver(g, precision="fp64", up_pass="levels")
+    fused = cfr.Solver(g, precision="fp64", up_pass="pairs")
+    plain = cfr.Solver(g, precision="fp64")
     orc = oracle_mod.Oracle(g, parallel=True)
     for n in (1, 29):
         fused.step(n, variant, mode)
@@ -651,12 +652,10 @@ def test_two_level_launches_equal_level_by_level(cfr, oracle_mod, variant, mode)
 @pytest.mark.parametrize("precision", ["fp32", "fp32_acc64"])
 def test_two_level_launches_fp32_modes(cfr, precision):
     """The same in the FP32 modes on the medium game: bit for bit equal to
-    one launch per level.  (The large game's pairs, levels 3+2 and 1+0 of
-    both players, are checked in FP64 against the oracle above and in the
-    FP32 mode over 1000 iterations.)"""
+    one launch per level."""
     g = gg.cfg2()
-    a = cfr.Solver(g, precision=precision)
-    b = cfr.Solver(g, precision=precision, up_pass="levels")
+    a = cfr.Solver(g, precision=precision, up_pass="pairs")
+    b = cfr.Solver(g, precision=precision)
     for s in (a, b):
         s.step(40, "dcfr", "alternating")
     for p in range(2):
