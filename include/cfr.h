@@ -191,6 +191,27 @@ int cfr_workspace_size(const cfr_game_desc *game, const cfr_options *opt, size_t
  * hipMalloc failed), CFR_EDEVICE (HIP error).                               */
 int cfr_create(const cfr_game_desc *game, const cfr_options *opt, cfr_solver **out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): as
+ * cfr_create, but the solver allocates nothing on the device or in
+ * page-locked host memory, at creation or later.  Its device state lives
+ * in a static array of CFR_STATIC_WORKSPACE_BYTES that the library holds
+ * on each GPU it runs on from its first use there until the process ends;
+ * every solver made this way on one GPU uses that GPU's array, so at most
+ * one lives per GPU at a time (CFR_ESTATE while another does; calls that
+ * overlap on one GPU would race on the array, which keeps the last
+ * solver's contents: creation initialises everything a solver reads).
+ * opt->workspace must be NULL (CFR_EINVAL) and opt->use_graph is ignored
+ * (iterations are launched one kernel at a time on opt->stream).  A game
+ * whose cfr_workspace_size exceeds the array gets CFR_ENOMEM before any
+ * device call.  The solver is used and released with the usual calls
+ * (cfr_step, cfr_strategy, cfr_exploitability, cfr_destroy ...) and gives
+ * the same results as one made by cfr_create; cfr_tune and
+ * cfr_kernel_timing (which create HIP events) and tilings with stream form
+ * 3 (whose quad copies are allocated) return CFR_EUNSUPPORTED.           */
+#define CFR_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+int cfr_create_static(const cfr_game_desc *game, const cfr_options *opt, cfr_solver **out);
+
 /* Enqueues n >= 0 iterations on the solver's stream and returns without
  * waiting.  The variant and mode of the first call stay fixed for the life
  * of the solver; a different pair returns CFR_ESTATE.                      */

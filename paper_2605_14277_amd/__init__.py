@@ -96,6 +96,7 @@ _lib.cfr_options_default.argtypes = [_P(cfr_options)]
 _lib.cfr_validate.argtypes = [_P(cfr_game_desc)]
 _lib.cfr_workspace_size.argtypes = [_P(cfr_game_desc), _P(cfr_options), _P(C.c_size_t)]
 _lib.cfr_create.argtypes = [_P(cfr_game_desc), _P(cfr_options), _P(C.c_void_p)]
+_lib.cfr_create_static.argtypes = [_P(cfr_game_desc), _P(cfr_options), _P(C.c_void_p)]
 _lib.cfr_step.argtypes = [C.c_void_p, C.c_int64, C.c_int, C.c_int]
 _lib.cfr_strategy.argtypes = [C.c_void_p, C.c_int, C.c_int, _P(C.c_double), C.c_int64]
 _lib.cfr_regrets.argtypes = [C.c_void_p, C.c_int, _P(C.c_double), C.c_int64]
@@ -139,7 +140,8 @@ _lib.cfr_prepare_quads.argtypes = [C.c_void_p, _P(C.c_int)]
 _lib.cfr_batch_add_prepared.argtypes = [C.c_void_p, C.c_void_p, _P(cfr_game_params),
                                         _P(C.c_int64)]
 _lib.cfr_prepared_destroy.argtypes = [C.c_void_p]
-for _f in ("cfr_options_default", "cfr_validate", "cfr_workspace_size", "cfr_create", "cfr_step",
+for _f in ("cfr_options_default", "cfr_validate", "cfr_workspace_size", "cfr_create",
+           "cfr_create_static", "cfr_step",
            "cfr_strategy", "cfr_regrets", "cfr_exploitability", "cfr_iteration",
            "cfr_kernel_timing", "cfr_kernel_stats", "cfr_get_tiling", "cfr_set_tiling",
            "cfr_state_size", "cfr_get_state", "cfr_set_state",
@@ -233,6 +235,17 @@ def cfr_create(game_arrays: GameArrays, opts: cfr_options) -> C.c_void_p:
     h = C.c_void_p()
     _check(_lib.cfr_create(C.byref(game_arrays.desc), C.byref(opts), C.byref(h)), "cfr_create")
     return h
+
+
+def cfr_create_static(game_arrays: GameArrays, opts: cfr_options) -> C.c_void_p:
+    h = C.c_void_p()
+    _check(_lib.cfr_create_static(C.byref(game_arrays.desc), C.byref(opts), C.byref(h)),
+           "cfr_create_static")
+    return h
+
+
+# bytes of the library's static per-device workspace (cfr_create_static)
+STATIC_WORKSPACE_BYTES = 64 << 20
 
 
 def cfr_step(h, n: int, variant: int, mode: int):
@@ -470,13 +483,16 @@ class _Untuned:
 
 class Solver:
     """One game on one GPU.  Device memory comes from a torch uint8 tensor;
-    work is enqueued on torch's current stream of that device."""
+    work is enqueued on torch's current stream of that device.  With
+    static_workspace=True the solver is made by cfr_create_static instead: no
+    device memory is allocated for it (its state lives in the library's static
+    per-device array) and iterations are launched without a graph."""
 
     def __init__(self, game, precision: str = "fp64", device: int = 0, alpha: float = 1.5,
                  beta: float = 0.0, gamma: float = 2.0, avg: str = "default",
                  use_graph: bool = True, stream=None, with_csc: bool = True,
                  spmv_order: str = "default", down_pass: str = "default",
-                 up_pass: str = "default"):
+                 up_pass: str = "default", static_workspace: bool = False):
         import torch
         self.torch = torch
         self.arrays = GameArrays(game, with_csc=with_csc)
@@ -498,6 +514,10 @@ class Solver:
         self.stream = stream
         o.stream = C.c_void_p(int(stream.cuda_stream))
         nbytes = cfr_workspace_size(self.arrays, o)
+        if static_workspace:
+            self.opts, self.workspace, self.workspace_bytes = o, None, nbytes
+            self.h = cfr_create_static(self.arrays, o)
+            return
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         o.workspace = C.c_void_p(int(self.workspace.data_ptr()))
         o.workspace_bytes = nbytes

@@ -18,6 +18,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -214,6 +215,9 @@ int check_device(int device)
 // Stream form 3 only where the column player's index space fits a quad word.
 int check_tiling_fits(const cfr::Engine &e, const cfr_spmv_tiling *t)
 {
+    if (e.no_alloc && (t->vec[0] == 3 || t->vec[1] == 3))
+        return fail(CFR_EUNSUPPORTED, "stream form 3 allocates its quad copies; a solver made by "
+                                      "cfr_create_static cannot use it");
     for (int w = 0; w < 2; ++w)
         if (t->vec[w] == 3 && !cfr::quads_fit(e.cap.seq[1 - w]))
             return fail(CFR_EINVAL, "stream form 3 needs every column index below 2^30 (the "
@@ -357,6 +361,116 @@ struct cfr_solver {
     int variant = -1, mode = -1;
 };
 
+namespace {
+
+// Device bytes of a lone solver for this (validated) game.
+size_t lone_bytes(const cfr_game_desc *game, int precision)
+{
+    cfr::HostGame hg;
+    cfr::prepare_game(game, true, false, hg);
+    const cfr::Capacity c = cfr::lone_capacity(hg, cfr::kSpmvItemsDefault, cfr::kSpmvRowCap,
+                                               cfr::kSpmvItemsDefault, cfr::kSpmvRowCap);
+    return cfr::engine_bytes(c, precision);
+}
+
+// cfr_create after validation, on the current device: the solver's state
+// in `ws` (ws_bytes long), or in a workspace it allocates when ws is null.
+// no_alloc: the solver allocates nothing on the device or in page-locked
+// memory, now or later (no upload stream, no staging, no graph).
+int create_lone(const cfr_game_desc *game, const cfr_options *opt, void *ws, size_t ws_bytes,
+                bool no_alloc, cfr_solver **out)
+{
+    cfr_solver *s = new cfr_solver();
+    cfr::Engine &e = s->eng;
+    e.spmv_order = opt->spmv_order;
+    e.use_graph = !no_alloc && opt->use_graph != 0;
+    e.no_alloc = no_alloc;
+    e.down_pass = opt->down_pass;
+    e.up_pass = opt->up_pass;
+    e.lone = true;
+    int rc = CFR_OK;
+    try {
+        cfr::HostGame hg;
+        cfr::prepare_game(game, true, true, hg);
+        cfr::GameImage img;
+        cfr::build_image(hg, opt->precision, false, true, img);
+        const cfr::Capacity c = cfr::lone_capacity(hg, e.items[0], e.rows[0], e.items[1],
+                                                   e.rows[1]);
+        rc = e.init(c, opt->precision, opt->device, (hipStream_t)opt->stream, ws, ws_bytes);
+        if (!rc) {
+            cfr::GameParams gp;
+            gp.variant = -1;
+            gp.avg_kind = opt->avg_weight;
+            gp.alpha = opt->dcfr_alpha;
+            gp.beta = opt->dcfr_beta;
+            gp.gamma = opt->dcfr_gamma;
+            int slot = -1;
+            rc = e.add(hg, img, gp, true, false, &slot);
+        }
+    } catch (...) {
+        s->eng.release();
+        delete s;
+        throw;
+    }
+    if (rc) {
+        s->eng.release();
+        delete s;
+        return rc;
+    }
+    *out = s;
+    return CFR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free solvers (cfr_create_static)
+// ---------------------------------------------------------------------------
+// Their device state lives in this array instead of in memory the library
+// allocates.  Each GPU holds its own copy from the library's first use on
+// that GPU until the process ends.  In host code the name stands for a
+// host-side shadow, not a device address: the device address is taken once
+// per device with hipGetSymbolAddress (static_slot) and only that address
+// is handed to the engine, and from there to kernels and copies.
+__device__ __align__(256) unsigned char scratch[CFR_STATIC_WORKSPACE_BYTES];
+
+struct StaticSlot {
+    void *ptr = nullptr;  // device address of `scratch` on this device
+    bool busy = false;    // a solver made by cfr_create_static lives here
+};
+std::mutex g_static_mu;
+std::vector<StaticSlot> g_static;  // by device ordinal
+
+// Takes the current device's array for one solver: its device address, or
+// an error (the array is already in use, or its address is unavailable).
+int static_take(int dev, void **ptr)
+{
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (g_static.size() <= (size_t)dev) g_static.resize((size_t)dev + 1);
+    StaticSlot &ss = g_static[(size_t)dev];
+    if (!ss.ptr) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(CFR_EDEVICE, hip_msg("address of the static workspace", e));
+        }
+        ss.ptr = p;
+    }
+    if (ss.busy)
+        return fail(CFR_ESTATE, "another solver made by cfr_create_static is alive on this "
+                                "device (they share its static workspace)");
+    ss.busy = true;
+    *ptr = ss.ptr;
+    return CFR_OK;
+}
+
+void static_give_back(int dev)
+{
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if ((size_t)dev < g_static.size()) g_static[(size_t)dev].busy = false;
+}
+
+}  // namespace
+
 struct cfr_prepared {
     cfr::HostGame hg;  // plans and row pointers (the streams live in the image)
     cfr::GameImage img;
@@ -406,11 +520,7 @@ int cfr_workspace_size(const cfr_game_desc *game, const cfr_options *opt, size_t
         if (rc) return rc;
         rc = validate_game(game, false);
         if (rc) return rc;
-        cfr::HostGame hg;
-        cfr::prepare_game(game, true, false, hg);
-        const cfr::Capacity c = cfr::lone_capacity(hg, cfr::kSpmvItemsDefault, cfr::kSpmvRowCap,
-                                                   cfr::kSpmvItemsDefault, cfr::kSpmvRowCap);
-        *bytes = cfr::engine_bytes(c, opt->precision);
+        *bytes = lone_bytes(game, opt->precision);
         return CFR_OK;
     } catch (const std::exception &ex) {
         return fail(CFR_ENOMEM, std::string("host allocation failed: ") + ex.what());
@@ -421,7 +531,6 @@ int cfr_create(const cfr_game_desc *game, const cfr_options *opt, cfr_solver **o
 {
     if (!out) return fail(CFR_EINVAL, "null output");
     *out = nullptr;
-    cfr_solver *s = nullptr;
     try {
         int rc = check_options(opt);
         if (rc) return rc;
@@ -430,45 +539,45 @@ int cfr_create(const cfr_game_desc *game, const cfr_options *opt, cfr_solver **o
         rc = check_device(opt->device);
         if (rc) return rc;
         DeviceGuard guard(opt->device);
-        s = new cfr_solver();
-        cfr::Engine &e = s->eng;
-        e.spmv_order = opt->spmv_order;
-        e.use_graph = opt->use_graph != 0;
-        e.down_pass = opt->down_pass;
-        e.up_pass = opt->up_pass;
-        e.lone = true;
-        {
-            cfr::HostGame hg;
-            cfr::prepare_game(game, true, true, hg);
-            cfr::GameImage img;
-            cfr::build_image(hg, opt->precision, false, true, img);
-            const cfr::Capacity c = cfr::lone_capacity(hg, e.items[0], e.rows[0], e.items[1],
-                                                       e.rows[1]);
-            rc = e.init(c, opt->precision, opt->device, (hipStream_t)opt->stream, opt->workspace,
-                        opt->workspace_bytes);
-            if (!rc) {
-                cfr::GameParams gp;
-                gp.variant = -1;
-                gp.avg_kind = opt->avg_weight;
-                gp.alpha = opt->dcfr_alpha;
-                gp.beta = opt->dcfr_beta;
-                gp.gamma = opt->dcfr_gamma;
-                int slot = -1;
-                rc = e.add(hg, img, gp, true, false, &slot);
-            }
-        }
-        if (rc) {
-            s->eng.release();
-            delete s;
-            return rc;
-        }
-        *out = s;
-        return CFR_OK;
+        return create_lone(game, opt, opt->workspace, opt->workspace_bytes, false, out);
     } catch (const std::exception &ex) {
-        if (s) {
-            s->eng.release();
-            delete s;
+        return fail(CFR_ENOMEM, std::string("host allocation failed: ") + ex.what());
+    }
+}
+
+int cfr_create_static(const cfr_game_desc *game, const cfr_options *opt, cfr_solver **out)
+{
+    if (!out) return fail(CFR_EINVAL, "null output");
+    *out = nullptr;
+    bool taken = false;
+    try {
+        int rc = check_options(opt);
+        if (rc) return rc;
+        if (opt->workspace)
+            return fail(CFR_EINVAL, "cfr_create_static takes no workspace (it uses the "
+                                    "library's static one)");
+        rc = validate_game(game, true);
+        if (rc) return rc;
+        const size_t need = lone_bytes(game, opt->precision);
+        if (need > (size_t)CFR_STATIC_WORKSPACE_BYTES) {
+            char buf[160];
+            snprintf(buf, sizeof buf,
+                     "the game needs %zu bytes of device state; the static workspace holds %zu",
+                     need, (size_t)CFR_STATIC_WORKSPACE_BYTES);
+            return fail(CFR_ENOMEM, buf);
         }
+        rc = check_device(opt->device);
+        if (rc) return rc;
+        DeviceGuard guard(opt->device);
+        void *ws = nullptr;
+        rc = static_take(opt->device, &ws);
+        if (rc) return rc;
+        taken = true;
+        rc = create_lone(game, opt, ws, (size_t)CFR_STATIC_WORKSPACE_BYTES, true, out);
+        if (rc) static_give_back(opt->device);
+        return rc;
+    } catch (const std::exception &ex) {
+        if (taken) static_give_back(opt->device);
         return fail(CFR_ENOMEM, std::string("host allocation failed: ") + ex.what());
     }
 }
@@ -693,6 +802,9 @@ int cfr_iteration(cfr_solver *s, int64_t *t)
 int cfr_kernel_timing(cfr_solver *s, int enable)
 {
     if (!s) return fail(CFR_EINVAL, "null solver");
+    if (s->eng.no_alloc && enable)
+        return fail(CFR_EUNSUPPORTED, "kernel timing creates HIP events; a solver made by "
+                                      "cfr_create_static does not");
     DeviceGuard guard(s->eng.device);
     return kernel_timing(s->eng, enable);
 }
@@ -732,6 +844,9 @@ int cfr_set_tiling(cfr_solver *s, const cfr_spmv_tiling *t)
 int cfr_tune(cfr_solver *s, int reps, cfr_spmv_tiling *chosen)
 {
     if (!s) return fail(CFR_EINVAL, "null solver");
+    if (s->eng.no_alloc)
+        return fail(CFR_EUNSUPPORTED, "the autotuner times with HIP events; a solver made by "
+                                      "cfr_create_static does not create them");
     if (s->eng.failed) return fail(CFR_ESTATE, "solver is in an error state");
     try {
         DeviceGuard guard(s->eng.device);
@@ -744,12 +859,15 @@ int cfr_tune(cfr_solver *s, int reps, cfr_spmv_tiling *chosen)
 int cfr_destroy(cfr_solver *s)
 {
     if (!s) return CFR_OK;
+    const bool static_ws = s->eng.no_alloc;
+    const int dev = s->eng.device;
     {
-        DeviceGuard guard(s->eng.device);
+        DeviceGuard guard(dev);
         (void)hipStreamSynchronize(s->eng.st);
         s->eng.release();
     }
     delete s;
+    if (static_ws) static_give_back(dev);
     return CFR_OK;
 }
 

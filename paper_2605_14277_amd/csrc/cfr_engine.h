@@ -251,6 +251,7 @@ struct Engine {
     int xcd_remap[2] = {1, 1};  // per product: XCD-contiguous block order
     int device = 0;
     bool use_graph = true;
+    bool no_alloc = false;  // allocates no device or page-locked memory (cfr_create_static)
     bool lone = false;  // a single game: shallow levels may run as one launch
     int down_pass = CFR_DOWN_DEFAULT;  // top-down pass: one launch, or one per level
     int up_pass = CFR_UP_DEFAULT;      // bottom-up pass of a lone game: per level, or pairs
@@ -309,6 +310,7 @@ struct Engine {
     // Carves the device buffers for `c` out of `workspace` (or allocates).
     int init(const Capacity &c, int precision, int dev, hipStream_t stream, void *workspace,
              size_t workspace_bytes);
+    int init_arenas(const Capacity &c);  // host-side range allocators and game slots
     void release();
     int device_error(const char *what, hipError_t e);
     int sync(const char *what);

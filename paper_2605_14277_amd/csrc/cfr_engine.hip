@@ -840,6 +840,9 @@ int Engine::init(const Capacity &c, int precision, int dev, hipStream_t stream, 
         e = hipMemsetAsync(dp[p].child_idx, 0, 4 * (size_t)std::max<int64_t>(c.inf[p], 1), st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return device_error("workspace initialisation", e);
+    // an allocation-free engine admits its one game synchronously on the
+    // caller's stream and stages from ordinary host memory
+    if (no_alloc) return init_arenas(c);
     e = hipStreamCreateWithFlags(&up_st, hipStreamNonBlocking);
     if (e != hipSuccess) return device_error("upload stream", e);
     {
@@ -851,6 +854,11 @@ int Engine::init(const Capacity &c, int precision, int dev, hipStream_t stream, 
         else
             (void)hipGetLastError();
     }
+    return init_arenas(c);
+}
+
+int Engine::init_arenas(const Capacity &c)
+{
     for (int p = 0; p < 2; ++p) {
         seq_alloc[p].init(c.seq[p]);
         inf_alloc[p].init(c.inf[p]);

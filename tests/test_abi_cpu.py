@@ -324,3 +324,33 @@ def test_tuning_cache_by_size_bucket(tmp_path):
     assert tune_cached(c, k2, path, 3) == (t2, False) and c.calls == 1
     import json
     assert json.load(open(path)) == {k: t1, k2: t2}
+
+
+def test_static_solver_refusals_on_the_host(cfr, games):
+    """cfr_create_static refuses, before any device call: a game whose
+    device state exceeds the static workspace (CFR_ENOMEM), a caller
+    workspace (CFR_EINVAL); a game that fits reaches the device check."""
+    o = cfr.cfr_options_default()
+    big = cfr.GameArrays(gg.cfg2())
+    assert cfr.cfr_workspace_size(big, o) > cfr.STATIC_WORKSPACE_BYTES
+    with pytest.raises(cfr.CfrError) as ei:
+        cfr.cfr_create_static(big, o)
+    assert ei.value.code == cfr.CFR_ENOMEM
+    small = cfr.GameArrays(games["cfg1"])
+    o.workspace = C.c_void_p(4096)
+    o.workspace_bytes = 1 << 20
+    with pytest.raises(cfr.CfrError) as ei:
+        cfr.cfr_create_static(small, o)
+    assert ei.value.code == cfr.CFR_EINVAL
+    import torch
+    if not torch.cuda.is_available():
+        o = cfr.cfr_options_default()
+        with pytest.raises(cfr.CfrError) as ei:
+            cfr.cfr_create_static(small, o)
+        assert ei.value.code == cfr.CFR_EDEVICE
+
+
+def test_static_workspace_size_matches_header(cfr):
+    text = open(HEADER).read()
+    m = re.search(r"#define CFR_STATIC_WORKSPACE_BYTES \(\(size_t\)(\d+) << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == cfr.STATIC_WORKSPACE_BYTES
