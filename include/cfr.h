@@ -184,9 +184,11 @@ int cfr_validate(const cfr_game_desc *game);
  * 256-byte alignment of every buffer).                                     */
 int cfr_workspace_size(const cfr_game_desc *game, const cfr_options *opt, size_t *bytes);
 
-/* Validates the game, lays it out level by level, copies it to the device
- * and sets t = 0, regrets and averages to zero and both current strategies
- * to uniform.  *out receives the solver; on failure *out is NULL.
+/* Validates the game (one tree-form sequential decision process per player
+ * and the sequence-form payoff matrix of Section 2.1), lays it out level by
+ * level, copies it to the device and sets t = 0, regrets and averages to
+ * zero and both current strategies to uniform (regret matching on zero
+ * regrets, the arbitrary choice Section 2.1 leaves open).  *out receives the solver; on failure *out is NULL.
  * Errors: CFR_EINVAL (game or options), CFR_ENOMEM (workspace too small or
  * hipMalloc failed), CFR_EDEVICE (HIP error).                               */
 int cfr_create(const cfr_game_desc *game, const cfr_options *opt, cfr_solver **out);
@@ -213,28 +215,39 @@ int cfr_create(const cfr_game_desc *game, const cfr_options *opt, cfr_solver **o
 int cfr_create_static(const cfr_game_desc *game, const cfr_options *opt, cfr_solver **out);
 
 /* Enqueues n >= 0 iterations on the solver's stream and returns without
- * waiting.  The variant and mode of the first call stay fixed for the life
- * of the solver; a different pair returns CFR_ESTATE.                      */
+ * waiting.  One iteration is Algorithm 2 (ObserveUtility after the payoff
+ * products, then NextStrategy) with the variant's regret update (Algorithms
+ * 3-5) and the update schedule of Section 3.5 (alternating: player 1
+ * observes A y^t and moves, then player 2 observes -A^T x^{t+1}).  The
+ * variant and mode of the first call stay fixed for the life of the
+ * solver; a different pair returns CFR_ESTATE.                             */
 int cfr_step(cfr_solver *s, int64_t n, int variant, int mode);
 
 /* Copies a sequence-form strategy of `player` (0 or 1) into out[len]
  * (len must equal that player's n_seq), in the caller's numbering, as
- * double.  kind is CFR_CURRENT or CFR_AVERAGE.  Waits for the stream.      */
+ * double: a point of the player's sequence-form polytope (Section 2.1),
+ * the current one produced by NextStrategy of Algorithm 2 or the weighted
+ * average.  kind is CFR_CURRENT or CFR_AVERAGE.  Waits for the stream.     */
 int cfr_strategy(cfr_solver *s, int player, int kind, double *out, int64_t len);
 
 /* Cumulative regrets of `player` (entry 0 is 0), caller's numbering, as
  * double; waits for the stream.                                            */
 int cfr_regrets(cfr_solver *s, int player, double *out, int64_t len);
 
-/* Evaluates the CURRENT or AVERAGE profile (xbar, ybar) on the device:
+/* Evaluates the CURRENT or AVERAGE profile (xbar, ybar) on the device and
+ * writes the first min(len, 5) of:
  *   out[0] exploitability = NashConv / 2
  *   out[1] NashConv = BR1 + BR2
  *   out[2] BR1 = max_x x^T A ybar
  *   out[3] BR2 = max_y -(xbar^T A y)
  *   out[4] value xbar^T A ybar
- * Best responses use a bottom-up max-sweep over each treeplex.  Waits for
- * the stream.  out must hold 5 doubles.                                    */
-int cfr_exploitability(cfr_solver *s, int kind, double *out);
+ * len < 4 is CFR_EINVAL.  Exploitability is the metric of the paper's
+ * Experiments section, which does not define it; it is read here as half
+ * the NashConv of the profile.  Best responses use the bottom-up pass of
+ * Algorithm 2 with the maximum over actions in place of the strategy-
+ * weighted sum (best response is named as future work in the paper's
+ * conclusions).  Waits for the stream.                                     */
+int cfr_exploitability(cfr_solver *s, int kind, double *out, int64_t len);
 
 /* Iterations completed so far (host counter; the device holds its own).   */
 int cfr_iteration(cfr_solver *s, int64_t *t);
@@ -314,7 +327,7 @@ int cfr_destroy(cfr_solver *s);
 
 /* ---- batches of games ----------------------------------------------------
  * Many independent games solved together (the repeated-game and research
- * use cases of Section 6): every launch of an iteration covers all games
+ * use cases of Sections 5 and 6): every launch of an iteration covers all games
  * that are still iterating, and one iteration of the whole batch is one
  * captured HIP graph, so the launch count per iteration does not grow with
  * the number of games.  Each game has its own regret minimiser, iteration
@@ -459,7 +472,8 @@ int cfr_batch_status(cfr_batch *b, int64_t id, cfr_game_status *out);
  * evaluation also becomes the game's last evaluation).                    */
 int cfr_batch_strategy(cfr_batch *b, int64_t id, int player, int kind, double *out,
                        int64_t len);
-int cfr_batch_exploitability(cfr_batch *b, int64_t id, int kind, double *out);
+int cfr_batch_exploitability(cfr_batch *b, int64_t id, int kind, double *out,
+                             int64_t len);
 
 /* Frees a game's slot and ranges.                                         */
 int cfr_batch_remove(cfr_batch *b, int64_t id);

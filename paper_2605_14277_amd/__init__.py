@@ -100,7 +100,7 @@ _lib.cfr_create_static.argtypes = [_P(cfr_game_desc), _P(cfr_options), _P(C.c_vo
 _lib.cfr_step.argtypes = [C.c_void_p, C.c_int64, C.c_int, C.c_int]
 _lib.cfr_strategy.argtypes = [C.c_void_p, C.c_int, C.c_int, _P(C.c_double), C.c_int64]
 _lib.cfr_regrets.argtypes = [C.c_void_p, C.c_int, _P(C.c_double), C.c_int64]
-_lib.cfr_exploitability.argtypes = [C.c_void_p, C.c_int, _P(C.c_double)]
+_lib.cfr_exploitability.argtypes = [C.c_void_p, C.c_int, _P(C.c_double), C.c_int64]
 _lib.cfr_iteration.argtypes = [C.c_void_p, _P(C.c_int64)]
 _lib.cfr_kernel_timing.argtypes = [C.c_void_p, C.c_int]
 _lib.cfr_kernel_stats.argtypes = [C.c_void_p, C.c_int, _P(C.c_int64), _P(C.c_double),
@@ -124,7 +124,8 @@ _lib.cfr_batch_run.argtypes = [C.c_void_p, C.c_int64, _P(C.c_int64)]
 _lib.cfr_batch_status.argtypes = [C.c_void_p, C.c_int64, _P(cfr_game_status)]
 _lib.cfr_batch_strategy.argtypes = [C.c_void_p, C.c_int64, C.c_int, C.c_int, _P(C.c_double),
                                     C.c_int64]
-_lib.cfr_batch_exploitability.argtypes = [C.c_void_p, C.c_int64, C.c_int, _P(C.c_double)]
+_lib.cfr_batch_exploitability.argtypes = [C.c_void_p, C.c_int64, C.c_int, _P(C.c_double),
+                                            C.c_int64]
 _lib.cfr_batch_remove.argtypes = [C.c_void_p, C.c_int64]
 _lib.cfr_batch_get_tiling.argtypes = [C.c_void_p, _P(cfr_spmv_tiling)]
 _lib.cfr_batch_set_tiling.argtypes = [C.c_void_p, _P(cfr_spmv_tiling)]
@@ -266,7 +267,7 @@ def cfr_regrets(h, player: int, n_seq: int) -> np.ndarray:
 
 def cfr_exploitability(h, kind: int) -> np.ndarray:
     out = np.empty(5)
-    _check(_lib.cfr_exploitability(h, kind, _dptr(out)), "cfr_exploitability")
+    _check(_lib.cfr_exploitability(h, kind, _dptr(out), 5), "cfr_exploitability")
     return out
 
 
@@ -408,7 +409,7 @@ def cfr_batch_strategy(h, gid: int, player: int, kind: int, n_seq: int) -> np.nd
 
 def cfr_batch_exploitability(h, gid: int, kind: int) -> np.ndarray:
     out = np.empty(5)
-    _check(_lib.cfr_batch_exploitability(h, int(gid), kind, _dptr(out)),
+    _check(_lib.cfr_batch_exploitability(h, int(gid), kind, _dptr(out), 5),
            "cfr_batch_exploitability")
     return out
 

@@ -1,8 +1,8 @@
 """Front end: a two-player zero-sum extensive-form game -> sequence-form arrays.
 
 The paper's implementation takes its games through a game-state interface
-(Section 3.6: the OpenSpiel-compatible entry point).  This module walks any
-object with that kind of state interface and emits what ``cfr_create`` and
+(the OpenSpiel-compatible entry point of Sections 2.2 and 5).  This module
+walks any object with that kind of state interface and emits what ``cfr_create`` and
 ``cfr_batch_add`` take: each player's treeplex (decision points with their
 parent sequences and contiguous action ranges) and the payoff matrix A of
 player 1 with chance folded in (Section 2.1: u1 = A y, u2 = -A^T x), as CSR

@@ -646,17 +646,18 @@ int cfr_regrets(cfr_solver *s, int player, double *out, int64_t len)
     }
 }
 
-int cfr_exploitability(cfr_solver *s, int kind, double *out)
+int cfr_exploitability(cfr_solver *s, int kind, double *out, int64_t len)
 {
     if (!s) return fail(CFR_EINVAL, "null solver");
     if (s->eng.failed) return fail(CFR_ESTATE, "solver is in an error state");
     if (!out) return fail(CFR_EINVAL, "null output");
+    if (len < 4) return fail(CFR_EINVAL, "the output holds fewer than 4 values");
     if (kind != CFR_CURRENT && kind != CFR_AVERAGE) return fail(CFR_EINVAL, "unknown kind");
     try {
         DeviceGuard guard(s->eng.device);
         int rc = s->eng.evaluate({0}, kind);
         if (rc) return rc;
-        for (int i = 0; i < 5; ++i) out[i] = s->eng.slots[0].last[i];
+        for (int64_t i = 0; i < std::min<int64_t>(len, 5); ++i) out[i] = s->eng.slots[0].last[i];
         return CFR_OK;
     } catch (const std::exception &ex) {
         return fail(CFR_ENOMEM, std::string("host allocation failed: ") + ex.what());
@@ -1194,9 +1195,10 @@ int cfr_batch_strategy(cfr_batch *b, int64_t id, int player, int kind, double *o
     }
 }
 
-int cfr_batch_exploitability(cfr_batch *b, int64_t id, int kind, double *out)
+int cfr_batch_exploitability(cfr_batch *b, int64_t id, int kind, double *out, int64_t len)
 {
     if (!b || !out) return fail(CFR_EINVAL, "null argument");
+    if (len < 4) return fail(CFR_EINVAL, "the output holds fewer than 4 values");
     if (b->eng.failed) return fail(CFR_ESTATE, "batch is in an error state");
     if (kind != CFR_CURRENT && kind != CFR_AVERAGE) return fail(CFR_EINVAL, "unknown kind");
     const int k = b->find(id);
@@ -1205,7 +1207,8 @@ int cfr_batch_exploitability(cfr_batch *b, int64_t id, int kind, double *out)
         DeviceGuard guard(b->eng.device);
         int rc = b->eng.evaluate({k}, kind);
         if (rc) return rc;
-        for (int i = 0; i < 5; ++i) out[i] = b->eng.slots[(size_t)k].last[i];
+        for (int64_t i = 0; i < std::min<int64_t>(len, 5); ++i)
+            out[i] = b->eng.slots[(size_t)k].last[i];
         return CFR_OK;
     } catch (const std::exception &ex) {
         return fail(CFR_ENOMEM, std::string("host allocation failed: ") + ex.what());

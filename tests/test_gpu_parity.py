@@ -492,6 +492,22 @@ def test_state_errors(cfr, games):
     assert s.iteration == 5
 
 
+def test_exploitability_output_length(cfr, games):
+    """cfr_exploitability writes the first min(len, 5) values and refuses
+    len < 4: a caller with room for the four of the contract gets exactly
+    those, and the value past them is untouched."""
+    import ctypes as C
+    s = cfr.Solver(games["cfg1"])
+    s.step(7, "cfr+", "alternating")
+    full = cfr.cfr_exploitability(s.h, 1)
+    out = np.full(5, -7.0)
+    ptr = out.ctypes.data_as(C.POINTER(C.c_double))
+    assert cfr._lib.cfr_exploitability(s.h, 1, ptr, 4) == cfr.CFR_OK
+    assert np.array_equal(out[:4], full[:4]) and out[4] == -7.0
+    assert cfr._lib.cfr_exploitability(s.h, 1, ptr, 3) == cfr.CFR_EINVAL
+    s.close()
+
+
 def test_workspace_too_small(cfr, games):
     import ctypes as C
 
