@@ -1274,6 +1274,25 @@ int Engine::add(const HostGame &hg, const GameImage &img, const GameParams &gp, 
             d.n_roots = pl.n_roots;
             d.top_fast = 1;
             for (int32_t lv = 0; lv < pl.top_levels; ++lv) d.top_fast &= pl.lvl_kind[lv] != 0;
+            // the shallow levels in one block: from the root down while they
+            // are small and on the fast path (two levels at least, or nothing
+            // is gained), the deepest of them reading value slots unless it
+            // is the game's last level.  The fast path's unused lanes read
+            // child_idx[0], the game's first decision point, which the block
+            // holds in LDS only when the game starts the index space.
+            d.shallow = ShallowPlan();
+            if (pl.top_levels == 0 && up_pass == CFR_UP_DEFAULT && I == 0) {
+                int32_t T = 0;
+                while (T < pl.n_levels && T < kShallowLevels && pl.lvl_kind[T] != 0 &&
+                       pl.lvl_inf[T + 1] <= kShallowMax)
+                    ++T;
+                if (T >= 2 && T < pl.n_levels && !(s.lvl_slots[p][T - 1] & kSlotsRead)) T = 0;
+                if (T >= 2) {
+                    d.shallow.levels = T;
+                    for (int32_t lv = 0; lv <= T; ++lv) d.shallow.lo[lv] = I + pl.lvl_inf[lv];
+                    for (int32_t lv = 0; lv < T; ++lv) d.shallow.kind[lv] = pl.lvl_kind[lv];
+                }
+            }
         }
     }
     // payoff matrix: row pointers at the row player's sequences, indices
@@ -1659,7 +1678,8 @@ hipError_t Engine::sweeps(const Tables &T, int p, double usign, hipStream_t s)
     const int maxL = (int)T.up_l[p].size();
     hipError_t e;
     const bool top = lone && d.top_levels > 0;
-    const int low = top ? d.top_levels : 0;
+    const int shallow = lone && !top ? d.shallow.levels : 0;
+    const int low = top ? d.top_levels : shallow;
     // ObserveUtility, deepest level first (level 0's launch also does its
     // top-down step); with CFR_UP_PAIRS a lone game runs pairs of adjacent
     // levels that fit the two-level launch as one launch each
@@ -1688,6 +1708,11 @@ hipError_t Engine::sweeps(const Tables &T, int p, double usign, hipStream_t s)
     if (top) {
         // the shallow levels of the lone game, both directions, one launch
         if ((e = launch_top(prec, slots[0].gp.variant, d, usign, 1, sc, s)) != hipSuccess) return e;
+    } else if (shallow > 0) {
+        // the shallow levels' bottom-up pass in one block (level 0 does its
+        // top-down step there too)
+        if ((e = launch_shallow(prec, slots[0].gp.variant, d, usign, sc, s)) != hipSuccess)
+            return e;
     }
     if (!top && down_pass == CFR_DOWN_DEFAULT && T.dall_depth[p] <= kDownAllMaxDepth)
         return launch_down_all(prec, T.dall_depth[p], T.dall[p], T.n_dall[p], &T.dall_direct[p], d,

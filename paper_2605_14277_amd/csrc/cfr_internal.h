@@ -62,6 +62,22 @@ struct SlotRef {
 };
 
 // Device arrays of one player, covering every slot (global indices).
+// The shallow levels 0 .. levels-1 of a lone game's bottom-up pass in one
+// block (k_shallow): each level's values stay in LDS for the level above,
+// and only the deepest of them reads its children's values from global
+// memory (their value slots).  Levels are taken from the root down while
+// all of them together hold at most kShallowMax decision points (one per
+// thread: a single block passing several times over a level was measured
+// slower than a launch per level), every one on the fast path.
+constexpr int kShallowThreads = 1024;
+constexpr int kShallowMax = kShallowThreads;
+constexpr int kShallowLevels = 8;
+struct ShallowPlan {
+    int32_t levels = 0;                // 0: not used
+    int32_t lo[kShallowLevels + 1] = {};  // global first decision point of each level, and the end
+    uint8_t kind[kShallowLevels] = {};    // 1 fast, 2 fast without decision points below
+};
+
 struct DevPlayer {
     int32_t *inf_first = nullptr;  // [decision points + sentinel] first sequence of each
     int32_t *seq_par = nullptr;    // [sequences] parent sequence of each sequence's decision point
@@ -94,6 +110,7 @@ struct DevPlayer {
     int32_t *top_off = nullptr;    // [top_levels*(n_roots+1)]
     int32_t *top_list = nullptr;   // decision points grouped by level, then root
     int top_fast = 0;              // every level in k_top is a fast level
+    ShallowPlan shallow;           // shallow levels of a lone game in one block (k_shallow)
 };
 
 // Kernel launchers (cfr_kernels.hip).  All enqueue on `st` and return the
@@ -143,6 +160,10 @@ hipError_t launch_down_all(int prec, int max_depth, const RangeBlock *tab, int32
 // 0..top_levels-1 (with averaging when `average`) of the game in slot 0.
 hipError_t launch_top(int prec, int variant, const DevPlayer &p, double usign, int average,
                       const Scalars *sc, hipStream_t st);
+// ObserveUtility of the shallow levels p.shallow of a lone game (slot 0),
+// deepest first, one block; level 0 also does its top-down step.
+hipError_t launch_shallow(int prec, int variant, const DevPlayer &p, double usign,
+                          const Scalars *sc, hipStream_t st);
 // xbar = s / W per game (x where W = 0), 1 at each game's empty sequence.
 hipError_t launch_normalize(int prec, const RangeBlock *tab, int32_t n_tab, const DevPlayer &p,
                             const Scalars *sc, hipStream_t st);

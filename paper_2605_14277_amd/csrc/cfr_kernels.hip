@@ -1100,6 +1100,59 @@ __global__ __launch_bounds__(kTopThreads) void k_top(
     }
 }
 
+// The shallow levels of a lone game in one block, deepest first: the values
+// of each level's decision points stay in LDS, where the level above reads
+// them through its child lists, so consecutive levels are separated by a
+// block barrier instead of a kernel boundary and a round trip through
+// global memory.  The deepest of these levels reads its children's values
+// (written by the launch of the level below) from their value slots, as its
+// own launch would.  Every decision point
+// runs the fast path of ObserveUtility with the same operations in the same
+// order as in a launch per level, so every result is the same bit for bit.
+// Only LDS is shared between threads here (the global stores are each
+// thread's own decision point's regrets and strategies).
+template <int P, int VAR>
+__global__ __launch_bounds__(kShallowThreads) void k_shallow(
+    ShallowPlan sp, const int32_t *__restrict__ inf_first, const int32_t *__restrict__ child_ptr,
+    const int32_t *__restrict__ child_idx, const typename Types<P>::V *__restrict__ g,
+    typename Types<P>::C usign, typename Types<P>::C *__restrict__ vinf,
+    typename Types<P>::V *__restrict__ b, typename Types<P>::R *__restrict__ r,
+    typename Types<P>::R *__restrict__ m, const Scalars *__restrict__ sc,
+    const int32_t *__restrict__ seq_par, typename Types<P>::V *__restrict__ x,
+    typename Types<P>::R *__restrict__ s, Kids<P> kd)
+{
+    using R = typename Types<P>::R;
+    using C = typename Types<P>::C;
+    __shared__ C lv[kShallowMax];
+    const int32_t base = sp.lo[0];
+    C *const lvb = lv - base;  // lvb[j]: value of shallow decision point j
+    C dpos = 1, dneg = 1;
+    if (VAR == CFR_DCFR) {
+        dpos = (C)sc->dpos;
+        dneg = (C)sc->dneg;
+    }
+    const R w = (R)sc->w;
+    for (int l = sp.levels - 1; l >= 0; --l) {
+        const bool deepest = l == sp.levels - 1;
+        for (int32_t j = sp.lo[l] + (int32_t)threadIdx.x; j < sp.lo[l + 1]; j += kShallowThreads) {
+            C V;
+            if (sp.kind[l] == 2)
+                V = up_infoset_fast<P, VAR, 0, 0, false>(j, inf_first, child_ptr, child_idx, g, usign,
+                                                         vinf, b, r, m, dpos, dneg, kd);
+            else if (!deepest)
+                V = up_infoset_fast<P, VAR, kFastKids, 0, false>(j, inf_first, child_ptr, child_idx,
+                                                                 g, usign, lvb, b, r, m, dpos,
+                                                                 dneg, kd);
+            else
+                V = up_infoset_fast<P, VAR, kFastKids, kSlotsRead, false>(
+                    j, inf_first, child_ptr, child_idx, g, usign, vinf, b, r, m, dpos, dneg, kd);
+            lvb[j] = V;
+            if (l == 0) down_infoset<P>(j, inf_first, seq_par, b, x, s, w, 1, true);
+        }
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------------------
 // NextStrategy top-down pass for one level, fused with averaging
 // ---------------------------------------------------------------------------
@@ -1607,6 +1660,33 @@ hipError_t top_t(const DevPlayer &p, double usign, int average, const Scalars *s
     return hipGetLastError();
 }
 
+template <int P, int VAR>
+hipError_t shallow_t(const DevPlayer &p, double usign, const Scalars *sc, hipStream_t st)
+{
+    using T = Types<P>;
+    if (p.shallow.levels <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_shallow<P, VAR>), dim3(1), dim3(kShallowThreads), 0, st, p.shallow,
+                       p.inf_first, p.child_ptr, p.child_idx, (const typename T::V *)p.g,
+                       (typename T::C)usign, (typename T::C *)p.vinf, (typename T::V *)p.b,
+                       (typename T::R *)p.r, (typename T::R *)p.m, sc, p.seq_par,
+                       (typename T::V *)p.x, (typename T::R *)p.s, kids<P>(p));
+    return hipGetLastError();
+}
+
+template <int P>
+hipError_t shallow_dispatch(int variant, const DevPlayer &p, double usign, const Scalars *sc,
+                            hipStream_t st)
+{
+    switch (variant) {
+    case CFR_VANILLA: return shallow_t<P, CFR_VANILLA>(p, usign, sc, st);
+    case CFR_PLUS: return shallow_t<P, CFR_PLUS>(p, usign, sc, st);
+    case CFR_DCFR: return shallow_t<P, CFR_DCFR>(p, usign, sc, st);
+    case CFR_PCFR_PLUS: return shallow_t<P, CFR_PCFR_PLUS>(p, usign, sc, st);
+    case CFR_PCFR: return shallow_t<P, CFR_PCFR>(p, usign, sc, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 template <int P>
 hipError_t top_dispatch(int variant, const DevPlayer &p, double usign, int average,
                         const Scalars *sc, hipStream_t st)
@@ -1742,6 +1822,12 @@ hipError_t launch_top(int prec, int variant, const DevPlayer &p, double usign, i
                       const Scalars *sc, hipStream_t st)
 {
     CFR_DISPATCH(prec, top_dispatch<P>(variant, p, usign, average, sc, st));
+}
+
+hipError_t launch_shallow(int prec, int variant, const DevPlayer &p, double usign,
+                          const Scalars *sc, hipStream_t st)
+{
+    CFR_DISPATCH(prec, shallow_dispatch<P>(variant, p, usign, sc, st));
 }
 
 hipError_t launch_down(int prec, const RangeBlock *tab, int32_t n_tab, const DevPlayer &p,

@@ -679,3 +679,48 @@ def test_two_level_launches_fp32_modes(cfr, precision):
         assert np.array_equal(a.regrets(p), b.regrets(p))
     a.close()
     b.close()
+
+
+# --------------------------------------------------------------------------
+# Shallow levels in one block
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("mode", MODES)
+def test_shallow_block_equals_level_by_level(cfr, oracle_mod, variant, mode):
+    """By default a lone game runs its shallow levels' bottom-up pass in one
+    block, the values passed between levels in LDS (the medium game: the top
+    three levels of each player, 260 and 559 decision points; the deepest of
+    them reads value slots).  In FP64 every iterate equals the
+    one-launch-per-level pass bit for bit, and both match the oracle."""
+    g = gg.cfg2()
+    fused = cfr.Solver(g, precision="fp64")
+    plain = cfr.Solver(g, precision="fp64", up_pass="levels")
+    orc = oracle_mod.Oracle(g, parallel=True)
+    for n in (1, 19):
+        fused.step(n, variant, mode)
+        plain.step(n, variant, mode)
+        orc.step(n, variant, mode)
+        for p in range(2):
+            for kind in ("current", "average"):
+                assert np.array_equal(fused.strategy(p, kind), plain.strategy(p, kind)), (p, kind)
+            assert np.array_equal(fused.regrets(p), plain.regrets(p)), p
+    compare_fp64(fused, orc, what=f"cfg2 shallow block {variant}/{mode}")
+    for s in (fused, plain, orc):
+        s.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_acc64"])
+def test_shallow_block_large_game(cfr, large_game, precision):
+    """The large game (player 1's two shallow levels, 448 decision points,
+    the deeper one reading value slots) in every precision: bit for bit
+    equal to one launch per level over a few DCFR iterations."""
+    a = cfr.Solver(large_game, precision=precision)
+    b = cfr.Solver(large_game, precision=precision, up_pass="levels")
+    for s in (a, b):
+        s.step(6, "dcfr", "alternating")
+    for p in range(2):
+        assert np.array_equal(a.strategy(p, "average"), b.strategy(p, "average"))
+        assert np.array_equal(a.regrets(p), b.regrets(p))
+    a.close()
+    b.close()
