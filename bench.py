@@ -537,8 +537,9 @@ def batch_record(args, torch) -> dict:
 
 def serve_record(args, torch, rates) -> dict:
     """Requests arriving as Poisson streams, served with continuous batching
-    (games join the batch at check boundaries while others iterate), against
-    one-at-a-time FIFO service of the same requests with the same solver."""
+    (games join a batch at check boundaries while others iterate; small games
+    in a batch of their own on another stream), against one-at-a-time FIFO
+    service of the same requests with the same solver."""
     import numpy as np
     from concurrent.futures import ThreadPoolExecutor
 
@@ -566,19 +567,38 @@ def serve_record(args, torch, rates) -> dict:
     var = rng.choice(["cfr+", "dcfr"], size=n)
     gaps = rng.exponential(1.0, size=n)
     budget = int(args.budget_gb * 1e9)
-    mix = np.sum([p.units for p in prepared], axis=0) / args.pool
     tiling = parse_tiling(args.serve_tiling)
     quads = 3 in tiling["vec"]
     # with quads, part of the budget goes to the quad stores (about 0.3 quads
     # per nonzero for the games of this distribution, per product)
-    ws_budget = int(budget * (0.55 if quads else 1.0))
-    seq, inf, nz = serve.capacities_for_bytes(ws_budget, mix, args.max_games, precision)
+    qshare = 0.55 if quads else 1.0
     vb = 4
+    # two lanes: games of at most small_nnz nonzeros in a batch of their own
+    # (a share of the budget sized by the mix of such games), the rest in
+    # the main batch
+    small_units = [p.units for p in prepared if p.units[4] <= args.small_nnz]
+    small = None
+    main_budget = budget
+    if args.serve_lanes == 2 and small_units:
+        sb = int(budget * args.small_share)
+        smix = np.sum(small_units, axis=0) / len(small_units)
+        s_seq, s_inf, s_nz = serve.capacities_for_bytes(int(sb * qshare), smix, args.max_games,
+                                                        precision)
+        small = {"seq_capacity": s_seq, "inf_capacity": s_inf, "nnz_capacity": s_nz,
+                 "max_games": args.max_games, "nnz_limit": args.small_nnz,
+                 "quad_capacity": int(0.3 * s_nz) if quads else 0}
+        main_budget = budget - sb
+        log(f"[serve] small-game lane (at most {args.small_nnz:.0e} nonzeros, "
+            f"{len(small_units)} of the {args.pool} pool games): {sb / 1e9:.0f} GB -> "
+            f"capacity {s_nz:.3e} nonzeros, {args.max_games} slots, a stream of its own")
+    mix = np.sum([p.units for p in prepared], axis=0) / args.pool
+    seq, inf, nz = serve.capacities_for_bytes(int(main_budget * qshare), mix, args.max_games,
+                                              precision)
     qcap = int(0.3 * nz) if quads else 0
-    log(f"[serve] device budget {budget / 1e9:.0f} GB -> capacity {nz:.3e} nonzeros, "
-        f"{args.max_games} slots" + (f", {qcap:.3e} quads per product "
-                                     f"({2 * qcap * (4 + 4 * vb) / 1e9:.0f} GB)" if quads else "")
-        + f"; product tiling {tiling}")
+    log(f"[serve] device budget {budget / 1e9:.0f} GB; main lane {main_budget / 1e9:.0f} GB -> "
+        f"capacity {nz:.3e} nonzeros, {args.max_games} slots"
+        + (f", {qcap:.3e} quads per product ({2 * qcap * (4 + 4 * vb) / 1e9:.0f} GB)"
+           if quads else "") + f"; product tiling {tiling}")
     if quads:
         with ThreadPoolExecutor(max_workers=args.workers) as ex:
             list(ex.map(lambda p: p.prepare_quads(tiling["perm"]), prepared))
@@ -602,9 +622,9 @@ def serve_record(args, torch, rates) -> dict:
                  "target": float(rel[k] * ranges[which[k]]), "max_iterations": max_it}
                 for k in range(n)]
         srv = serve.Server(seq, inf, nz, max_games=args.max_games, precision=precision,
-                           check_every=K, tiling=tiling, quad_capacity=qcap)
+                           check_every=K, tiling=tiling, quad_capacity=qcap, small=small)
         out = srv.serve(reqs, prepared=prepared)
-        host = srv.batch.host_stats()
+        host = srv.host_stats()
         srv.close()
         done = [o for o in out if o["state"] == "done"]
         lat = np.array([o["latency"] for o in done])
@@ -632,8 +652,11 @@ def serve_record(args, torch, rates) -> dict:
     return {"workload": f"{n} requests per rate, Poisson arrivals, games from a pool of "
                         f"{args.pool} of the batch distribution, CFR+ or DCFR, target 1e-2 or "
                         f"1e-3 of the payoff range or {max_it} iterations, checks every {K}, "
-                        f"{args.budget_gb:g} GB device budget, {args.max_games} slots",
-            "tiling": tiling, "rates": per_rate,
+                        f"{args.budget_gb:g} GB device budget, {args.max_games} slots"
+                        + (f" per lane; games of at most {args.small_nnz:.0e} nonzeros in a "
+                           f"lane of their own ({args.small_share:g} of the budget)"
+                           if small else ""),
+            "lanes": 2 if small else 1, "tiling": tiling, "rates": per_rate,
             "pool": {"games": args.pool, "nnz_median": float(np.median(nnz)),
                      "nnz_max": int(nnz.max()), "generate_s": gen_s, "prepare_s": prep_s}}
 
@@ -761,6 +784,12 @@ def main():
     ap.add_argument("--requests", type=int, default=128, help="serve: requests per rate")
     ap.add_argument("--pool", type=int, default=64, help="serve: distinct games")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="serve: device budget")
+    ap.add_argument("--serve-lanes", type=int, default=2, choices=[1, 2],
+                    help="serve: 2 = games of at most --small-nnz nonzeros in a batch of their "
+                         "own on a stream of their own")
+    ap.add_argument("--small-nnz", type=float, default=5e6, help="serve: small-game lane limit")
+    ap.add_argument("--small-share", type=float, default=0.2,
+                    help="serve: share of the device budget for the small-game lane")
     ap.add_argument("--max-games", type=int, default=256, help="serve: game slots")
     ap.add_argument("--plain-stride", type=int, default=16,
                     help="batch: also solve every k-th game alone with vanilla CFR (0: skip)")

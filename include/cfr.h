@@ -466,6 +466,20 @@ int cfr_prepared_destroy(cfr_prepared *p);
  * of games still iterating or waiting to start.                          */
 int cfr_batch_run(cfr_batch *b, int64_t n, int64_t *n_active);
 
+/* One check period of cfr_batch_run without waiting, so that the host (or
+ * another batch on another stream) works while the device iterates:
+ * cfr_batch_run_begin joins the games due to start, enqueues the
+ * iterations up to the next check and that check's evaluation on the
+ * batch's stream (results copied to page-locked memory) and returns;
+ * cfr_batch_run_end waits for them, applies the check exactly as
+ * cfr_batch_run does (same iterates, same stopping) and writes the number
+ * of games still iterating or waiting to *n_active (may be NULL).  Between
+ * the two calls only cfr_batch_status may be called on the batch (other
+ * calls return CFR_ESTATE); run_end without a begun period does nothing.
+ * CFR_EUNSUPPORTED if the page-locked staging could not be allocated.   */
+int cfr_batch_run_begin(cfr_batch *b);
+int cfr_batch_run_end(cfr_batch *b, int64_t *n_active);
+
 int cfr_batch_status(cfr_batch *b, int64_t id, cfr_game_status *out);
 
 /* As cfr_strategy / cfr_exploitability for one game of the batch (the

@@ -121,6 +121,8 @@ _lib.cfr_batch_index_limits.argtypes = [_P(cfr_batch_options), _P(C.c_int)]
 _lib.cfr_batch_create.argtypes = [_P(cfr_batch_options), _P(C.c_void_p)]
 _lib.cfr_batch_add.argtypes = [C.c_void_p, _P(cfr_game_desc), _P(cfr_game_params), _P(C.c_int64)]
 _lib.cfr_batch_run.argtypes = [C.c_void_p, C.c_int64, _P(C.c_int64)]
+_lib.cfr_batch_run_begin.argtypes = [C.c_void_p]
+_lib.cfr_batch_run_end.argtypes = [C.c_void_p, _P(C.c_int64)]
 _lib.cfr_batch_status.argtypes = [C.c_void_p, C.c_int64, _P(cfr_game_status)]
 _lib.cfr_batch_strategy.argtypes = [C.c_void_p, C.c_int64, C.c_int, C.c_int, _P(C.c_double),
                                     C.c_int64]
@@ -148,7 +150,8 @@ for _f in ("cfr_options_default", "cfr_validate", "cfr_workspace_size", "cfr_cre
            "cfr_state_size", "cfr_get_state", "cfr_set_state",
            "cfr_tune", "cfr_destroy", "cfr_batch_options_default", "cfr_game_params_default",
            "cfr_batch_game_size", "cfr_batch_workspace_size", "cfr_batch_create",
-           "cfr_batch_add", "cfr_batch_run", "cfr_batch_status", "cfr_batch_strategy",
+           "cfr_batch_add", "cfr_batch_run", "cfr_batch_run_begin", "cfr_batch_run_end",
+           "cfr_batch_status", "cfr_batch_strategy",
            "cfr_batch_exploitability", "cfr_batch_remove", "cfr_batch_get_tiling",
            "cfr_batch_set_tiling", "cfr_batch_tune", "cfr_batch_kernel_timing",
            "cfr_batch_kernel_stats", "cfr_batch_destroy", "cfr_prepare", "cfr_prepared_size",
@@ -389,6 +392,16 @@ def cfr_batch_add(h, game_arrays: GameArrays, params: cfr_game_params) -> int:
 def cfr_batch_run(h, n: int) -> int:
     k = C.c_int64(0)
     _check(_lib.cfr_batch_run(h, int(n), C.byref(k)), "cfr_batch_run")
+    return int(k.value)
+
+
+def cfr_batch_run_begin(h):
+    _check(_lib.cfr_batch_run_begin(h), "cfr_batch_run_begin")
+
+
+def cfr_batch_run_end(h) -> int:
+    k = C.c_int64(0)
+    _check(_lib.cfr_batch_run_end(h, C.byref(k)), "cfr_batch_run_end")
     return int(k.value)
 
 
@@ -648,6 +661,14 @@ class Batch:
 
     def run(self, n: int) -> int:
         return cfr_batch_run(self.h, n)
+
+    def run_begin(self):
+        """Enqueues one check period and returns (cfr_batch_run_begin)."""
+        cfr_batch_run_begin(self.h)
+
+    def run_end(self) -> int:
+        """Waits for the check period begun and applies its check."""
+        return cfr_batch_run_end(self.h)
 
     def status(self, gid: int) -> dict:
         return cfr_batch_status(self.h, gid)

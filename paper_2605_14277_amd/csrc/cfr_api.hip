@@ -1013,6 +1013,8 @@ int cfr_batch_create(const cfr_batch_options *opt, cfr_batch **out)
 int cfr_batch_add(cfr_batch *b, const cfr_game_desc *game, const cfr_game_params *gp, int64_t *id)
 {
     if (!b || !id) return fail(CFR_EINVAL, "null argument");
+    if (b->eng.pending)
+        return fail(CFR_ESTATE, "a check period begun by cfr_batch_run_begin has not ended");
     if (b->eng.failed) return fail(CFR_ESTATE, "batch is in an error state");
     try {
         int rc = check_game_params(gp);
@@ -1101,6 +1103,8 @@ int cfr_batch_add_prepared(cfr_batch *b, const cfr_prepared *p, const cfr_game_p
                            int64_t *id)
 {
     if (!b || !p || !id) return fail(CFR_EINVAL, "null argument");
+    if (b->eng.pending)
+        return fail(CFR_ESTATE, "a check period begun by cfr_batch_run_begin has not ended");
     if (b->eng.failed) return fail(CFR_ESTATE, "batch is in an error state");
     if (p->precision != b->eng.prec)
         return fail(CFR_EINVAL, "the game was prepared for another precision");
@@ -1159,6 +1163,41 @@ int cfr_batch_run(cfr_batch *b, int64_t n, int64_t *n_active)
     }
 }
 
+static void count_active(const cfr_batch *b, int64_t *n_active)
+{
+    if (!n_active) return;
+    int64_t k = 0;
+    for (const cfr::Slot &s : b->eng.slots) k += s.live && (s.active || s.pending);
+    *n_active = k;
+}
+
+int cfr_batch_run_begin(cfr_batch *b)
+{
+    if (!b) return fail(CFR_EINVAL, "null batch");
+    if (b->eng.failed) return fail(CFR_ESTATE, "batch is in an error state");
+    try {
+        DeviceGuard guard(b->eng.device);
+        return b->eng.run_begin();
+    } catch (const std::exception &ex) {
+        return fail(CFR_ENOMEM, std::string("host allocation failed: ") + ex.what());
+    }
+}
+
+int cfr_batch_run_end(cfr_batch *b, int64_t *n_active)
+{
+    if (!b) return fail(CFR_EINVAL, "null batch");
+    if (b->eng.failed) return fail(CFR_ESTATE, "batch is in an error state");
+    try {
+        DeviceGuard guard(b->eng.device);
+        int rc = b->eng.run_end();
+        if (rc) return rc;
+        count_active(b, n_active);
+        return CFR_OK;
+    } catch (const std::exception &ex) {
+        return fail(CFR_ENOMEM, std::string("host allocation failed: ") + ex.what());
+    }
+}
+
 int cfr_batch_status(cfr_batch *b, int64_t id, cfr_game_status *out)
 {
     if (!b || !out) return fail(CFR_EINVAL, "null argument");
@@ -1176,6 +1215,8 @@ int cfr_batch_status(cfr_batch *b, int64_t id, cfr_game_status *out)
 int cfr_batch_strategy(cfr_batch *b, int64_t id, int player, int kind, double *out, int64_t len)
 {
     if (!b || !out) return fail(CFR_EINVAL, "null argument");
+    if (b->eng.pending)
+        return fail(CFR_ESTATE, "a check period begun by cfr_batch_run_begin has not ended");
     if (b->eng.failed) return fail(CFR_ESTATE, "batch is in an error state");
     const int k = b->find(id);
     if (k < 0) return fail(CFR_EINVAL, "unknown game");
@@ -1198,6 +1239,8 @@ int cfr_batch_strategy(cfr_batch *b, int64_t id, int player, int kind, double *o
 int cfr_batch_exploitability(cfr_batch *b, int64_t id, int kind, double *out, int64_t len)
 {
     if (!b || !out) return fail(CFR_EINVAL, "null argument");
+    if (b->eng.pending)
+        return fail(CFR_ESTATE, "a check period begun by cfr_batch_run_begin has not ended");
     if (len < 4) return fail(CFR_EINVAL, "the output holds fewer than 4 values");
     if (b->eng.failed) return fail(CFR_ESTATE, "batch is in an error state");
     if (kind != CFR_CURRENT && kind != CFR_AVERAGE) return fail(CFR_EINVAL, "unknown kind");
@@ -1218,6 +1261,8 @@ int cfr_batch_exploitability(cfr_batch *b, int64_t id, int kind, double *out, in
 int cfr_batch_remove(cfr_batch *b, int64_t id)
 {
     if (!b) return fail(CFR_EINVAL, "null batch");
+    if (b->eng.pending)
+        return fail(CFR_ESTATE, "a check period begun by cfr_batch_run_begin has not ended");
     const int k = b->find(id);
     if (k < 0) return fail(CFR_EINVAL, "unknown game");
     DeviceGuard guard(b->eng.device);
@@ -1237,6 +1282,8 @@ int cfr_batch_get_tiling(cfr_batch *b, cfr_spmv_tiling *t)
 int cfr_batch_set_tiling(cfr_batch *b, const cfr_spmv_tiling *t)
 {
     if (!b) return fail(CFR_EINVAL, "null batch");
+    if (b->eng.pending)
+        return fail(CFR_ESTATE, "a check period begun by cfr_batch_run_begin has not ended");
     int rc = check_tiling(t);
     if (rc) return rc;
     try {
@@ -1254,6 +1301,8 @@ int cfr_batch_set_tiling(cfr_batch *b, const cfr_spmv_tiling *t)
 int cfr_batch_tune(cfr_batch *b, int reps, cfr_spmv_tiling *chosen)
 {
     if (!b) return fail(CFR_EINVAL, "null batch");
+    if (b->eng.pending)
+        return fail(CFR_ESTATE, "a check period begun by cfr_batch_run_begin has not ended");
     if (b->eng.failed) return fail(CFR_ESTATE, "batch is in an error state");
     try {
         DeviceGuard guard(b->eng.device);
@@ -1266,6 +1315,8 @@ int cfr_batch_tune(cfr_batch *b, int reps, cfr_spmv_tiling *chosen)
 int cfr_batch_kernel_timing(cfr_batch *b, int enable)
 {
     if (!b) return fail(CFR_EINVAL, "null batch");
+    if (b->eng.pending)
+        return fail(CFR_ESTATE, "a check period begun by cfr_batch_run_begin has not ended");
     DeviceGuard guard(b->eng.device);
     return kernel_timing(b->eng, enable);
 }
@@ -1274,6 +1325,8 @@ int cfr_batch_kernel_stats(cfr_batch *b, int kernel, int64_t *launches, double *
                            double *bytes_per_launch)
 {
     if (!b || kernel < 0 || kernel > 1) return fail(CFR_EINVAL, "bad batch or kernel");
+    if (b->eng.pending)
+        return fail(CFR_ESTATE, "a check period begun by cfr_batch_run_begin has not ended");
     DeviceGuard guard(b->eng.device);
     return kernel_stats(b->eng, kernel, launches, total_ms, bytes_per_launch);
 }

@@ -286,6 +286,13 @@ struct Engine {
     int64_t check_every = 0;  // 0: no checks (single-game solver)
     int64_t phase = 0;        // iterations since the last check
     int64_t checks = 0;       // checks done so far
+    // an asynchronous check period (run_begin .. run_end): the games of the
+    // check it enqueued, the page-locked copy of every slot's scalars the
+    // check reads back, and the event that marks the copy's completion
+    bool pending = false;
+    std::vector<int> pending_set;
+    Scalars *eval_stage = nullptr;
+    hipEvent_t eval_ev = nullptr;
 
     // host-side time and calls per activity (kHost* below), for reports
     enum {
@@ -360,9 +367,22 @@ struct Engine {
     // Evaluates the average (or current) profile of the games in `set`;
     // results land in each slot's `last`.
     int evaluate(const std::vector<int> &set, int kind);
+    // The two halves of evaluate: the launches and the copy of every slot's
+    // scalars to `out` (host memory of slots.size() records) on the stream;
+    // then, once that copy has completed, the set's results from `out`.
+    int evaluate_launch(const std::vector<int> &set, int kind, Scalars *out);
+    void evaluate_collect(const std::vector<int> &set, const Scalars *out);
+    // After a check of `set`: games that met their stopping rule stop.
+    void apply_check(const std::vector<int> &set);
     // n iterations with checks every check_every iterations; games that meet
     // their stopping rule at a check stop iterating.
     int run(int64_t n);
+    // One check period without waiting: run_begin enqueues the iterations up
+    // to the next check and that check's evaluation (with its results copied
+    // to page-locked memory) and returns; run_end waits for them and applies
+    // the check.  Nothing else may change the engine in between.
+    int run_begin();
+    int run_end();
     // Times `reps` launches of one product with the current tiling (ms each).
     int time_spmv(int which, int reps, double *ms);
 

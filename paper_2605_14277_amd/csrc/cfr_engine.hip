@@ -854,6 +854,20 @@ int Engine::init(const Capacity &c, int precision, int dev, hipStream_t stream, 
         else
             (void)hipGetLastError();
     }
+    {
+        // results of asynchronous checks (run_begin / run_end)
+        void *p = nullptr;
+        if (hipHostMalloc(&p, sizeof(Scalars) * (size_t)c.slots, hipHostMallocDefault) ==
+                hipSuccess &&
+            p)
+            eval_stage = (Scalars *)p;
+        else
+            (void)hipGetLastError();
+        if (hipEventCreateWithFlags(&eval_ev, hipEventDisableTiming) != hipSuccess) {
+            eval_ev = nullptr;
+            (void)hipGetLastError();
+        }
+    }
     return init_arenas(c);
 }
 
@@ -878,6 +892,7 @@ void Engine::drop_graph()
 
 void Engine::release()
 {
+    if (pending && eval_ev) (void)hipEventSynchronize(eval_ev);
     for (int k = 0; k < 2; ++k) {
         for (auto &pr : events[k]) {
             (void)hipEventDestroy(pr.first);
@@ -893,6 +908,11 @@ void Engine::release()
     up_st = nullptr;
     if (scal_stage) (void)hipHostFree(scal_stage);
     scal_stage = nullptr;
+    if (eval_ev) (void)hipEventDestroy(eval_ev);
+    eval_ev = nullptr;
+    if (eval_stage) (void)hipHostFree(eval_stage);
+    eval_stage = nullptr;
+    pending = false;
     if (own_ws && ws) (void)hipFree(ws);
     ws = nullptr;
     for (QuadStore &Q : quad) {
@@ -1793,10 +1813,8 @@ int Engine::iterate(int64_t n)
     return CFR_OK;
 }
 
-int Engine::evaluate(const std::vector<int> &set, int kind)
+int Engine::evaluate_launch(const std::vector<int> &set, int kind, Scalars *out)
 {
-    if (set.empty()) return CFR_OK;
-    HostTimer timer(&host_s[kHostEval], &host_n[kHostEval]);
     const Tables *T = nullptr;
     if (it.valid && set == active_set()) {
         T = &it;
@@ -1836,45 +1854,81 @@ int Engine::evaluate(const std::vector<int> &set, int kind)
     }
     CHECK(launch_dot(prec, T->seq[0], T->n_seq[0], src[0], dp[0].g, partials, T->fin, T->n_fin,
                      sc, 2, st));
-    std::vector<Scalars> h(slots.size());
-    CHECK(hipMemcpyAsync(h.data(), sc, sizeof(Scalars) * h.size(), hipMemcpyDeviceToHost, st));
+    CHECK(hipMemcpyAsync(out, sc, sizeof(Scalars) * slots.size(), hipMemcpyDeviceToHost, st));
 #undef CHECK
-    int rc = sync("evaluation");
-    if (rc) return rc;
+    return CFR_OK;
+}
+
+void Engine::evaluate_collect(const std::vector<int> &set, const Scalars *out)
+{
     reap_uploads(false);
     for (int k : set) {
         Slot &s = slots[(size_t)k];
-        const double br1 = h[(size_t)k].out[0], br2 = h[(size_t)k].out[1];
+        const double br1 = out[(size_t)k].out[0], br2 = out[(size_t)k].out[1];
         s.last[0] = (br1 + br2) / 2.0;
         s.last[1] = br1 + br2;
         s.last[2] = br1;
         s.last[3] = br2;
-        s.last[4] = h[(size_t)k].out[2];
+        s.last[4] = out[(size_t)k].out[2];
         s.last_t = s.t;
     }
+}
+
+int Engine::evaluate(const std::vector<int> &set, int kind)
+{
+    if (set.empty()) return CFR_OK;
+    HostTimer timer(&host_s[kHostEval], &host_n[kHostEval]);
+    std::vector<Scalars> h(slots.size());
+    int rc = evaluate_launch(set, kind, h.data());
+    if (rc) return rc;
+    rc = sync("evaluation");
+    if (rc) return rc;
+    evaluate_collect(set, h.data());
     return CFR_OK;
+}
+
+void Engine::apply_check(const std::vector<int> &set)
+{
+    bool changed = false;
+    for (int k : set) {
+        Slot &s = slots[(size_t)k];
+        const bool hit = s.gp.target > 0 && s.last[0] <= s.gp.target;
+        if (hit) s.reached = true;
+        if (hit || (s.gp.max_it > 0 && s.t >= s.gp.max_it)) {
+            s.active = false;
+            changed = true;
+        }
+    }
+    if (changed) {
+        it.valid = false;
+        drop_graph();
+    }
+}
+
+// At a check boundary: games admitted since the last check join now (or,
+// admitted asynchronously, once their copies had a check period).
+static void join_pending(Engine &eng)
+{
+    bool joined = false;
+    const bool idle = eng.active_set().empty();
+    for (Slot &s : eng.slots)
+        if (s.live && s.pending && (idle || s.join_after <= eng.checks)) {
+            s.pending = false;
+            s.active = true;
+            joined = true;
+        }
+    if (joined) {
+        eng.it.valid = false;
+        eng.drop_graph();
+    }
 }
 
 int Engine::run(int64_t n)
 {
+    if (pending) return fail(CFR_ESTATE, "a check period begun asynchronously has not ended");
     int64_t done = 0;
     while (done < n) {
-        if (phase == 0) {
-            // games admitted since the last check join now (or, admitted
-            // asynchronously, once their copies had a check period)
-            bool joined = false;
-            const bool idle = active_set().empty();
-            for (Slot &s : slots)
-                if (s.live && s.pending && (idle || s.join_after <= checks)) {
-                    s.pending = false;
-                    s.active = true;
-                    joined = true;
-                }
-            if (joined) {
-                it.valid = false;
-                drop_graph();
-            }
-        }
+        if (phase == 0) join_pending(*this);
         const std::vector<int> act = active_set();
         if (act.empty()) break;
         const int64_t chunk =
@@ -1889,21 +1943,44 @@ int Engine::run(int64_t n)
         ++checks;
         rc = evaluate(act, CFR_AVERAGE);
         if (rc) return rc;
-        bool changed = false;
-        for (int k : act) {
-            Slot &s = slots[(size_t)k];
-            const bool hit = s.gp.target > 0 && s.last[0] <= s.gp.target;
-            if (hit) s.reached = true;
-            if (hit || (s.gp.max_it > 0 && s.t >= s.gp.max_it)) {
-                s.active = false;
-                changed = true;
-            }
-        }
-        if (changed) {
-            it.valid = false;
-            drop_graph();
-        }
+        apply_check(act);
     }
+    return CFR_OK;
+}
+
+int Engine::run_begin()
+{
+    if (pending) return fail(CFR_ESTATE, "a check period is already running");
+    if (check_every <= 0) return fail(CFR_ESTATE, "no check period");
+    if (!eval_stage || !eval_ev)
+        return fail(CFR_EUNSUPPORTED, "no page-locked staging for asynchronous checks");
+    if (phase == 0) join_pending(*this);
+    const std::vector<int> act = active_set();
+    if (act.empty()) return CFR_OK;
+    const int64_t chunk = check_every - phase;
+    int rc = iterate(chunk);
+    if (rc) return rc;
+    phase = 0;
+    ++checks;
+    HostTimer timer(&host_s[kHostEval], &host_n[kHostEval]);
+    rc = evaluate_launch(act, CFR_AVERAGE, eval_stage);
+    if (rc) return rc;
+    hipError_t e = hipEventRecord(eval_ev, st);
+    if (e != hipSuccess) return device_error("check event", e);
+    pending = true;
+    pending_set = act;
+    return CFR_OK;
+}
+
+int Engine::run_end()
+{
+    if (!pending) return CFR_OK;
+    pending = false;
+    hipError_t e = hipEventSynchronize(eval_ev);
+    if (e != hipSuccess) return device_error("check period", e);
+    evaluate_collect(pending_set, eval_stage);
+    apply_check(pending_set);
+    pending_set.clear();
     return CFR_OK;
 }
 

@@ -6,9 +6,11 @@ threads (``cfr_prepare``: validation, level order, float conversion; no
 device work, and ctypes releases the GIL), so preparation overlaps the
 device's iterations.  At each check boundary the loop admits waiting
 requests in arrival order while they fit the batch's free slots and device
-ranges (``cfr_batch_add_prepared`` returns CFR_ENOMEM otherwise), runs one
-check period of every game in the batch (``cfr_batch_run``), and frees the
-games that met their stopping rule.  Admission at check boundaries keeps
+ranges (``cfr_batch_add_prepared`` returns CFR_ENOMEM otherwise), begins one
+check period of every game in the batch (``cfr_batch_run_begin``), and
+when it has ended (``cfr_batch_run_end``) frees the games that met their
+stopping rule.  Optionally small games are served by a second batch on a
+stream of its own.  Admission at check boundaries keeps
 every game's iterates and checks identical to the game solved alone.  A
 request that cannot be served (a malformed game, or one larger than the
 whole batch) is answered as rejected, with the library's error code, and
@@ -117,33 +119,81 @@ def capacities_for_bytes(budget: int, mix_units, max_games: int, precision: str 
     return caps(lo)
 
 
+class _Lane:
+    """One batch of the server with its own queue of admitted-to-be requests
+    and its games in flight."""
+
+    def __init__(self, batch: Batch, capacity, nnz_limit):
+        self.batch = batch
+        self.capacity = capacity  # index units of the whole batch
+        self.nnz_limit = nnz_limit  # requests with at most this many nonzeros (None: any)
+        self.waiting = deque()
+        self.inflight = {}
+        self.running = False  # a check period has been begun and not ended
+
+
 class Server:
-    """Continuous batching over one Batch."""
+    """Continuous batching over one Batch, or two: with `small` (a dict with
+    seq_capacity, inf_capacity, nnz_capacity, max_games, nnz_limit and
+    optionally quad_capacity) requests whose game has at most nnz_limit
+    payoff nonzeros go to a second batch on a stream of its own, so that
+    small games iterate without waiting for the large games' launches (in one
+    batch every game advances one iteration per iteration of the whole
+    batch).  Each lane runs its check periods asynchronously
+    (cfr_batch_run_begin / cfr_batch_run_end), so the host's admissions and
+    table builds for one lane overlap the other lane's iterations."""
 
     def __init__(self, seq_capacity, inf_capacity, nnz_capacity, max_games: int = 256,
                  precision: str = "fp32_acc64", check_every: int = 10, workers: int = 8,
                  device: int = 0, async_admission: bool = True, tiling: dict | None = None,
-                 quad_capacity: int = 0):
-        # asynchronous admission: a request's copies to the device overlap
-        # the iterations of the requests already running
-        self.batch = Batch(seq_capacity, inf_capacity, nnz_capacity, max_games=max_games,
-                           precision=precision, mode="alternating", check_every=check_every,
-                           device=device, async_admission=async_admission,
-                           quad_capacity=quad_capacity)
+                 quad_capacity: int = 0, small: dict | None = None):
+        import torch
         # column orders of the quad copies that arriving requests get built
         # on the worker threads (stream form 3 on some product), else None
         self.quad_perm = None
-        if tiling is not None:
-            self.batch.tiling = tiling
-            if 3 in tiling["vec"]:
-                self.quad_perm = tuple(int(v) for v in tiling["perm"])
+        if tiling is not None and 3 in tiling["vec"]:
+            self.quad_perm = tuple(int(v) for v in tiling["perm"])
+
+        def lane(seq, inf, nnz, games, qcap, limit, stream):
+            # asynchronous admission: a request's copies to the device overlap
+            # the iterations of the requests already running
+            b = Batch(seq, inf, nnz, max_games=games, precision=precision, mode="alternating",
+                      check_every=check_every, device=device, async_admission=async_admission,
+                      quad_capacity=qcap, stream=stream)
+            if tiling is not None:
+                b.tiling = tiling
+            cap = np.array([seq[0], seq[1], inf[0], inf[1], nnz], dtype=np.int64)
+            return _Lane(b, cap, limit)
+
+        self.lanes = []
+        if small is not None:
+            st = torch.cuda.Stream(device=torch.device("cuda", int(device)))
+            self.lanes.append(lane(small["seq_capacity"], small["inf_capacity"],
+                                   small["nnz_capacity"], small["max_games"],
+                                   small.get("quad_capacity", 0), small["nnz_limit"], st))
+        self.lanes.append(lane(seq_capacity, inf_capacity, nnz_capacity, max_games, quad_capacity,
+                               None, None))
+        self.batch = self.lanes[-1].batch  # the lane that takes any request
         self.precision = precision
         self.check_every = check_every
         self.workers = workers
-        # index units of the whole batch: a request larger than this in any
-        # unit can never be admitted and is rejected when it reaches the head
-        self.capacity = np.array([seq_capacity[0], seq_capacity[1], inf_capacity[0],
-                                  inf_capacity[1], nnz_capacity], dtype=np.int64)
+
+    def host_stats(self) -> dict:
+        """Host time and calls per activity, summed over the lanes."""
+        tot = {}
+        for ln in self.lanes:
+            for k, v in ln.batch.host_stats().items():
+                t = tot.setdefault(k, {"seconds": 0.0, "calls": 0})
+                t["seconds"] += v["seconds"]
+                t["calls"] += v["calls"]
+        return tot
+
+    def _lane_for(self, units) -> _Lane:
+        for ln in self.lanes:
+            if ln.nnz_limit is not None and units[4] <= ln.nnz_limit and \
+                    np.all(np.asarray(units) <= ln.capacity):
+                return ln
+        return self.lanes[-1]
 
     def serve(self, requests, keep_strategies: bool = False, prepared=None) -> list:
         """Serves `requests` in real time: a list of dicts with "arrival"
@@ -151,12 +201,13 @@ class Server:
         `prepared`, a list of Prepared games: "prepared"), "variant",
         "target" and "max_iterations".  Returns one record per request:
         arrival, admitted, finished, latency, iterations, expl,
-        reached_target, state (and the average strategies with
-        keep_strategies).  state is "done" for a solved request; a request
-        that cannot be served is answered with state "rejected" (its game is
-        malformed: the library's error code and message in "code" and
-        "error"; or it is larger than the whole batch: CFR_ENOMEM) and the
-        loop goes on serving the others."""
+        reached_target, state and lane (0 for the small-game lane when there
+        is one) (and the average strategies with keep_strategies).  state is
+        "done" for a solved request; a request that cannot be served is
+        answered with state "rejected" (its game is malformed: the library's
+        error code and message in "code" and "error"; or it is larger than
+        the whole batch: CFR_ENOMEM) and the loop goes on serving the
+        others."""
         n = len(requests)
         out = [None] * n
         futures = [None] * n
@@ -164,8 +215,53 @@ class Server:
         clock = time.perf_counter
         t0 = clock()
         next_arrival = 0
-        waiting = deque()
-        inflight = {}
+        arrived = deque()  # arrived, not yet routed to a lane (preparation running)
+
+        def reject(k, code, msg):
+            now = clock() - t0
+            out[k] = {"arrival": requests[k]["arrival"], "admitted": None, "finished": now,
+                      "latency": now - requests[k]["arrival"], "iterations": 0, "expl": None,
+                      "reached_target": 0, "state": "rejected", "code": code, "error": msg,
+                      "lane": None}
+
+        def collect(li, ln):
+            now = clock() - t0
+            for gid in list(ln.inflight):
+                st = ln.batch.status(gid)
+                if st["state"] != "done":
+                    continue
+                k, admitted, _ = ln.inflight.pop(gid)
+                rec = {"arrival": requests[k]["arrival"], "admitted": admitted,
+                       "finished": now, "latency": now - requests[k]["arrival"],
+                       "iterations": st["iterations"], "expl": st["expl"],
+                       "reached_target": st["reached_target"], "state": "done", "lane": li}
+                if keep_strategies:
+                    rec["strategy"] = [ln.batch.strategy(gid, p, "average") for p in range(2)]
+                ln.batch.remove(gid)
+                out[k] = rec
+
+        def admit(ln):
+            # admit in arrival order while the head fits
+            while ln.waiting:
+                k, prep = ln.waiting[0]
+                r = requests[k]
+                if np.any(np.asarray(prep.units) > ln.capacity):
+                    ln.waiting.popleft()
+                    reject(k, CFR_ENOMEM, "the game is larger than the whole batch")
+                    continue
+                try:
+                    gid = add_prepared(ln.batch, prep, r["variant"], r["target"],
+                                       r["max_iterations"])
+                except CfrError as e:
+                    if e.code == CFR_ENOMEM and ln.inflight:
+                        break  # waits for games in flight to free space
+                    ln.waiting.popleft()
+                    reject(k, e.code, str(e))
+                    continue
+                ln.waiting.popleft()
+                # the prepared game stays referenced while its copies may run
+                ln.inflight[gid] = (k, clock() - t0, prep)
+
         try:
             while any(r is None for r in out):
                 now = clock() - t0
@@ -177,70 +273,46 @@ class Server:
                     else:
                         futures[k] = pool.submit(Prepared, r["game"], self.precision,
                                                  self.quad_perm)
-                    waiting.append(k)
+                    arrived.append(k)
                     next_arrival += 1
-                # admit in arrival order while the head fits
-                while waiting:
-                    k = waiting[0]
+                # route prepared requests, in arrival order, to their lanes
+                while arrived:
+                    k = arrived[0]
                     f = futures[k]
                     if not isinstance(f, Prepared) and not f.done():
                         break
-                    r = requests[k]
-
-                    def reject(code, msg):
-                        waiting.popleft()
-                        now = clock() - t0
-                        out[k] = {"arrival": r["arrival"], "admitted": None, "finished": now,
-                                  "latency": now - r["arrival"], "iterations": 0, "expl": None,
-                                  "reached_target": 0, "state": "rejected", "code": code,
-                                  "error": msg}
-
+                    arrived.popleft()
                     try:
                         prep = f if isinstance(f, Prepared) else f.result()
                     except CfrError as e:  # the game failed validation
-                        reject(e.code, str(e))
+                        reject(k, e.code, str(e))
                         continue
-                    if np.any(np.asarray(prep.units) > self.capacity):
-                        reject(CFR_ENOMEM, "the game is larger than the whole batch")
-                        continue
-                    try:
-                        gid = add_prepared(self.batch, prep, r["variant"], r["target"],
-                                           r["max_iterations"])
-                    except CfrError as e:
-                        if e.code == CFR_ENOMEM and inflight:
-                            break  # waits for games in flight to free space
-                        reject(e.code, str(e))
-                        continue
-                    waiting.popleft()
-                    # the prepared game stays referenced while its copies may run
-                    inflight[gid] = (k, clock() - t0, prep)
-                if inflight:
-                    self.batch.run(self.check_every)
-                    now = clock() - t0
-                    for gid in list(inflight):
-                        st = self.batch.status(gid)
-                        if st["state"] != "done":
-                            continue
-                        k, admitted, _ = inflight.pop(gid)
-                        rec = {"arrival": requests[k]["arrival"], "admitted": admitted,
-                               "finished": now, "latency": now - requests[k]["arrival"],
-                               "iterations": st["iterations"], "expl": st["expl"],
-                               "reached_target": st["reached_target"], "state": "done"}
-                        if keep_strategies:
-                            rec["strategy"] = [self.batch.strategy(gid, p, "average")
-                                               for p in range(2)]
-                        self.batch.remove(gid)
-                        out[k] = rec
-                elif waiting:
-                    time.sleep(0.0005)  # the head is still being prepared
-                elif next_arrival < n:
-                    time.sleep(max(0.0, requests[next_arrival]["arrival"] - (clock() - t0)))
+                    self._lane_for(prep.units).waiting.append((k, prep))
+                for li, ln in enumerate(self.lanes):
+                    if ln.running:
+                        ln.batch.run_end()
+                        ln.running = False
+                        collect(li, ln)
+                    admit(ln)
+                    if ln.inflight:
+                        ln.batch.run_begin()
+                        ln.running = True
+                if not any(ln.running for ln in self.lanes):
+                    if arrived or any(ln.waiting for ln in self.lanes):
+                        time.sleep(0.0005)  # the head is still being prepared
+                    elif next_arrival < n:
+                        time.sleep(max(0.0, requests[next_arrival]["arrival"] - (clock() - t0)))
         finally:
+            for ln in self.lanes:
+                if ln.running:
+                    ln.batch.run_end()
+                    ln.running = False
             pool.shutdown(wait=True)
         return out
 
     def close(self):
-        self.batch.close()
+        for ln in self.lanes:
+            ln.batch.close()
 
 
 def sequential_latencies(arrivals, service_times):

@@ -381,3 +381,41 @@ def test_many_games_in_one_batch(cfr, mix):
         assert_same(b, gid, solo, f"{name}/{v}")
         solo.close()
     b.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_acc64"])
+def test_asynchronous_check_periods_equal_run(cfr, mix, precision):
+    """Check periods begun and ended asynchronously (cfr_batch_run_begin /
+    cfr_batch_run_end) give the same iterates, checks and stops as
+    cfr_batch_run, bit for bit; between the two calls only status queries
+    are allowed."""
+    games = [g for _, g, _ in mix]
+    targets = {name: 1e-3 * (float(np.ptp(g.val)) if g.nnz else 1.0) for name, g, _ in mix}
+    out = []
+    for asynchronous in (False, True):
+        b = make_batch(cfr, games, max_games=len(mix), precision=precision, check_every=10)
+        ids = [b.add(g, v, target=targets[name], max_iterations=300) for name, g, v in mix]
+        if asynchronous:
+            left = len(ids)
+            rounds = 0
+            while left:
+                b.run_begin()
+                if rounds == 0:
+                    assert b.status(ids[0])["iterations"] >= 0  # allowed
+                    for call in (lambda: b.run(10), lambda: b.strategy(ids[0], 0, "average"),
+                                 lambda: b.add(games[0], "cfr+"), lambda: b.remove(ids[0])):
+                        with pytest.raises(cfr.CfrError) as ei:
+                            call()
+                        assert ei.value.code == cfr.CFR_ESTATE
+                left = b.run_end()
+                rounds += 1
+            assert b.run_end() == 0  # nothing begun: nothing to do
+        else:
+            b.run(100000)
+        st = [b.status(gid) for gid in ids]
+        out.append(([(x["iterations"], x["reached_target"], x["expl"]) for x in st],
+                    [b.strategy(gid, p, "average") for gid in ids for p in range(2)]))
+        b.close()
+    assert out[0][0] == out[1][0]
+    for a, c in zip(out[0][1], out[1][1]):
+        assert np.array_equal(a, c)

@@ -47,19 +47,37 @@ def _requests(pool, n, mean_gap, seed):
 QUADS = {"items": [16, 16], "rows": [256, 256], "vec": [3, 3], "perm": [1, 1], "xcd": [0, 0]}
 
 
+def _small_lane(cfr, pool, limit):
+    """A small-game lane for the pool games of at most `limit` nonzeros,
+    with room for about two of them at once."""
+    units = sorted((cfr.Batch.game_size(g) for g in pool if g.nnz <= limit), key=lambda u: -u[4])
+    cap = np.sum(units[:2], axis=0)
+    return {"seq_capacity": [cap[0], cap[1]], "inf_capacity": [cap[2], cap[3]],
+            "nnz_capacity": int(cap[4]), "max_games": 3, "nnz_limit": limit}
+
+
+@pytest.mark.parametrize("lanes", [1, 2], ids=["one-lane", "two-lanes"])
 @pytest.mark.parametrize("tiling", [None, QUADS], ids=["elements", "quads"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_acc64"])
-def test_served_results_equal_alone(cfr, games, precision, tiling):
+def test_served_results_equal_alone(cfr, games, precision, tiling, lanes):
     from paper_2605_14277_amd import serve
     pool = [games["cfg1"], games["stops"], games["s2d3"], games["perfect"], gg.cfg2_literal()]
     reqs = _requests(pool, 20, 0.004, seed=3)
     # room for about three games at once, so requests also wait for space
     units = sorted((cfr.Batch.game_size(g) for g in pool), key=lambda u: -u[4])
     cap = np.sum(units[:3], axis=0)
+    # two lanes: the four small games (at most 1000 nonzeros) apart from the
+    # medium game, each lane a batch on a stream of its own
+    small = _small_lane(cfr, pool, 1000) if lanes == 2 else None
     srv = serve.Server([cap[0], cap[1]], [cap[2], cap[3]], int(cap[4]), max_games=4,
-                       precision=precision, check_every=10, workers=4, tiling=tiling)
+                       precision=precision, check_every=10, workers=4, tiling=tiling, small=small)
     out = srv.serve(reqs, keep_strategies=True)
     srv.close()
+    if lanes == 2:
+        used = {o["lane"] for o in out}
+        assert used == {0, 1}, used
+        for r, o in zip(reqs, out):
+            assert o["lane"] == (0 if r["game"].nnz <= 1000 else 1)
     overlaps = sum(1 for i in range(len(out)) for j in range(i + 1, len(out))
                    if out[i]["admitted"] < out[j]["finished"] and
                    out[j]["admitted"] < out[i]["finished"])
@@ -127,8 +145,9 @@ def _malformed(game):
     return g
 
 
+@pytest.mark.parametrize("lanes", [1, 2], ids=["one-lane", "two-lanes"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_acc64"])
-def test_served_stream_with_cap_malformed_and_oversized_requests(cfr, games, precision):
+def test_served_stream_with_cap_malformed_and_oversized_requests(cfr, games, precision, lanes):
     """A stream in which one request stops on its iteration limit while
     others run (a target it cannot reach), one game is malformed and one is
     larger than the whole batch: the two are answered as rejected
@@ -146,8 +165,9 @@ def test_served_stream_with_cap_malformed_and_oversized_requests(cfr, games, pre
     bad = dict(reqs[5], game=_malformed(reqs[5]["game"]))
     over = dict(reqs[8], game=big)
     reqs[5], reqs[8] = bad, over
+    small = _small_lane(cfr, pool, 1000) if lanes == 2 else None
     srv = serve.Server([cap[0], cap[1]], [cap[2], cap[3]], int(cap[4]), max_games=4,
-                       precision=precision, check_every=10, workers=4)
+                       precision=precision, check_every=10, workers=4, small=small)
     out = srv.serve(reqs, keep_strategies=True)
     srv.close()
     assert out[5]["state"] == "rejected" and out[5]["code"] == cfr.CFR_EINVAL, out[5]
