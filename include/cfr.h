@@ -474,11 +474,16 @@ int cfr_batch_run(cfr_batch *b, int64_t n, int64_t *n_active);
  * cfr_batch_run_end waits for them, applies the check exactly as
  * cfr_batch_run does (same iterates, same stopping) and writes the number
  * of games still iterating or waiting to *n_active (may be NULL).  Between
- * the two calls only cfr_batch_status may be called on the batch (other
- * calls return CFR_ESTATE); run_end without a begun period does nothing.
+ * the two calls only cfr_batch_status and cfr_batch_run_ready may be
+ * called on the batch (other calls return CFR_ESTATE); run_end without a
+ * begun period does nothing.
  * CFR_EUNSUPPORTED if the page-locked staging could not be allocated.   */
 int cfr_batch_run_begin(cfr_batch *b);
 int cfr_batch_run_end(cfr_batch *b, int64_t *n_active);
+/* *ready = 1 when no check period is begun or the begun one has completed
+ * on the device (cfr_batch_run_end would not wait), else 0.  Does not
+ * wait; may be called between run_begin and run_end.                    */
+int cfr_batch_run_ready(cfr_batch *b, int *ready);
 
 int cfr_batch_status(cfr_batch *b, int64_t id, cfr_game_status *out);
 

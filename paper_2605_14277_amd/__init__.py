@@ -123,6 +123,7 @@ _lib.cfr_batch_add.argtypes = [C.c_void_p, _P(cfr_game_desc), _P(cfr_game_params
 _lib.cfr_batch_run.argtypes = [C.c_void_p, C.c_int64, _P(C.c_int64)]
 _lib.cfr_batch_run_begin.argtypes = [C.c_void_p]
 _lib.cfr_batch_run_end.argtypes = [C.c_void_p, _P(C.c_int64)]
+_lib.cfr_batch_run_ready.argtypes = [C.c_void_p, _P(C.c_int)]
 _lib.cfr_batch_status.argtypes = [C.c_void_p, C.c_int64, _P(cfr_game_status)]
 _lib.cfr_batch_strategy.argtypes = [C.c_void_p, C.c_int64, C.c_int, C.c_int, _P(C.c_double),
                                     C.c_int64]
@@ -151,6 +152,7 @@ for _f in ("cfr_options_default", "cfr_validate", "cfr_workspace_size", "cfr_cre
            "cfr_tune", "cfr_destroy", "cfr_batch_options_default", "cfr_game_params_default",
            "cfr_batch_game_size", "cfr_batch_workspace_size", "cfr_batch_create",
            "cfr_batch_add", "cfr_batch_run", "cfr_batch_run_begin", "cfr_batch_run_end",
+           "cfr_batch_run_ready",
            "cfr_batch_status", "cfr_batch_strategy",
            "cfr_batch_exploitability", "cfr_batch_remove", "cfr_batch_get_tiling",
            "cfr_batch_set_tiling", "cfr_batch_tune", "cfr_batch_kernel_timing",
@@ -397,6 +399,12 @@ def cfr_batch_run(h, n: int) -> int:
 
 def cfr_batch_run_begin(h):
     _check(_lib.cfr_batch_run_begin(h), "cfr_batch_run_begin")
+
+
+def cfr_batch_run_ready(h) -> bool:
+    r = C.c_int(0)
+    _check(_lib.cfr_batch_run_ready(h, C.byref(r)), "cfr_batch_run_ready")
+    return bool(r.value)
 
 
 def cfr_batch_run_end(h) -> int:
@@ -669,6 +677,10 @@ class Batch:
     def run_end(self) -> int:
         """Waits for the check period begun and applies its check."""
         return cfr_batch_run_end(self.h)
+
+    def run_ready(self) -> bool:
+        """True when run_end would not wait."""
+        return cfr_batch_run_ready(self.h)
 
     def status(self, gid: int) -> dict:
         return cfr_batch_status(self.h, gid)

@@ -1183,6 +1183,14 @@ int cfr_batch_run_begin(cfr_batch *b)
     }
 }
 
+int cfr_batch_run_ready(cfr_batch *b, int *ready)
+{
+    if (!b || !ready) return fail(CFR_EINVAL, "null argument");
+    DeviceGuard guard(b->eng.device);
+    *ready = b->eng.run_ready();
+    return CFR_OK;
+}
+
 int cfr_batch_run_end(cfr_batch *b, int64_t *n_active)
 {
     if (!b) return fail(CFR_EINVAL, "null batch");

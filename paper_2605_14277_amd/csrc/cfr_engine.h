@@ -383,6 +383,8 @@ struct Engine {
     // the check.  Nothing else may change the engine in between.
     int run_begin();
     int run_end();
+    // 1 when no check period is begun or the begun one has completed.
+    int run_ready();
     // Times `reps` launches of one product with the current tiling (ms each).
     int time_spmv(int which, int reps, double *ms);
 

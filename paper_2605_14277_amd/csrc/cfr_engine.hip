@@ -1972,6 +1972,16 @@ int Engine::run_begin()
     return CFR_OK;
 }
 
+int Engine::run_ready()
+{
+    if (!pending) return 1;
+    const hipError_t e = hipEventQuery(eval_ev);
+    if (e == hipErrorNotReady) return 0;
+    // completed, or failed: run_end reports a failure
+    (void)hipGetLastError();
+    return 1;
+}
+
 int Engine::run_end()
 {
     if (!pending) return CFR_OK;

@@ -288,8 +288,13 @@ class Server:
                         reject(k, e.code, str(e))
                         continue
                     self._lane_for(prep.units).waiting.append((k, prep))
+                # service every lane whose check period has completed (a lane of
+                # small games is not held up by a lane of large ones)
+                serviced = False
                 for li, ln in enumerate(self.lanes):
                     if ln.running:
+                        if not ln.batch.run_ready():
+                            continue
                         ln.batch.run_end()
                         ln.running = False
                         collect(li, ln)
@@ -297,11 +302,14 @@ class Server:
                     if ln.inflight:
                         ln.batch.run_begin()
                         ln.running = True
-                if not any(ln.running for ln in self.lanes):
-                    if arrived or any(ln.waiting for ln in self.lanes):
-                        time.sleep(0.0005)  # the head is still being prepared
-                    elif next_arrival < n:
-                        time.sleep(max(0.0, requests[next_arrival]["arrival"] - (clock() - t0)))
+                        serviced = True
+                if any(ln.running for ln in self.lanes):
+                    if not serviced:
+                        time.sleep(0.0001)  # every lane's period is still on the device
+                elif arrived or any(ln.waiting for ln in self.lanes):
+                    time.sleep(0.0005)  # the head is still being prepared
+                elif next_arrival < n:
+                    time.sleep(max(0.0, requests[next_arrival]["arrival"] - (clock() - t0)))
         finally:
             for ln in self.lanes:
                 if ln.running:

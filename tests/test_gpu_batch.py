@@ -388,7 +388,7 @@ def test_asynchronous_check_periods_equal_run(cfr, mix, precision):
     """Check periods begun and ended asynchronously (cfr_batch_run_begin /
     cfr_batch_run_end) give the same iterates, checks and stops as
     cfr_batch_run, bit for bit; between the two calls only status queries
-    are allowed."""
+    and cfr_batch_run_ready are allowed."""
     games = [g for _, g, _ in mix]
     targets = {name: 1e-3 * (float(np.ptp(g.val)) if g.nnz else 1.0) for name, g, _ in mix}
     out = []
@@ -407,7 +407,11 @@ def test_asynchronous_check_periods_equal_run(cfr, mix, precision):
                         with pytest.raises(cfr.CfrError) as ei:
                             call()
                         assert ei.value.code == cfr.CFR_ESTATE
+                if rounds % 2:
+                    while not b.run_ready():  # polled, then ended without waiting
+                        pass
                 left = b.run_end()
+                assert b.run_ready()
                 rounds += 1
             assert b.run_end() == 0  # nothing begun: nothing to do
         else:
