@@ -622,7 +622,8 @@ def serve_record(args, torch, rates) -> dict:
                  "target": float(rel[k] * ranges[which[k]]), "max_iterations": max_it}
                 for k in range(n)]
         srv = serve.Server(seq, inf, nz, max_games=args.max_games, precision=precision,
-                           check_every=K, tiling=tiling, quad_capacity=qcap, small=small)
+                           check_every=K, tiling=tiling, quad_capacity=qcap, small=small,
+                           solo=args.solo if small else 0, admit_after=args.admit_after)
         out = srv.serve(reqs, prepared=prepared)
         host = srv.host_stats()
         srv.close()
@@ -654,8 +655,9 @@ def serve_record(args, torch, rates) -> dict:
                         f"1e-3 of the payoff range or {max_it} iterations, checks every {K}, "
                         f"{args.budget_gb:g} GB device budget, {args.max_games} slots"
                         + (f" per lane; games of at most {args.small_nnz:.0e} nonzeros in a "
-                           f"lane of their own ({args.small_share:g} of the budget)"
-                           if small else ""),
+                           f"lane of their own ({args.small_share:g} of the budget); the other "
+                           f"lane holds {args.solo} game(s) and admits more once a request has "
+                           f"waited {args.admit_after:g} s" if small else ""),
             "lanes": 2 if small else 1, "tiling": tiling, "rates": per_rate,
             "pool": {"games": args.pool, "nnz_median": float(np.median(nnz)),
                      "nnz_max": int(nnz.max()), "generate_s": gen_s, "prepare_s": prep_s}}
@@ -790,6 +792,11 @@ def main():
     ap.add_argument("--small-nnz", type=float, default=5e6, help="serve: small-game lane limit")
     ap.add_argument("--small-share", type=float, default=0.2,
                     help="serve: share of the device budget for the small-game lane")
+    ap.add_argument("--solo", type=int, default=1,
+                    help="serve: games the main lane holds before admitting another beside "
+                         "them only after --admit-after seconds of waiting (0: always admit)")
+    ap.add_argument("--admit-after", type=float, default=0.05,
+                    help="serve: the wait that lets a request join a busy main lane")
     ap.add_argument("--max-games", type=int, default=256, help="serve: game slots")
     ap.add_argument("--plain-stride", type=int, default=16,
                     help="batch: also solve every k-th game alone with vanilla CFR (0: skip)")

@@ -22,6 +22,7 @@ with the index-unit proportions of the expected request mix.
 from __future__ import annotations
 
 import ctypes as C
+import threading
 import time
 from collections import deque
 from concurrent.futures import ThreadPoolExecutor
@@ -123,13 +124,18 @@ class _Lane:
     """One batch of the server with its own queue of admitted-to-be requests
     and its games in flight."""
 
-    def __init__(self, batch: Batch, capacity, nnz_limit):
+    def __init__(self, batch: Batch, capacity, nnz_limit, solo: int = 0, admit_after: float = 0.0):
         self.batch = batch
         self.capacity = capacity  # index units of the whole batch
         self.nnz_limit = nnz_limit  # requests with at most this many nonzeros (None: any)
-        self.waiting = deque()
+        # with `solo` games in flight, a waiting request is admitted beside
+        # them only once it has waited `admit_after` seconds (0: no limit)
+        self.solo = solo
+        self.admit_after = admit_after
+        self.waiting = deque()  # appended by the serving thread, taken by the lane's
         self.inflight = {}
         self.running = False  # a check period has been begun and not ended
+        self.wake = threading.Event()  # a request has been routed to the lane
 
 
 class Server:
@@ -140,13 +146,22 @@ class Server:
     small games iterate without waiting for the large games' launches (in one
     batch every game advances one iteration per iteration of the whole
     batch).  Each lane runs its check periods asynchronously
-    (cfr_batch_run_begin / cfr_batch_run_end), so the host's admissions and
-    table builds for one lane overlap the other lane's iterations."""
+    (cfr_batch_run_begin / cfr_batch_run_end, polled with
+    cfr_batch_run_ready) from a host thread of its own, so the admissions,
+    table builds and uploads of one lane overlap the other lane's iterations
+    and host work; the serving thread takes arrivals and routes them.  With `solo` the lane that
+    takes any request holds that many games and admits another beside them
+    only once it has waited `admit_after` seconds: at light load large games
+    run on their own (in a batch each game advances one iteration per
+    iteration of the whole batch, so a large game shares the device's
+    bandwidth with every other), while a queue that builds up under load
+    brings batching back."""
 
     def __init__(self, seq_capacity, inf_capacity, nnz_capacity, max_games: int = 256,
                  precision: str = "fp32_acc64", check_every: int = 10, workers: int = 8,
                  device: int = 0, async_admission: bool = True, tiling: dict | None = None,
-                 quad_capacity: int = 0, small: dict | None = None):
+                 quad_capacity: int = 0, small: dict | None = None, solo: int = 0,
+                 admit_after: float = 0.0):
         import torch
         # column orders of the quad copies that arriving requests get built
         # on the worker threads (stream form 3 on some product), else None
@@ -154,7 +169,7 @@ class Server:
         if tiling is not None and 3 in tiling["vec"]:
             self.quad_perm = tuple(int(v) for v in tiling["perm"])
 
-        def lane(seq, inf, nnz, games, qcap, limit, stream):
+        def lane(seq, inf, nnz, games, qcap, limit, stream, solo_=0, after=0.0):
             # asynchronous admission: a request's copies to the device overlap
             # the iterations of the requests already running
             b = Batch(seq, inf, nnz, max_games=games, precision=precision, mode="alternating",
@@ -163,7 +178,7 @@ class Server:
             if tiling is not None:
                 b.tiling = tiling
             cap = np.array([seq[0], seq[1], inf[0], inf[1], nnz], dtype=np.int64)
-            return _Lane(b, cap, limit)
+            return _Lane(b, cap, limit, solo_, after)
 
         self.lanes = []
         if small is not None:
@@ -172,7 +187,7 @@ class Server:
                                    small["nnz_capacity"], small["max_games"],
                                    small.get("quad_capacity", 0), small["nnz_limit"], st))
         self.lanes.append(lane(seq_capacity, inf_capacity, nnz_capacity, max_games, quad_capacity,
-                               None, None))
+                               None, None, solo, admit_after))
         self.batch = self.lanes[-1].batch  # the lane that takes any request
         self.precision = precision
         self.check_every = check_every
@@ -245,6 +260,9 @@ class Server:
             while ln.waiting:
                 k, prep = ln.waiting[0]
                 r = requests[k]
+                if ln.solo and len(ln.inflight) >= ln.solo and \
+                        clock() - t0 - r["arrival"] < ln.admit_after:
+                    break  # the lane is busy and the head has not waited long enough
                 if np.any(np.asarray(prep.units) > ln.capacity):
                     ln.waiting.popleft()
                     reject(k, CFR_ENOMEM, "the game is larger than the whole batch")
@@ -262,8 +280,47 @@ class Server:
                 # the prepared game stays referenced while its copies may run
                 ln.inflight[gid] = (k, clock() - t0, prep)
 
+        routed_all = threading.Event()  # every request has been routed (or rejected)
+        abort = threading.Event()
+        errors = []
+
+        def lane_loop(li, ln):
+            # one host thread per lane: its admissions, table builds and
+            # uploads (library calls, which release the interpreter lock)
+            # overlap the other lane's
+            try:
+                while not abort.is_set():
+                    if ln.running:
+                        while not ln.batch.run_ready():
+                            time.sleep(5e-5)  # the check period is still on the device
+                        ln.batch.run_end()
+                        ln.running = False
+                        collect(li, ln)
+                    admit(ln)
+                    if ln.inflight:
+                        ln.batch.run_begin()
+                        ln.running = True
+                        continue
+                    ln.wake.clear()
+                    if ln.waiting:
+                        continue
+                    if routed_all.is_set():
+                        break
+                    ln.wake.wait(0.01)
+            except BaseException as e:  # reported by the serving thread
+                errors.append(e)
+                abort.set()
+            finally:
+                if ln.running:
+                    ln.running = False
+                    ln.batch.run_end()
+
+        threads = [threading.Thread(target=lane_loop, args=(li, ln), daemon=True)
+                   for li, ln in enumerate(self.lanes)]
+        for th in threads:
+            th.start()
         try:
-            while any(r is None for r in out):
+            while (next_arrival < n or arrived) and not abort.is_set():
                 now = clock() - t0
                 while next_arrival < n and requests[next_arrival]["arrival"] <= now:
                     k = next_arrival
@@ -287,35 +344,26 @@ class Server:
                     except CfrError as e:  # the game failed validation
                         reject(k, e.code, str(e))
                         continue
-                    self._lane_for(prep.units).waiting.append((k, prep))
-                # service every lane whose check period has completed (a lane of
-                # small games is not held up by a lane of large ones)
-                serviced = False
-                for li, ln in enumerate(self.lanes):
-                    if ln.running:
-                        if not ln.batch.run_ready():
-                            continue
-                        ln.batch.run_end()
-                        ln.running = False
-                        collect(li, ln)
-                    admit(ln)
-                    if ln.inflight:
-                        ln.batch.run_begin()
-                        ln.running = True
-                        serviced = True
-                if any(ln.running for ln in self.lanes):
-                    if not serviced:
-                        time.sleep(0.0001)  # every lane's period is still on the device
-                elif arrived or any(ln.waiting for ln in self.lanes):
+                    ln = self._lane_for(prep.units)
+                    ln.waiting.append((k, prep))
+                    ln.wake.set()
+                if arrived:
                     time.sleep(0.0005)  # the head is still being prepared
                 elif next_arrival < n:
-                    time.sleep(max(0.0, requests[next_arrival]["arrival"] - (clock() - t0)))
+                    time.sleep(min(0.01, max(0.0, requests[next_arrival]["arrival"] -
+                                             (clock() - t0))))
+        except BaseException:
+            abort.set()
+            raise
         finally:
+            routed_all.set()
             for ln in self.lanes:
-                if ln.running:
-                    ln.batch.run_end()
-                    ln.running = False
+                ln.wake.set()
+            for th in threads:
+                th.join()
             pool.shutdown(wait=True)
+        if errors:
+            raise errors[0]
         return out
 
     def close(self):

@@ -56,10 +56,11 @@ def _small_lane(cfr, pool, limit):
             "nnz_capacity": int(cap[4]), "max_games": 3, "nnz_limit": limit}
 
 
-@pytest.mark.parametrize("lanes", [1, 2], ids=["one-lane", "two-lanes"])
+@pytest.mark.parametrize("lanes,solo", [(1, 0), (2, 0), (2, 1)],
+                         ids=["one-lane", "two-lanes", "two-lanes-solo"])
 @pytest.mark.parametrize("tiling", [None, QUADS], ids=["elements", "quads"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_acc64"])
-def test_served_results_equal_alone(cfr, games, precision, tiling, lanes):
+def test_served_results_equal_alone(cfr, games, precision, tiling, lanes, solo):
     from paper_2605_14277_amd import serve
     pool = [games["cfg1"], games["stops"], games["s2d3"], games["perfect"], gg.cfg2_literal()]
     reqs = _requests(pool, 20, 0.004, seed=3)
@@ -69,8 +70,11 @@ def test_served_results_equal_alone(cfr, games, precision, tiling, lanes):
     # two lanes: the four small games (at most 1000 nonzeros) apart from the
     # medium game, each lane a batch on a stream of its own
     small = _small_lane(cfr, pool, 1000) if lanes == 2 else None
+    # solo: the lane of the medium game holds one game and admits another
+    # beside it only after a wait of 2 ms
     srv = serve.Server([cap[0], cap[1]], [cap[2], cap[3]], int(cap[4]), max_games=4,
-                       precision=precision, check_every=10, workers=4, tiling=tiling, small=small)
+                       precision=precision, check_every=10, workers=4, tiling=tiling, small=small,
+                       solo=solo, admit_after=0.002)
     out = srv.serve(reqs, keep_strategies=True)
     srv.close()
     if lanes == 2:
