@@ -357,9 +357,13 @@ struct Engine {
     int rebuild();  // iteration tables of the active games; drops the graph
     void drop_graph();
 
+    // `gathered`: the permuted copy the product reads is already current
+    // (written by the top-down pass just before), so no gather launch
     hipError_t spmv(const Tables &T, int which, const void *xin, void *yout, bool begin,
-                    hipStream_t s, bool timed);
-    hipError_t sweeps(const Tables &T, int p, double usign, hipStream_t s);
+                    hipStream_t s, bool timed, bool gathered = false);
+    // With `fold` non-null, a lone game's top-down pass also writes the
+    // permuted copy of x (and sets *fold) when it runs as one launch.
+    hipError_t sweeps(const Tables &T, int p, double usign, hipStream_t s, bool *fold = nullptr);
     hipError_t enqueue_iteration(hipStream_t s);
     hipError_t build_graph();
     // n iterations of every active game (no checks).

@@ -1661,15 +1661,17 @@ int Engine::rebuild()
 }
 
 hipError_t Engine::spmv(const Tables &T, int which, const void *xin, void *yout, bool begin,
-                        hipStream_t s, bool timed)
+                        hipStream_t s, bool timed, bool gathered)
 {
     const SpmvBlock *tab = which == 0 ? T.csr : T.csc;
     const int32_t n = which == 0 ? T.n_csr : T.n_csc;
     if (perm_on[which]) {
         // the product reads the gathered player's vector in first-touch order
         const int q = 1 - which;
-        hipError_t e = launch_gather(prec, T.seq[q], T.n_seq[q], dp[q].perm, xin, dp[q].xp, s);
-        if (e != hipSuccess) return e;
+        if (!gathered) {
+            hipError_t e = launch_gather(prec, T.seq[q], T.n_seq[q], dp[q].perm, xin, dp[q].xp, s);
+            if (e != hipSuccess) return e;
+        }
         xin = dp[q].xp;
     }
     const bool quads = vec[which] == 3;
@@ -1692,7 +1694,7 @@ hipError_t Engine::spmv(const Tables &T, int which, const void *xin, void *yout,
                        sequential(), begin ? 1 : 0, sc, s);
 }
 
-hipError_t Engine::sweeps(const Tables &T, int p, double usign, hipStream_t s)
+hipError_t Engine::sweeps(const Tables &T, int p, double usign, hipStream_t s, bool *fold)
 {
     const DevPlayer &d = dp[p];
     const int maxL = (int)T.up_l[p].size();
@@ -1734,9 +1736,17 @@ hipError_t Engine::sweeps(const Tables &T, int p, double usign, hipStream_t s)
         if ((e = launch_shallow(prec, slots[0].gp.variant, d, usign, sc, s)) != hipSuccess)
             return e;
     }
-    if (!top && down_pass == CFR_DOWN_DEFAULT && T.dall_depth[p] <= kDownAllMaxDepth)
-        return launch_down_all(prec, T.dall_depth[p], T.dall[p], T.n_dall[p], &T.dall_direct[p], d,
-                               1, sc, s);
+    if (!top && down_pass == CFR_DOWN_DEFAULT && T.dall_depth[p] <= kDownAllMaxDepth) {
+        const RangeBlock &dr = T.dall_direct[p];
+        if (fold && lone && dr.hi > dr.lo) {
+            // from the game's empty sequence on, writing the permuted copy too
+            *fold = true;
+            const RangeBlock all{dr.aux, dr.hi, dr.slot, dr.aux};
+            return launch_down_all(prec, T.dall_depth[p], T.dall[p], T.n_dall[p], &all, d, 1, sc,
+                                   s, 1, dr.lo);
+        }
+        return launch_down_all(prec, T.dall_depth[p], T.dall[p], T.n_dall[p], &dr, d, 1, sc, s);
+    }
     for (int L = std::max(low, 1); L < maxL; ++L) {
         const auto &dl = T.down_l[p][(size_t)L];
         if ((e = launch_down(prec, T.down[p] + dl.first, dl.second, d, 1, sc, s)) != hipSuccess)
@@ -1757,9 +1767,12 @@ hipError_t Engine::enqueue_iteration(hipStream_t s)
         if ((e = sweeps(it, 0, 1.0, s)) != hipSuccess) return e;
         return sweeps(it, 1, -1.0, s);
     }
+    // player 1's top-down pass, right before the product that reads its
+    // strategy, may write the permuted copy that product gathers from
+    bool folded = false;
     if ((e = spmv(it, 0, dp[1].x, dp[0].g, true, s, timed)) != hipSuccess) return e;
-    if ((e = sweeps(it, 0, 1.0, s)) != hipSuccess) return e;
-    if ((e = spmv(it, 1, dp[0].x, dp[1].g, false, s, timed)) != hipSuccess) return e;
+    if ((e = sweeps(it, 0, 1.0, s, perm_on[1] ? &folded : nullptr)) != hipSuccess) return e;
+    if ((e = spmv(it, 1, dp[0].x, dp[1].g, false, s, timed, folded)) != hipSuccess) return e;
     return sweeps(it, 1, -1.0, s);
 }
 

@@ -153,9 +153,12 @@ hipError_t launch_down(int prec, const RangeBlock *tab, int32_t n_tab, const Dev
 // Top-down pass over every level below level 0 in one launch: each sequence
 // of `tab` (aux = its game's empty sequence) multiplies the behavioural
 // strategies of its at most max_depth (<= kDownAllMaxDepth) ancestors.
+// With `fold` (a direct range from one game's empty sequence on) it also
+// writes the first-touch copy p.xp[p.pos[i]] = x[i] and averages only the
+// sequences from avg_lo on.
 hipError_t launch_down_all(int prec, int max_depth, const RangeBlock *tab, int32_t n_tab,
                            const RangeBlock *direct, const DevPlayer &p, int average,
-                           const Scalars *sc, hipStream_t st);
+                           const Scalars *sc, hipStream_t st, int fold = 0, int32_t avg_lo = 0);
 // ObserveUtility on levels top_levels-1..0, then the top-down pass on levels
 // 0..top_levels-1 (with averaging when `average`) of the game in slot 0.
 hipError_t launch_top(int prec, int variant, const DevPlayer &p, double usign, int average,

@@ -1183,14 +1183,22 @@ __global__ __launch_bounds__(kThreads) void k_down(const RangeBlock *__restrict_
 // order as the level-by-level pass, so the result is bit for bit the same.
 // It reads only b and the parent links, which the bottom-up pass has
 // finished, never another thread's x.  MAXD bounds the chain length.
-template <int P, int MAXD>
+// With FOLD (one game, range from its empty sequence on) the launch also
+// writes the copy in first-touch order that the next product reads,
+// xp[pos[i]] = x[i], so no gather launch is needed; the sequences below
+// avg_lo (the empty sequence and level 0's, whose x the bottom-up pass
+// already wrote: the chain gives the same products) are rewritten with the
+// same values and not averaged again.
+template <int P, int MAXD, bool FOLD>
 __global__ __launch_bounds__(kThreads) void k_down_all(const RangeBlock *__restrict__ tab,
                                                        const int32_t *__restrict__ seq_par,
                                                        const typename Types<P>::V *__restrict__ b,
                                                        typename Types<P>::V *__restrict__ x,
                                                        typename Types<P>::R *__restrict__ s,
                                                        const Scalars *__restrict__ sc, int average,
-                                                       RangeBlock dr)
+                                                       RangeBlock dr, const int32_t *__restrict__ pos,
+                                                       typename Types<P>::V *__restrict__ xp,
+                                                       int32_t avg_lo)
 {
     using V = typename Types<P>::V;
     using R = typename Types<P>::R;
@@ -1213,11 +1221,12 @@ __global__ __launch_bounds__(kThreads) void k_down_all(const RangeBlock *__restr
 #pragma unroll
     for (int k = MAXD - 1; k >= 0; --k)
         if (k < d) xv = xv * chain[k];
-    if (average) {
+    if (average && (!FOLD || i >= avg_lo)) {
         R w = (R)sc[rb.slot].w;
         s[i] = s[i] + w * (R)x[i];
     }
     x[i] = xv;
+    if (FOLD) xp[pos[i]] = xv;
 }
 
 // ---------------------------------------------------------------------------
@@ -1713,23 +1722,40 @@ hipError_t down_t(const RangeBlock *tab, int32_t n_tab, const DevPlayer &p, int 
     return hipGetLastError();
 }
 
-template <int P>
-hipError_t down_all_t(int maxd, const RangeBlock *tab, int32_t n_tab, const RangeBlock &dr,
-                      const DevPlayer &p, int average, const Scalars *sc, hipStream_t st)
+template <int P, int MAXD, bool FOLD>
+void down_all_launch(unsigned grid, const RangeBlock *tab, const RangeBlock &dr, const DevPlayer &p,
+                     int average, const Scalars *sc, int32_t avg_lo, hipStream_t st)
 {
     using T = Types<P>;
+    hipLaunchKernelGGL((k_down_all<P, MAXD, FOLD>), dim3(grid), dim3(kThreads), 0, st, tab,
+                       p.seq_par, (const typename T::V *)p.b, (typename T::V *)p.x,
+                       (typename T::R *)p.s, sc, average, dr, FOLD ? p.pos : nullptr,
+                       FOLD ? (typename T::V *)p.xp : nullptr, avg_lo);
+}
+
+template <int P>
+hipError_t down_all_t(int maxd, const RangeBlock *tab, int32_t n_tab, const RangeBlock &dr,
+                      const DevPlayer &p, int average, const Scalars *sc, int fold,
+                      int32_t avg_lo, hipStream_t st)
+{
     const unsigned grid = sweep_grid(n_tab, dr);
     if (grid == 0) return hipSuccess;
-    if (maxd <= 8)
-        hipLaunchKernelGGL((k_down_all<P, 8>), dim3(grid), dim3(kThreads), 0, st, tab, p.seq_par,
-                           (const typename T::V *)p.b, (typename T::V *)p.x, (typename T::R *)p.s,
-                           sc, average, dr);
-    else if (maxd <= kDownAllMaxDepth)
-        hipLaunchKernelGGL((k_down_all<P, kDownAllMaxDepth>), dim3(grid), dim3(kThreads), 0, st,
-                           tab, p.seq_par, (const typename T::V *)p.b, (typename T::V *)p.x,
-                           (typename T::R *)p.s, sc, average, dr);
-    else
+    // the fold needs one game's direct range, from its empty sequence on
+    if (fold && (dr.hi <= dr.lo || dr.lo != dr.aux || avg_lo < dr.lo || avg_lo > dr.hi))
         return hipErrorInvalidValue;
+    if (maxd <= 8) {
+        if (fold)
+            down_all_launch<P, 8, true>(grid, tab, dr, p, average, sc, avg_lo, st);
+        else
+            down_all_launch<P, 8, false>(grid, tab, dr, p, average, sc, avg_lo, st);
+    } else if (maxd <= kDownAllMaxDepth) {
+        if (fold)
+            down_all_launch<P, kDownAllMaxDepth, true>(grid, tab, dr, p, average, sc, avg_lo, st);
+        else
+            down_all_launch<P, kDownAllMaxDepth, false>(grid, tab, dr, p, average, sc, avg_lo, st);
+    } else {
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -1838,10 +1864,10 @@ hipError_t launch_down(int prec, const RangeBlock *tab, int32_t n_tab, const Dev
 
 hipError_t launch_down_all(int prec, int max_depth, const RangeBlock *tab, int32_t n_tab,
                            const RangeBlock *direct, const DevPlayer &p, int average,
-                           const Scalars *sc, hipStream_t st)
+                           const Scalars *sc, hipStream_t st, int fold, int32_t avg_lo)
 {
     const RangeBlock dr = direct ? *direct : RangeBlock{0, 0, 0, 0};
-    CFR_DISPATCH(prec, down_all_t<P>(max_depth, tab, n_tab, dr, p, average, sc, st));
+    CFR_DISPATCH(prec, down_all_t<P>(max_depth, tab, n_tab, dr, p, average, sc, fold, avg_lo, st));
 }
 
 hipError_t launch_normalize(int prec, const RangeBlock *tab, int32_t n_tab, const DevPlayer &p,

@@ -408,6 +408,41 @@ def test_quads_fp64_equal_elementwise(cfr, oracle_mod, games, name):
     compare_fp64(last, orc, tol=1e-9, what=f"{name}-quads")
 
 
+@pytest.mark.parametrize("mode", ["alternating", "simultaneous"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_top_down_pass_writes_the_permuted_copy(cfr, precision, mode):
+    """With alternating updates, player 1's top-down pass of a lone game
+    writes the first-touch copy of x that the product A^T x reads, instead of
+    a gather launch.  Evaluations (which gather the average strategy into the
+    same copy) and a restored checkpoint sit between the steps.  Every
+    iterate equals that of the same solver without the first-touch order,
+    bit for bit: the order only renumbers the columns, and each row keeps
+    its nonzeros in the same order."""
+    g = gg.cfg2()
+    base = {"items": [16, 16], "rows": [256, 256], "vec": [2, 2], "xcd": [1, 1]}
+    out = []
+    for perm in ([0, 0], [0, 1], [1, 1]):
+        say(f"case: cfg2 {precision} {mode} perm {perm}")
+        s = cfr.Solver(g, precision=precision)
+        s.tiling = dict(base, perm=perm)
+        rec = []
+        s.step(7, "dcfr", mode)
+        rec.append(s.exploitability("average")["expl"])
+        state = s.get_state()
+        s.step(5, "dcfr", mode)
+        rec += [s.strategy(p, "current") for p in range(2)]
+        s.set_state(state)
+        s.step(9, "dcfr", mode)
+        rec.append(s.exploitability("average")["expl"])
+        rec += [s.strategy(p, k) for p in range(2) for k in ("current", "average")]
+        rec += [s.regrets(p) for p in range(2)]
+        out.append(rec)
+        s.close()
+    for other in out[1:]:
+        for a, c in zip(out[0], other):
+            assert np.array_equal(a, c)
+
+
 @pytest.mark.parametrize("precision", ["fp32", "fp32_acc64"])
 def test_quads_fp32_short_horizon(cfr, oracle_mod, precision):
     """Stream form 3 in the FP32 modes tracks the FP64 oracle on the same
