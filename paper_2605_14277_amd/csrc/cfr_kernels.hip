@@ -725,6 +725,140 @@ __device__ __forceinline__ void up_infoset(
     }
 }
 
+// The fast path of up_infoset below (up_infoset_fast) split in two, for
+// the one-block pass over the shallow levels, which issues every level's
+// loads before computing any level.  The loads of one fast-path decision
+// point (at most kFastActs actions, each with at most kFastKids decision
+// points below it): its action range, each
+// action's payoff, strategy and regret (and prediction), and the child
+// counts with either the child values (from value slots, SL & kSlotsRead)
+// or the child ids (the caller then reads the values).  Every load is
+// issued unconditionally (lanes past the end read a valid clamped address
+// and ignore the value), so one dependent round serves each of: action
+// range; action data with child pointers, or with child counts and values
+// when the level reads slots; otherwise child ids.
+template <int P, int NC>
+struct FastLoads {
+    static constexpr int NCA = NC > 0 ? NC : 1;
+    int32_t a0, n;
+    typename Types<P>::V gv[kFastActs], bv[kFastActs];
+    typename Types<P>::R rv[kFastActs], mv[kFastActs];
+    int cnt[kFastActs];
+    typename Types<P>::C cv[kFastActs][NCA];
+    int32_t cid[kFastActs][NCA];
+};
+
+template <int P, int VAR, int NC, int SL>
+__device__ __forceinline__ void fast_load(int32_t j, const int32_t *__restrict__ inf_first,
+                                          const int32_t *__restrict__ child_ptr,
+                                          const int32_t *__restrict__ child_idx,
+                                          const typename Types<P>::V *__restrict__ g,
+                                          const typename Types<P>::V *__restrict__ b,
+                                          const typename Types<P>::R *__restrict__ r,
+                                          const typename Types<P>::R *__restrict__ m,
+                                          const Kids<P> &kd, FastLoads<P, NC> &L)
+{
+    static_assert(NC == 0 || NC == 4, "child values are read as slots of four");
+    constexpr int NA = kFastActs;
+    constexpr bool kPred = VAR == CFR_PCFR_PLUS || VAR == CFR_PCFR;
+    L.a0 = inf_first[j];
+    L.n = inf_first[j + 1] - L.a0;
+    if (NC > 0 && (SL & kSlotsRead)) {
+#pragma unroll
+        for (int k = 0; k < NA; ++k) {
+            const int32_t a = L.a0 + (k < L.n ? k : 0);
+            L.gv[k] = g[a];
+            L.bv[k] = b[a];
+            L.rv[k] = r[a];
+            if (kPred) L.mv[k] = m[a];
+            L.cnt[k] = kd.ccount[a];
+#pragma unroll
+            for (int i = 0; i < NC; ++i) L.cv[k][i] = kd.cval[4 * (int64_t)a + i];
+        }
+    } else {
+        int32_t c0[NA];
+#pragma unroll
+        for (int k = 0; k < NA; ++k) {
+            const int32_t a = L.a0 + (k < L.n ? k : 0);
+            L.gv[k] = g[a];
+            L.bv[k] = b[a];
+            L.rv[k] = r[a];
+            if (kPred) L.mv[k] = m[a];
+            if (NC > 0) {
+                c0[k] = child_ptr[a];
+                L.cnt[k] = child_ptr[a + 1] - c0[k];
+            } else {
+                c0[k] = 0;
+                L.cnt[k] = 0;
+            }
+        }
+        if (NC > 0) {
+#pragma unroll
+            for (int k = 0; k < NA; ++k)
+#pragma unroll
+                for (int i = 0; i < NC; ++i)
+                    L.cid[k][i] = child_idx[i < L.cnt[k] ? c0[k] + i : 0];
+        }
+    }
+}
+
+// The arithmetic of one fast-path decision point from its loads (child
+// values in L.cv): counterfactual values q (own payoff, then the children in
+// ascending order), the value V = sum_a b q, the regret update with the
+// variant's post-step, and regret matching.  Writes r (and m) and the next
+// strategy b; returns V.  The arithmetic and its order are exactly those
+// of up_infoset and up_infoset_fast (a one-block pass equals a launch per
+// level bit for bit, which the tests check).
+template <int P, int VAR, int NC>
+__device__ __forceinline__ typename Types<P>::C fast_apply(
+    const FastLoads<P, NC> &L, typename Types<P>::C usign, typename Types<P>::V *__restrict__ b,
+    typename Types<P>::R *__restrict__ r, typename Types<P>::R *__restrict__ m,
+    typename Types<P>::C dpos, typename Types<P>::C dneg)
+{
+    using V = typename Types<P>::V;
+    using R = typename Types<P>::R;
+    using C = typename Types<P>::C;
+    constexpr int NA = kFastActs;
+    constexpr bool kPred = VAR == CFR_PCFR_PLUS || VAR == CFR_PCFR;
+    const int32_t a0 = L.a0, n = L.n;
+    C q[NA];
+    C V_ = 0;
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+        if (k < n) {
+            C acc = usign * (C)L.gv[k];
+#pragma unroll
+            for (int i = 0; i < NC; ++i)
+                if (i < L.cnt[k]) acc = acc + L.cv[k][i];
+            q[k] = acc;
+            V_ = V_ + (C)L.bv[k] * acc;
+        }
+    }
+    C z[NA];
+    C Z = 0;
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+        if (k < n) {
+            const int32_t a = a0 + k;
+            C inst = q[k] - V_;
+            C rr = post_step<P, VAR>((C)L.rv[k] + inst, dpos, dneg);
+            r[a] = (R)rr;
+            C zz = (C)(R)rr;
+            if (kPred) {
+                m[a] = (R)inst;
+                zz = zz + (C)(R)inst;
+            }
+            zz = zz > 0 ? zz : 0;
+            z[k] = zz;
+            Z = Z + zz;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NA; ++k)
+        if (k < n) b[a0 + k] = (V)(Z > 0 ? z[k] / Z : (C)1 / (C)n);
+    return V_;
+}
+
 // Fast path of up_infoset for a decision point with at most kFastActs
 // actions, each with at most kFastKids decision points below it.  Every
 // load is issued unconditionally (lanes past the end read a valid clamped
@@ -1100,26 +1234,29 @@ __global__ __launch_bounds__(kTopThreads) void k_top(
     }
 }
 
-// The shallow levels of a lone game in one block, deepest first: the values
-// of each level's decision points stay in LDS, where the level above reads
-// them through its child lists, so consecutive levels are separated by a
-// block barrier instead of a kernel boundary and a round trip through
-// global memory.  The deepest of these levels reads its children's values
-// (written by the launch of the level below) from their value slots, as its
-// own launch would.  Every decision point
-// runs the fast path of ObserveUtility with the same operations in the same
-// order as in a launch per level, so every result is the same bit for bit.
-// Only LDS is shared between threads here (the global stores are each
-// thread's own decision point's regrets and strategies).
+// The shallow levels of a lone game in one block: the values of each level's
+// decision points stay in LDS, where the level above reads them through its
+// child lists, so consecutive levels are separated by a block barrier
+// instead of a kernel boundary and a round trip through global memory.  The
+// deepest of these levels reads its children's values (written by the
+// launch of the level below) from their value slots, as its own launch
+// would.  Each thread owns one decision point of the shallow levels (at
+// most kShallowThreads in all) and issues all of its loads before any level
+// is computed, so every level's dependent load rounds overlap those of the
+// levels below it; the levels are then computed deepest first, each from
+// registers and LDS.  Every decision point runs the fast path of
+// ObserveUtility with the same operations in the same order as in a launch
+// per level, so every result is the same bit for bit.  Only LDS is shared
+// between threads here (the global stores are each thread's own decision
+// point's regrets and strategies).
 template <int P, int VAR>
 __global__ __launch_bounds__(kShallowThreads) void k_shallow(
     ShallowPlan sp, const int32_t *__restrict__ inf_first, const int32_t *__restrict__ child_ptr,
     const int32_t *__restrict__ child_idx, const typename Types<P>::V *__restrict__ g,
-    typename Types<P>::C usign, typename Types<P>::C *__restrict__ vinf,
-    typename Types<P>::V *__restrict__ b, typename Types<P>::R *__restrict__ r,
-    typename Types<P>::R *__restrict__ m, const Scalars *__restrict__ sc,
-    const int32_t *__restrict__ seq_par, typename Types<P>::V *__restrict__ x,
-    typename Types<P>::R *__restrict__ s, Kids<P> kd)
+    typename Types<P>::C usign, typename Types<P>::V *__restrict__ b,
+    typename Types<P>::R *__restrict__ r, typename Types<P>::R *__restrict__ m,
+    const Scalars *__restrict__ sc, const int32_t *__restrict__ seq_par,
+    typename Types<P>::V *__restrict__ x, typename Types<P>::R *__restrict__ s, Kids<P> kd)
 {
     using R = typename Types<P>::R;
     using C = typename Types<P>::C;
@@ -1132,21 +1269,32 @@ __global__ __launch_bounds__(kShallowThreads) void k_shallow(
         dneg = (C)sc->dneg;
     }
     const R w = (R)sc->w;
+    const int32_t j = base + (int32_t)threadIdx.x;
+    const bool own = j < sp.lo[sp.levels];
+    int lvl = 0;
+    for (int l = 1; l < sp.levels; ++l)
+        if (j >= sp.lo[l]) lvl = l;
+    // the deepest level reads slots unless it has no decision points below
+    // it (then every child count is zero and the child loads are unused)
+    const bool slots = lvl == sp.levels - 1 && sp.kind[lvl] != 2;
+    FastLoads<P, kFastKids> L;
+    if (own) {
+        if (slots)
+            fast_load<P, VAR, kFastKids, kSlotsRead>(j, inf_first, child_ptr, child_idx, g, b, r,
+                                                     m, kd, L);
+        else
+            fast_load<P, VAR, kFastKids, 0>(j, inf_first, child_ptr, child_idx, g, b, r, m, kd,
+                                            L);
+    }
     for (int l = sp.levels - 1; l >= 0; --l) {
-        const bool deepest = l == sp.levels - 1;
-        for (int32_t j = sp.lo[l] + (int32_t)threadIdx.x; j < sp.lo[l + 1]; j += kShallowThreads) {
-            C V;
-            if (sp.kind[l] == 2)
-                V = up_infoset_fast<P, VAR, 0, 0, false>(j, inf_first, child_ptr, child_idx, g, usign,
-                                                         vinf, b, r, m, dpos, dneg, kd);
-            else if (!deepest)
-                V = up_infoset_fast<P, VAR, kFastKids, 0, false>(j, inf_first, child_ptr, child_idx,
-                                                                 g, usign, lvb, b, r, m, dpos,
-                                                                 dneg, kd);
-            else
-                V = up_infoset_fast<P, VAR, kFastKids, kSlotsRead, false>(
-                    j, inf_first, child_ptr, child_idx, g, usign, vinf, b, r, m, dpos, dneg, kd);
-            lvb[j] = V;
+        if (own && lvl == l) {
+            if (l < sp.levels - 1) {
+#pragma unroll
+                for (int k = 0; k < kFastActs; ++k)
+#pragma unroll
+                    for (int i = 0; i < kFastKids; ++i) L.cv[k][i] = lvb[L.cid[k][i]];
+            }
+            lvb[j] = fast_apply<P, VAR, kFastKids>(L, usign, b, r, m, dpos, dneg);
             if (l == 0) down_infoset<P>(j, inf_first, seq_par, b, x, s, w, 1, true);
         }
         __syncthreads();
@@ -1676,9 +1824,9 @@ hipError_t shallow_t(const DevPlayer &p, double usign, const Scalars *sc, hipStr
     if (p.shallow.levels <= 0) return hipSuccess;
     hipLaunchKernelGGL((k_shallow<P, VAR>), dim3(1), dim3(kShallowThreads), 0, st, p.shallow,
                        p.inf_first, p.child_ptr, p.child_idx, (const typename T::V *)p.g,
-                       (typename T::C)usign, (typename T::C *)p.vinf, (typename T::V *)p.b,
-                       (typename T::R *)p.r, (typename T::R *)p.m, sc, p.seq_par,
-                       (typename T::V *)p.x, (typename T::R *)p.s, kids<P>(p));
+                       (typename T::C)usign, (typename T::V *)p.b, (typename T::R *)p.r,
+                       (typename T::R *)p.m, sc, p.seq_par, (typename T::V *)p.x,
+                       (typename T::R *)p.s, kids<P>(p));
     return hipGetLastError();
 }
 
