@@ -52,6 +52,13 @@ struct PlayerPlan {
     int32_t top_levels = 0, n_roots = 0;
     std::vector<int32_t> top_off;     // [top_levels*(n_roots+1)]
     std::vector<int32_t> top_list;    // decision points of the shallow levels by level, then root
+    // levels fuse_lo..fuse_hi in one launch (k_fuse) when fuse_hi > fuse_lo:
+    // block b takes the decision points fuse_list[fuse_off[b*(D+1)+l] ..
+    // fuse_off[b*(D+1)+l+1]) of level fuse_lo + l (D = fuse_hi - fuse_lo + 1),
+    // whole subtrees below a set of level-fuse_lo decision points
+    int32_t fuse_lo = 0, fuse_hi = -1, fuse_blocks = 0;
+    std::vector<int32_t> fuse_off;    // [fuse_blocks*(D+1)]
+    std::vector<int32_t> fuse_list;   // decision points of the fused levels by block, then level
 };
 
 // CSR -> CSR of the transpose, every output row in ascending input-row order.
@@ -140,6 +147,7 @@ struct Capacity {
     int64_t t_up[2] = {0, 0}, t_down[2] = {0, 0}, t_seq[2] = {0, 0};  // range blocks
     int64_t t_dall[2] = {0, 0};  // range blocks of the one-launch top-down pass
     int64_t top_off[2] = {0, 0}, top_list[2] = {0, 0};
+    int64_t fuse_off[2] = {0, 0}, fuse_list[2] = {0, 0};
 };
 // Exact capacity of one game alone (the single-game solver).
 Capacity lone_capacity(const HostGame &hg, int items_csr, int rows_csr, int items_csc,

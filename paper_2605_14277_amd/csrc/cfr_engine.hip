@@ -43,6 +43,110 @@ std::string hip_msg(const char *what, hipError_t e)
 
 namespace {
 
+// The fused levels of a lone game (k_fuse): from the first level below the
+// shallow ones (the levels the one-block pass would take; level 1 at the
+// earliest, since level 0 also does its top-down step) down while every
+// level is on the fast path, the deepest holds at most kFuseDeepMax
+// decision points and each subtree below one decision point of the first
+// level holds at most kFuseThreads of them.  Blocks take consecutive such
+// subtrees while they hold at most kFuseThreads decision points.
+void plan_fuse(PlayerPlan &pl, const std::vector<int32_t> &inf_par,
+               const std::vector<int32_t> &seq_new_inf)
+{
+    pl.fuse_lo = 0;
+    pl.fuse_hi = -1;
+    pl.fuse_blocks = 0;
+    pl.fuse_off.clear();
+    pl.fuse_list.clear();
+    const int32_t L = pl.n_levels;
+    int32_t S = 0;
+    while (S < L && S < kShallowLevels && pl.lvl_kind[S] != 0 && pl.lvl_inf[S + 1] <= kShallowMax)
+        ++S;
+    if (S < 2) S = 0;
+    const int32_t T0 = std::max<int32_t>(S, 1);
+    if (T0 + 1 >= L || pl.lvl_kind[T0] == 0) return;
+    const int32_t k0 = pl.lvl_inf[T0], nA = pl.lvl_inf[T0 + 1] - k0;
+    // subtree (index of its level-T0 decision point) of every decision point
+    // at level T0 and below; parents come before children in level order
+    std::vector<int32_t> anc((size_t)pl.n_inf, -1);
+    for (int32_t k = k0; k < pl.n_inf; ++k)
+        anc[k] = k < k0 + nA ? k - k0 : anc[seq_new_inf[inf_par[k]]];
+    std::vector<int32_t> sub((size_t)nA, 1), next;
+    int32_t T1 = T0;
+    for (int32_t l = T0 + 1; l < L && l - T0 < kFuseLevels; ++l) {
+        if (pl.lvl_kind[l] == 0 || pl.lvl_inf[l + 1] - pl.lvl_inf[l] > kFuseDeepMax) break;
+        next = sub;
+        for (int32_t k = pl.lvl_inf[l]; k < pl.lvl_inf[l + 1]; ++k) next[anc[k]]++;
+        if (*std::max_element(next.begin(), next.end()) > kFuseThreads) break;
+        sub.swap(next);
+        T1 = l;
+    }
+    if (T1 == T0) return;
+    const int32_t D = T1 - T0 + 1;
+    std::vector<int32_t> blk((size_t)nA);
+    int32_t nb = 0, fill = 0;
+    for (int32_t a = 0; a < nA; ++a) {
+        if (fill + sub[a] > kFuseThreads) {
+            ++nb;
+            fill = 0;
+        }
+        blk[a] = nb;
+        fill += sub[a];
+    }
+    ++nb;
+    std::vector<int32_t> cnt((size_t)nb * D, 0);
+    for (int32_t l = T0; l <= T1; ++l)
+        for (int32_t k = pl.lvl_inf[l]; k < pl.lvl_inf[l + 1]; ++k)
+            cnt[(size_t)blk[anc[k]] * D + (l - T0)]++;
+    pl.fuse_off.assign((size_t)nb * (D + 1), 0);
+    std::vector<int32_t> at((size_t)nb * D);
+    int32_t pos = 0;
+    for (int32_t bk = 0; bk < nb; ++bk) {
+        for (int32_t l = 0; l < D; ++l) {
+            pl.fuse_off[(size_t)bk * (D + 1) + l] = pos;
+            at[(size_t)bk * D + l] = pos;
+            pos += cnt[(size_t)bk * D + l];
+        }
+        pl.fuse_off[(size_t)bk * (D + 1) + D] = pos;
+    }
+    pl.fuse_list.assign((size_t)pos, 0);
+    for (int32_t l = T0; l <= T1; ++l)
+        for (int32_t k = pl.lvl_inf[l]; k < pl.lvl_inf[l + 1]; ++k)
+            pl.fuse_list[(size_t)at[(size_t)blk[anc[k]] * D + (l - T0)]++] = k;
+    pl.fuse_lo = T0;
+    pl.fuse_hi = T1;
+    pl.fuse_blocks = nb;
+}
+
+// The fused plan's lists index only decision points of their own levels,
+// each once, and no block holds more than kFuseThreads (what k_fuse
+// indexes and launches).
+bool fuse_plan_ok(const PlayerPlan &pl)
+{
+    const int32_t D = pl.fuse_hi - pl.fuse_lo + 1;
+    if (pl.fuse_lo < 1 || D < 2 || D > kFuseLevels || pl.fuse_hi >= pl.n_levels ||
+        pl.fuse_blocks < 1 || pl.fuse_off.size() != (size_t)pl.fuse_blocks * (D + 1))
+        return false;
+    std::vector<uint8_t> seen((size_t)pl.n_inf, 0);
+    int32_t prev = 0;
+    for (int32_t bk = 0; bk < pl.fuse_blocks; ++bk) {
+        const int32_t *off = pl.fuse_off.data() + (size_t)bk * (D + 1);
+        if (off[0] != prev || off[D] - off[0] > kFuseThreads) return false;
+        for (int32_t l = 0; l < D; ++l) {
+            if (off[l + 1] < off[l]) return false;
+            for (int32_t i = off[l]; i < off[l + 1]; ++i) {
+                const int32_t k = pl.fuse_list[(size_t)i];
+                if (k < pl.lvl_inf[pl.fuse_lo + l] || k >= pl.lvl_inf[pl.fuse_lo + l + 1] || seen[k])
+                    return false;
+                seen[k] = 1;
+            }
+        }
+        prev = off[D];
+    }
+    return (size_t)prev == pl.fuse_list.size() &&
+           prev == pl.lvl_inf[pl.fuse_hi + 1] - pl.lvl_inf[pl.fuse_lo];
+}
+
 void plan_player(const cfr_player_desc &d, bool lone, PlayerPlan &pl)
 {
     const int32_t n_seq = (int32_t)d.n_seq, n_inf = (int32_t)d.n_inf;
@@ -144,6 +248,11 @@ void plan_player(const cfr_player_desc &d, bool lone, PlayerPlan &pl)
     pl.n_roots = n_levels > 0 ? pl.lvl_inf[1] - pl.lvl_inf[0] : 0;
     pl.top_off.clear();
     pl.top_list.clear();
+    pl.fuse_lo = 0;
+    pl.fuse_hi = -1;
+    pl.fuse_blocks = 0;
+    pl.fuse_off.clear();
+    pl.fuse_list.clear();
     if (n_levels == 0 || !lone) return;
     std::vector<int32_t> root((size_t)n_inf, 0);
     std::vector<int32_t> seq_new_inf((size_t)n_seq, 0);
@@ -172,6 +281,7 @@ void plan_player(const cfr_player_desc &d, bool lone, PlayerPlan &pl)
         pl.top_off.clear();
         pl.top_list.clear();
     }
+    if (pl.top_levels == 0) plan_fuse(pl, inf_par, seq_new_inf);
 }
 
 // Builds the internal row-sorted matrix of `rows` in level order.
@@ -327,6 +437,8 @@ Layout carve(Carver &k, const Capacity &c, int prec)
         d.cval = k.take(C * 4 * n);
         d.top_off = (int32_t *)k.take(4 * (size_t)std::max<int64_t>(c.top_off[p], 1));
         d.top_list = (int32_t *)k.take(4 * (size_t)std::max<int64_t>(c.top_list[p], 1));
+        d.fuse_off = (int32_t *)k.take(4 * (size_t)std::max<int64_t>(c.fuse_off[p], 1));
+        d.fuse_list = (int32_t *)k.take(4 * (size_t)std::max<int64_t>(c.fuse_list[p], 1));
     }
     for (int w = 0; w < 2; ++w) {
         L.ptr[w] = (int32_t *)k.take(4 * (size_t)std::max<int64_t>(c.seq[w], 1));
@@ -666,6 +778,8 @@ Capacity lone_capacity(const HostGame &hg, int items_csr, int rows_csr, int item
         c.t_dall[p] = pl.n_levels > 1 ? chunks(pl.n_seq - pl.lvl_seq[1]) : 0;
         c.top_off[p] = (int64_t)pl.top_off.size();
         c.top_list[p] = (int64_t)pl.top_list.size();
+        c.fuse_off[p] = (int64_t)pl.fuse_off.size();
+        c.fuse_list[p] = (int64_t)pl.fuse_list.size();
     }
     c.nnz = hg.nnz;
     // product tables large enough for every tiling the tuner may choose
@@ -700,6 +814,8 @@ void bound_tables(Capacity &c)
         c.t_dall[p] = c.seq[p] / kRangeBlock + c.slots + 1;
         c.top_off[p] = 0;
         c.top_list[p] = 0;
+        c.fuse_off[p] = 0;
+        c.fuse_list[p] = 0;
     }
 }
 
@@ -1313,6 +1429,22 @@ int Engine::add(const HostGame &hg, const GameImage &img, const GameParams &gp, 
                     for (int32_t lv = 0; lv < T; ++lv) d.shallow.kind[lv] = pl.lvl_kind[lv];
                 }
             }
+            // the fused levels below the shallow ones; the shallowest stores
+            // its values as the level above reads them, the deepest reads
+            // its children's values as the level below stores them
+            d.fuse = FusePlan();
+            if (pl.fuse_hi > pl.fuse_lo && pl.top_levels == 0 && up_pass == CFR_UP_DEFAULT &&
+                I == 0 && d.shallow.levels <= pl.fuse_lo && fuse_plan_ok(pl)) {
+                CHECK(h2d(d.fuse_off, pl.fuse_off.data(), pl.fuse_off.size(), ups));
+                CHECK(h2d(d.fuse_list, pl.fuse_list.data(), pl.fuse_list.size(), ups));
+                const int32_t T1 = pl.fuse_hi;
+                d.fuse.levels = pl.fuse_hi - pl.fuse_lo + 1;
+                d.fuse.lo = pl.fuse_lo;
+                d.fuse.blocks = pl.fuse_blocks;
+                d.fuse.top_slots = (s.lvl_slots[p][(size_t)pl.fuse_lo] & kSlotsWrite) ? 1 : 0;
+                d.fuse.deep_read = pl.lvl_kind[T1] == 2 ? 0
+                                   : (s.lvl_slots[p][(size_t)T1] & kSlotsRead) ? 1 : 2;
+            }
         }
     }
     // payoff matrix: row pointers at the row player's sequences, indices
@@ -1706,7 +1838,16 @@ hipError_t Engine::sweeps(const Tables &T, int p, double usign, hipStream_t s, b
     // top-down step); with CFR_UP_PAIRS a lone game runs pairs of adjacent
     // levels that fit the two-level launch as one launch each
     const bool pairs = lone && up_pass == CFR_UP_PAIRS && !slots.empty() && slots[0].live;
+    const bool fuse = lone && !top && up_pass == CFR_UP_DEFAULT && d.fuse.levels >= 2 &&
+                      d.fuse.lo >= low;
     for (int L = maxL - 1; L >= low;) {
+        if (fuse && L == d.fuse.lo + d.fuse.levels - 1) {
+            // the fused levels, one launch
+            if ((e = launch_fuse(prec, slots[0].gp.variant, d, usign, sc, s)) != hipSuccess)
+                return e;
+            L = d.fuse.lo - 1;
+            continue;
+        }
         const auto &lo = T.up_l[p][(size_t)L];
         if (pairs && L - 1 >= low && slots[0].lvl_pair[p][(size_t)L] && lo.size() == 1 &&
             T.up_l[p][(size_t)L - 1].size() == 1) {

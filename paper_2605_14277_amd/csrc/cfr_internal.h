@@ -78,6 +78,35 @@ struct ShallowPlan {
     uint8_t kind[kShallowLevels] = {};    // 1 fast, 2 fast without decision points below
 };
 
+// Levels lo .. lo+levels-1 below the shallow ones of a lone game in one
+// launch (k_fuse): each block takes whole subtrees below a group of level-lo
+// decision points, at most kFuseThreads decision points in all (one per
+// thread), every level on the fast path.  Inside a block the levels pass
+// their values through vinf, separated by block barriers; the shallowest
+// writes its values where the level above reads them, the deepest reads its
+// children's values as its own launch would.  Only small levels are fused
+// (the deepest at most kFuseDeepMax decision points): larger ones are bound
+// by their bytes, where a launch over the whole level keeps more waves in
+// flight.  Blocks of 256 (several per CU) and a deepest level of at most
+// 65536 decision points measured best on the medium and large games, against
+// blocks of 128, 512 or 1024 and limits of 16384 to 131072.
+#ifndef CFR_FUSE_THREADS
+#define CFR_FUSE_THREADS 256
+#endif
+#ifndef CFR_FUSE_DEEP_MAX
+#define CFR_FUSE_DEEP_MAX 65536
+#endif
+constexpr int kFuseThreads = CFR_FUSE_THREADS;
+constexpr int kFuseLevels = 4;
+constexpr int32_t kFuseDeepMax = CFR_FUSE_DEEP_MAX;
+struct FusePlan {
+    int32_t levels = 0;     // 0: not used
+    int32_t lo = 0;         // shallowest fused level
+    int32_t blocks = 0;
+    int32_t top_slots = 0;  // the shallowest level writes value slots
+    int32_t deep_read = 0;  // deepest level: 0 no children, 1 reads slots, 2 reads vinf
+};
+
 struct DevPlayer {
     int32_t *inf_first = nullptr;  // [decision points + sentinel] first sequence of each
     int32_t *seq_par = nullptr;    // [sequences] parent sequence of each sequence's decision point
@@ -111,6 +140,9 @@ struct DevPlayer {
     int32_t *top_list = nullptr;   // decision points grouped by level, then root
     int top_fast = 0;              // every level in k_top is a fast level
     ShallowPlan shallow;           // shallow levels of a lone game in one block (k_shallow)
+    FusePlan fuse;                 // fused levels of a lone game (k_fuse)
+    int32_t *fuse_off = nullptr;   // [blocks*(levels+1)] list offsets by block, then level
+    int32_t *fuse_list = nullptr;  // decision points of the fused levels by block, then level
 };
 
 // Kernel launchers (cfr_kernels.hip).  All enqueue on `st` and return the
@@ -165,6 +197,9 @@ hipError_t launch_top(int prec, int variant, const DevPlayer &p, double usign, i
                       const Scalars *sc, hipStream_t st);
 // ObserveUtility of the shallow levels p.shallow of a lone game (slot 0),
 // deepest first, one block; level 0 also does its top-down step.
+// The fused levels of p.fuse (k_fuse), one block per group of subtrees.
+hipError_t launch_fuse(int prec, int variant, const DevPlayer &p, double usign,
+                       const Scalars *sc, hipStream_t st);
 hipError_t launch_shallow(int prec, int variant, const DevPlayer &p, double usign,
                           const Scalars *sc, hipStream_t st);
 // xbar = s / W per game (x where W = 0), 1 at each game's empty sequence.

@@ -1301,6 +1301,75 @@ __global__ __launch_bounds__(kShallowThreads) void k_shallow(
     }
 }
 
+// Levels lo .. lo+D-1 of a lone game (below its shallow levels) in one
+// launch.  Block b takes the decision points fuse_list[off[l] .. off[l+1])
+// of level lo+l (off = fuse_off + b*(D+1)): whole subtrees below some of
+// level lo's decision points, so every child a block's decision point reads
+// is the block's own or below the fused levels.  Each thread owns one of
+// them and issues all of its loads before any level is computed (the
+// deepest level also its children's values: from value slots, or by child
+// id from vinf, both written by the launch of the level below).  The levels
+// are then computed deepest first; each stores its values in vinf and a
+// block barrier passes them to the level above, except the shallowest,
+// which stores them where its parents' level reads them (slot or vinf).
+// The arithmetic is that of a launch per level, bit for bit.
+template <int P, int VAR>
+__global__ __launch_bounds__(kFuseThreads) void k_fuse(
+    FusePlan fp, const int32_t *__restrict__ fuse_off, const int32_t *__restrict__ fuse_list,
+    const int32_t *__restrict__ inf_first, const int32_t *__restrict__ child_ptr,
+    const int32_t *__restrict__ child_idx, const typename Types<P>::V *__restrict__ g,
+    typename Types<P>::C usign, typename Types<P>::C *vinf, typename Types<P>::V *__restrict__ b,
+    typename Types<P>::R *__restrict__ r, typename Types<P>::R *__restrict__ m,
+    const Scalars *__restrict__ sc, Kids<P> kd)
+{
+    using C = typename Types<P>::C;
+    const int D = fp.levels;
+    const int32_t *off = fuse_off + (size_t)blockIdx.x * (size_t)(D + 1);
+    C dpos = 1, dneg = 1;
+    if (VAR == CFR_DCFR) {
+        dpos = (C)sc->dpos;
+        dneg = (C)sc->dneg;
+    }
+    const int32_t pos = off[0] + (int32_t)threadIdx.x;
+    const bool own = pos < off[D];
+    int lvl = 0;
+    for (int l = 1; l < D; ++l)
+        if (pos >= off[l]) lvl = l;
+    const bool deepest = lvl == D - 1;
+    FastLoads<P, kFastKids> L;
+    int32_t j = 0, cs = -1;
+    if (own) {
+        j = fuse_list[pos];
+        if (deepest && fp.deep_read == 1)
+            fast_load<P, VAR, kFastKids, kSlotsRead>(j, inf_first, child_ptr, child_idx, g, b, r,
+                                                     m, kd, L);
+        else
+            fast_load<P, VAR, kFastKids, 0>(j, inf_first, child_ptr, child_idx, g, b, r, m, kd,
+                                            L);
+        if (deepest && fp.deep_read == 2) {
+#pragma unroll
+            for (int k = 0; k < kFastActs; ++k)
+#pragma unroll
+                for (int i = 0; i < kFastKids; ++i) L.cv[k][i] = vinf[L.cid[k][i]];
+        }
+        if (lvl == 0 && fp.top_slots) cs = kd.cslot[j];
+    }
+    for (int l = D - 1; l >= 0; --l) {
+        if (own && lvl == l) {
+            if (l < D - 1) {
+                // the values the level below stored before the barrier
+#pragma unroll
+                for (int k = 0; k < kFastActs; ++k)
+#pragma unroll
+                    for (int i = 0; i < kFastKids; ++i) L.cv[k][i] = vinf[L.cid[k][i]];
+            }
+            const C V = fast_apply<P, VAR, kFastKids>(L, usign, b, r, m, dpos, dneg);
+            store_value(kd, l == 0 ? cs : -1, j, vinf, V);
+        }
+        if (l > 0) __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------------------
 // NextStrategy top-down pass for one level, fused with averaging
 // ---------------------------------------------------------------------------
@@ -1830,6 +1899,33 @@ hipError_t shallow_t(const DevPlayer &p, double usign, const Scalars *sc, hipStr
     return hipGetLastError();
 }
 
+template <int P, int VAR>
+hipError_t fuse_t(const DevPlayer &p, double usign, const Scalars *sc, hipStream_t st)
+{
+    using T = Types<P>;
+    if (p.fuse.levels < 2 || p.fuse.blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_fuse<P, VAR>), dim3((unsigned)p.fuse.blocks), dim3(kFuseThreads), 0, st,
+                       p.fuse, p.fuse_off, p.fuse_list, p.inf_first, p.child_ptr, p.child_idx,
+                       (const typename T::V *)p.g, (typename T::C)usign, (typename T::C *)p.vinf,
+                       (typename T::V *)p.b, (typename T::R *)p.r, (typename T::R *)p.m, sc,
+                       kids<P>(p));
+    return hipGetLastError();
+}
+
+template <int P>
+hipError_t fuse_dispatch(int variant, const DevPlayer &p, double usign, const Scalars *sc,
+                         hipStream_t st)
+{
+    switch (variant) {
+    case CFR_VANILLA: return fuse_t<P, CFR_VANILLA>(p, usign, sc, st);
+    case CFR_PLUS: return fuse_t<P, CFR_PLUS>(p, usign, sc, st);
+    case CFR_DCFR: return fuse_t<P, CFR_DCFR>(p, usign, sc, st);
+    case CFR_PCFR_PLUS: return fuse_t<P, CFR_PCFR_PLUS>(p, usign, sc, st);
+    case CFR_PCFR: return fuse_t<P, CFR_PCFR>(p, usign, sc, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 template <int P>
 hipError_t shallow_dispatch(int variant, const DevPlayer &p, double usign, const Scalars *sc,
                             hipStream_t st)
@@ -1996,6 +2092,12 @@ hipError_t launch_top(int prec, int variant, const DevPlayer &p, double usign, i
                       const Scalars *sc, hipStream_t st)
 {
     CFR_DISPATCH(prec, top_dispatch<P>(variant, p, usign, average, sc, st));
+}
+
+hipError_t launch_fuse(int prec, int variant, const DevPlayer &p, double usign,
+                       const Scalars *sc, hipStream_t st)
+{
+    CFR_DISPATCH(prec, fuse_dispatch<P>(variant, p, usign, sc, st));
 }
 
 hipError_t launch_shallow(int prec, int variant, const DevPlayer &p, double usign,
