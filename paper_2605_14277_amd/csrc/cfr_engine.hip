@@ -44,9 +44,9 @@ std::string hip_msg(const char *what, hipError_t e)
 namespace {
 
 // The fused levels of a lone game (k_fuse): from the first level below the
-// shallow ones (the levels the one-block pass would take; level 1 at the
-// earliest, since level 0 also does its top-down step) down while every
-// level is on the fast path, the deepest holds at most kFuseDeepMax
+// shallow ones (the levels the one-block pass would take; level 0 when
+// there are none, whose top-down step the launch then does too) down while
+// every level is on the fast path, the deepest holds at most kFuseDeepMax
 // decision points and each subtree below one decision point of the first
 // level holds at most kFuseThreads of them.  Blocks take consecutive such
 // subtrees while they hold at most kFuseThreads decision points.
@@ -63,7 +63,7 @@ void plan_fuse(PlayerPlan &pl, const std::vector<int32_t> &inf_par,
     while (S < L && S < kShallowLevels && pl.lvl_kind[S] != 0 && pl.lvl_inf[S + 1] <= kShallowMax)
         ++S;
     if (S < 2) S = 0;
-    const int32_t T0 = std::max<int32_t>(S, 1);
+    const int32_t T0 = S;
     if (T0 + 1 >= L || pl.lvl_kind[T0] == 0) return;
     const int32_t k0 = pl.lvl_inf[T0], nA = pl.lvl_inf[T0 + 1] - k0;
     // subtree (index of its level-T0 decision point) of every decision point
@@ -124,7 +124,7 @@ void plan_fuse(PlayerPlan &pl, const std::vector<int32_t> &inf_par,
 bool fuse_plan_ok(const PlayerPlan &pl)
 {
     const int32_t D = pl.fuse_hi - pl.fuse_lo + 1;
-    if (pl.fuse_lo < 1 || D < 2 || D > kFuseLevels || pl.fuse_hi >= pl.n_levels ||
+    if (pl.fuse_lo < 0 || D < 2 || D > kFuseLevels || pl.fuse_hi >= pl.n_levels ||
         pl.fuse_blocks < 1 || pl.fuse_off.size() != (size_t)pl.fuse_blocks * (D + 1))
         return false;
     std::vector<uint8_t> seen((size_t)pl.n_inf, 0);

@@ -83,8 +83,9 @@ struct ShallowPlan {
 // decision points, at most kFuseThreads decision points in all (one per
 // thread), every level on the fast path.  Inside a block the levels pass
 // their values through vinf, separated by block barriers; the shallowest
-// writes its values where the level above reads them, the deepest reads its
-// children's values as its own launch would.  Only small levels are fused
+// writes its values where the level above reads them (or, as level 0, does
+// its top-down step), the deepest reads its children's values as its own
+// launch would.  Only small levels are fused
 // (the deepest at most kFuseDeepMax decision points): larger ones are bound
 // by their bytes, where a launch over the whole level keeps more waves in
 // flight.  Blocks of 256 (several per CU) and a deepest level of at most

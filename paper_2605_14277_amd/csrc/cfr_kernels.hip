@@ -1311,17 +1311,21 @@ __global__ __launch_bounds__(kShallowThreads) void k_shallow(
 // id from vinf, both written by the launch of the level below).  The levels
 // are then computed deepest first; each stores its values in vinf and a
 // block barrier passes them to the level above, except the shallowest,
-// which stores them where its parents' level reads them (slot or vinf).
-// The arithmetic is that of a launch per level, bit for bit.
-template <int P, int VAR>
+// which stores them where its parents' level reads them (slot or vinf), or,
+// when it is level 0, also does its top-down step, as level 0's own launch
+// would (ROOT: the fused levels start at level 0).  The arithmetic is that
+// of a launch per level, bit for bit.
+template <int P, int VAR, bool ROOT>
 __global__ __launch_bounds__(kFuseThreads) void k_fuse(
     FusePlan fp, const int32_t *__restrict__ fuse_off, const int32_t *__restrict__ fuse_list,
     const int32_t *__restrict__ inf_first, const int32_t *__restrict__ child_ptr,
     const int32_t *__restrict__ child_idx, const typename Types<P>::V *__restrict__ g,
     typename Types<P>::C usign, typename Types<P>::C *vinf, typename Types<P>::V *__restrict__ b,
     typename Types<P>::R *__restrict__ r, typename Types<P>::R *__restrict__ m,
-    const Scalars *__restrict__ sc, Kids<P> kd)
+    const Scalars *__restrict__ sc, const int32_t *__restrict__ seq_par,
+    typename Types<P>::V *__restrict__ x, typename Types<P>::R *__restrict__ s, Kids<P> kd)
 {
+    using R = typename Types<P>::R;
     using C = typename Types<P>::C;
     const int D = fp.levels;
     const int32_t *off = fuse_off + (size_t)blockIdx.x * (size_t)(D + 1);
@@ -1365,6 +1369,8 @@ __global__ __launch_bounds__(kFuseThreads) void k_fuse(
             }
             const C V = fast_apply<P, VAR, kFastKids>(L, usign, b, r, m, dpos, dneg);
             store_value(kd, l == 0 ? cs : -1, j, vinf, V);
+            if (ROOT && l == 0)
+                down_infoset<P>(j, inf_first, seq_par, b, x, s, (R)sc->w, 1, true);
         }
         if (l > 0) __syncthreads();
     }
@@ -1904,11 +1910,12 @@ hipError_t fuse_t(const DevPlayer &p, double usign, const Scalars *sc, hipStream
 {
     using T = Types<P>;
     if (p.fuse.levels < 2 || p.fuse.blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_fuse<P, VAR>), dim3((unsigned)p.fuse.blocks), dim3(kFuseThreads), 0, st,
-                       p.fuse, p.fuse_off, p.fuse_list, p.inf_first, p.child_ptr, p.child_idx,
+    auto kern = p.fuse.lo == 0 ? k_fuse<P, VAR, true> : k_fuse<P, VAR, false>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)p.fuse.blocks), dim3(kFuseThreads), 0, st, p.fuse,
+                       p.fuse_off, p.fuse_list, p.inf_first, p.child_ptr, p.child_idx,
                        (const typename T::V *)p.g, (typename T::C)usign, (typename T::C *)p.vinf,
                        (typename T::V *)p.b, (typename T::R *)p.r, (typename T::R *)p.m, sc,
-                       kids<P>(p));
+                       p.seq_par, (typename T::V *)p.x, (typename T::R *)p.s, kids<P>(p));
     return hipGetLastError();
 }
 
