@@ -1888,7 +1888,10 @@ hipError_t Engine::sweeps(const Tables &T, int p, double usign, hipStream_t s, b
         }
         return launch_down_all(prec, T.dall_depth[p], T.dall[p], T.n_dall[p], &dr, d, 1, sc, s);
     }
-    for (int L = std::max(low, 1); L < maxL; ++L) {
+    // one launch per level below the levels whose top-down pass is done:
+    // k_top's, else level 0 (its bottom-up launch, the one-block shallow
+    // pass or a fused launch from level 0 does its step)
+    for (int L = top ? std::max(d.top_levels, 1) : 1; L < maxL; ++L) {
         const auto &dl = T.down_l[p][(size_t)L];
         if ((e = launch_down(prec, T.down[p] + dl.first, dl.second, d, 1, sc, s)) != hipSuccess)
             return e;

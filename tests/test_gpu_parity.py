@@ -408,6 +408,50 @@ def test_quads_fp64_equal_elementwise(cfr, oracle_mod, games, name):
     compare_fp64(last, orc, tol=1e-9, what=f"{name}-quads")
 
 
+def _no_shallow_p2():
+    """A public game whose player 2 has no one-block shallow pass (its top
+    two levels hold 192 + 1056 decision points), so its fused launch starts
+    at level 0 and covers its whole treeplex (three levels, 29 decision
+    points per subtree)."""
+    return gg.public_game(11, S=96, max_depth=6, branch_lo=2, branch_hi=3, p_stop=0.1,
+                          payoff_kind="showdown", name="no-shallow-p2")
+
+
+@pytest.mark.parametrize("name", ["cfg2", "no-shallow-p2"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_sweep_structures_equal(cfr, oracle_mod, name, precision):
+    """A lone game's default sweep runs the shallow levels in one block and
+    the small levels below them in fused launches (from level 0 when there
+    is no shallow pass, with level 0's top-down step), then the one-launch
+    top-down pass.  It equals the top-down pass one launch per level
+    (down_pass "levels": every level below level 0, whichever launch did
+    the bottom-up pass of the levels above) and the whole sweep one launch
+    per level (up_pass "levels" too) bit for bit, with and without the
+    first-touch order on A^T x; in FP64 it also equals the oracle."""
+    g = gg.cfg2() if name == "cfg2" else _no_shallow_p2()
+    perm = {"items": [16, 16], "rows": [256, 256], "vec": [2, 2], "perm": [0, 1], "xcd": [1, 1]}
+    for variant, mode, tiling in (("dcfr", "alternating", perm), ("pcfr+", "simultaneous", None),
+                                  ("cfr+", "alternating", None)):
+        out = []
+        for kw in ({}, {"down_pass": "levels"}, {"up_pass": "levels", "down_pass": "levels"}):
+            say(f"case: {name} {precision} {variant} {mode} tiling={tiling is not None} {kw}")
+            s = cfr.Solver(g, precision=precision, **kw)
+            if tiling is not None:
+                s.tiling = tiling
+            s.step(25, variant, mode)
+            out.append([s.strategy(p, k) for p in range(2) for k in ("current", "average")] +
+                       [s.regrets(p) for p in range(2)])
+            if not kw and precision == "fp64":
+                orc = oracle_mod.Oracle(g)
+                orc.step(25, variant, mode)
+                compare_fp64(s, orc, tol=1e-9, what=f"{name}-{variant}-{mode}")
+                orc.close()
+            s.close()
+        for other in out[1:]:
+            for a, c in zip(out[0], other):
+                assert np.array_equal(a, c), (name, variant, mode)
+
+
 @pytest.mark.parametrize("mode", ["alternating", "simultaneous"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_top_down_pass_writes_the_permuted_copy(cfr, precision, mode):
