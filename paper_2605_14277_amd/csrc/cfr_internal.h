@@ -91,6 +91,18 @@ struct ShallowPlan {
 // flight.  Blocks of 256 (several per CU) and a deepest level of at most
 // 65536 decision points measured best on the medium and large games, against
 // blocks of 128, 512 or 1024 and limits of 16384 to 131072.
+// A lone game's bottom-up (UP) and top-down (DOWN) launches over one direct
+// range: 1 deals each XCD a contiguous eighth of the range (neighbouring
+// sequences, which share parents and are read together by the next
+// product, stay in one L2), 0 keeps the blocks in order.  Both on measured
+// 0.3028 against 0.3100 ms per large-game iteration on one box and within
+// noise on another.
+#ifndef CFR_SWEEP_XCD_UP
+#define CFR_SWEEP_XCD_UP 1
+#endif
+#ifndef CFR_SWEEP_XCD_DOWN
+#define CFR_SWEEP_XCD_DOWN 1
+#endif
 #ifndef CFR_FUSE_THREADS
 #define CFR_FUSE_THREADS 256
 #endif

@@ -1017,11 +1017,21 @@ __device__ __forceinline__ void down_infoset(int32_t j, const int32_t *__restric
 // The range of one block of a sweep launch: the table's entry, or with a
 // direct range (hi > lo: one game's contiguous range, passed by value) the
 // block's share of it, which saves the dependent load of the entry.
+template <bool XCD>
 __device__ __forceinline__ RangeBlock block_range(const RangeBlock *__restrict__ tab,
                                                   const RangeBlock &dr)
 {
     if (dr.hi > dr.lo) {
-        const int32_t lo = dr.lo + (int32_t)blockIdx.x * kRangeBlock;
+        int32_t bid = (int32_t)blockIdx.x;
+        if (XCD) {
+            // workgroups are dealt round-robin over the 8 XCDs: each XCD
+            // takes a contiguous eighth of the range (the grid is a multiple
+            // of 8; blocks past the end get an empty range)
+            const int32_t n = (dr.hi - dr.lo + kRangeBlock - 1) / kRangeBlock;
+            const int32_t per = (n + 7) / 8;
+            bid = (int32_t)(blockIdx.x % 8) * per + (int32_t)(blockIdx.x / 8);
+        }
+        const int32_t lo = dr.lo + bid * kRangeBlock;
         return RangeBlock{lo, min(lo + kRangeBlock, dr.hi), dr.slot, dr.aux};
     }
     return tab[blockIdx.x];
@@ -1045,7 +1055,7 @@ __global__ __launch_bounds__(kThreads) void k_up(
 {
     using R = typename Types<P>::R;
     using C = typename Types<P>::C;
-    const RangeBlock rb = block_range(tab, dr);
+    const RangeBlock rb = block_range<CFR_SWEEP_XCD_UP>(tab, dr);
     const int32_t j = rb.lo + (int32_t)threadIdx.x;
     if (j >= rb.hi) return;
     const Scalars *gs = sc + rb.slot;
@@ -1425,7 +1435,7 @@ __global__ __launch_bounds__(kThreads) void k_down_all(const RangeBlock *__restr
 {
     using V = typename Types<P>::V;
     using R = typename Types<P>::R;
-    const RangeBlock rb = block_range(tab, dr);
+    const RangeBlock rb = block_range<CFR_SWEEP_XCD_DOWN>(tab, dr);
     const int32_t i = rb.lo + (int32_t)threadIdx.x;
     if (i >= rb.hi) return;
     const int32_t root = rb.aux;
@@ -1767,7 +1777,10 @@ hipError_t spmv_t(int items, int vec, const SpmvBlock *tab, int32_t n_tab, const
 // Blocks of a sweep launch: the table's entries, or those of the direct range.
 inline unsigned sweep_grid(int32_t n_tab, const RangeBlock &dr)
 {
-    if (dr.hi > dr.lo) return (unsigned)((dr.hi - dr.lo + kRangeBlock - 1) / kRangeBlock);
+    if (dr.hi > dr.lo) {
+        const unsigned n = (unsigned)((dr.hi - dr.lo + kRangeBlock - 1) / kRangeBlock);
+        return CFR_SWEEP_XCD_UP || CFR_SWEEP_XCD_DOWN ? (n + 7) / 8 * 8 : n;
+    }
     return (unsigned)n_tab;
 }
 
