@@ -194,6 +194,12 @@ struct Slot {
     std::vector<uint8_t> lvl_kind[2];
     std::vector<uint8_t> lvl_pair[2];
     std::vector<uint8_t> lvl_slots[2];   // per level: kSlotsWrite | kSlotsRead
+    // the game's own sweep structures while it iterates alone: levels in
+    // k_top (lone solver only), and its fused levels (checked lists, local
+    // decision points; fuse_hi < fuse_lo: none)
+    int32_t top_levels[2] = {0, 0};
+    int32_t fuse_lo[2] = {0, 0}, fuse_hi[2] = {-1, -1}, fuse_blocks[2] = {0, 0};
+    std::vector<int32_t> fuse_off[2], fuse_list[2];
     std::vector<int32_t> ptr[2];         // local row pointers of csr / csc (re-partitioning)
     int64_t qb[2] = {-1, -1};            // first quad of the game's stream-form-3 copy (-1: none)
     int64_t nq[2] = {0, 0};              // quads in it
@@ -364,6 +370,11 @@ struct Engine {
     bool tables_in_bounds(const Tables &T) const;
     int rebuild();  // iteration tables of the active games; drops the graph
     void drop_graph();
+    // The one-block shallow pass and the fused levels of the game in slot k
+    // when it is the only one iterating (k < 0: none); uploads its fused
+    // lists on stream s.
+    hipError_t single_plans(int k, hipStream_t s);
+    int single_slot = -1;  // the game those structures belong to
 
     // `gathered`: the permuted copy the product reads is already current
     // (written by the top-down pass just before), so no gather launch

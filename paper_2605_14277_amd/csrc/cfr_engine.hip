@@ -43,12 +43,13 @@ std::string hip_msg(const char *what, hipError_t e)
 
 namespace {
 
-// The fused levels of a lone game (k_fuse): from the first level below the
-// shallow ones (the levels the one-block pass would take; level 0 when
-// there are none, whose top-down step the launch then does too) down while
-// every level is on the fast path, the deepest holds at most kFuseDeepMax
-// decision points and each subtree below one decision point of the first
-// level holds at most kFuseThreads of them.  Blocks take consecutive such
+// The fused levels of a game iterating alone (k_fuse): from the first level
+// below the shallow ones (the levels the one-block pass would take; level 0
+// when there are none, whose top-down step the launch then does too) down
+// while every level is on the fast path and holds at most kFuseDeepMax
+// decision points (so the lists of any game fit kFuseListMax) and each
+// subtree below one decision point of the first level holds at most
+// kFuseThreads of them.  Blocks take consecutive such
 // subtrees while they hold at most kFuseThreads decision points.
 void plan_fuse(PlayerPlan &pl, const std::vector<int32_t> &inf_par,
                const std::vector<int32_t> &seq_new_inf)
@@ -64,7 +65,8 @@ void plan_fuse(PlayerPlan &pl, const std::vector<int32_t> &inf_par,
         ++S;
     if (S < 2) S = 0;
     const int32_t T0 = S;
-    if (T0 + 1 >= L || pl.lvl_kind[T0] == 0) return;
+    if (T0 + 1 >= L || pl.lvl_kind[T0] == 0 || pl.lvl_inf[T0 + 1] - pl.lvl_inf[T0] > kFuseDeepMax)
+        return;
     const int32_t k0 = pl.lvl_inf[T0], nA = pl.lvl_inf[T0 + 1] - k0;
     // subtree (index of its level-T0 decision point) of every decision point
     // at level T0 and below; parents come before children in level order
@@ -253,11 +255,16 @@ void plan_player(const cfr_player_desc &d, bool lone, PlayerPlan &pl)
     pl.fuse_blocks = 0;
     pl.fuse_off.clear();
     pl.fuse_list.clear();
-    if (n_levels == 0 || !lone) return;
-    std::vector<int32_t> root((size_t)n_inf, 0);
+    if (n_levels == 0) return;
     std::vector<int32_t> seq_new_inf((size_t)n_seq, 0);
     for (int32_t k = 0; k < n_inf; ++k)
         for (int32_t a = pl.inf_first[k]; a < pl.inf_first[k + 1]; ++a) seq_new_inf[a] = k;
+    if (!lone) {
+        // a batch's game: its fused levels serve while it iterates alone
+        plan_fuse(pl, inf_par, seq_new_inf);
+        return;
+    }
+    std::vector<int32_t> root((size_t)n_inf, 0);
     for (int32_t k = 0; k < n_inf; ++k)
         root[k] = inf_par[k] == 0 ? k : root[seq_new_inf[inf_par[k]]];
     const int32_t R = pl.n_roots;
@@ -814,8 +821,11 @@ void bound_tables(Capacity &c)
         c.t_dall[p] = c.seq[p] / kRangeBlock + c.slots + 1;
         c.top_off[p] = 0;
         c.top_list[p] = 0;
-        c.fuse_off[p] = 0;
-        c.fuse_list[p] = 0;
+        // the fused levels of the one game iterating alone: a game's list
+        // holds at most its own decision points and at most kFuseLevels
+        // levels of kFuseDeepMax, and a block holds one of them at least
+        c.fuse_list[p] = std::min<int64_t>(kFuseListMax, c.inf[p]);
+        c.fuse_off[p] = (int64_t)(kFuseLevels + 1) * c.fuse_list[p];
     }
 }
 
@@ -1410,41 +1420,22 @@ int Engine::add(const HostGame &hg, const GameImage &img, const GameParams &gp, 
             d.n_roots = pl.n_roots;
             d.top_fast = 1;
             for (int32_t lv = 0; lv < pl.top_levels; ++lv) d.top_fast &= pl.lvl_kind[lv] != 0;
-            // the shallow levels in one block: from the root down while they
-            // are small and on the fast path (two levels at least, or nothing
-            // is gained), the deepest of them reading value slots unless it
-            // is the game's last level.  The fast path's unused lanes read
-            // child_idx[0], the game's first decision point, which the block
-            // holds in LDS only when the game starts the index space.
-            d.shallow = ShallowPlan();
-            if (pl.top_levels == 0 && up_pass == CFR_UP_DEFAULT && I == 0) {
-                int32_t T = 0;
-                while (T < pl.n_levels && T < kShallowLevels && pl.lvl_kind[T] != 0 &&
-                       pl.lvl_inf[T + 1] <= kShallowMax)
-                    ++T;
-                if (T >= 2 && T < pl.n_levels && !(s.lvl_slots[p][T - 1] & kSlotsRead)) T = 0;
-                if (T >= 2) {
-                    d.shallow.levels = T;
-                    for (int32_t lv = 0; lv <= T; ++lv) d.shallow.lo[lv] = I + pl.lvl_inf[lv];
-                    for (int32_t lv = 0; lv < T; ++lv) d.shallow.kind[lv] = pl.lvl_kind[lv];
-                }
-            }
-            // the fused levels below the shallow ones; the shallowest stores
-            // its values as the level above reads them, the deepest reads
-            // its children's values as the level below stores them
-            d.fuse = FusePlan();
-            if (pl.fuse_hi > pl.fuse_lo && pl.top_levels == 0 && up_pass == CFR_UP_DEFAULT &&
-                I == 0 && d.shallow.levels <= pl.fuse_lo && fuse_plan_ok(pl)) {
-                CHECK(h2d(d.fuse_off, pl.fuse_off.data(), pl.fuse_off.size(), ups));
-                CHECK(h2d(d.fuse_list, pl.fuse_list.data(), pl.fuse_list.size(), ups));
-                const int32_t T1 = pl.fuse_hi;
-                d.fuse.levels = pl.fuse_hi - pl.fuse_lo + 1;
-                d.fuse.lo = pl.fuse_lo;
-                d.fuse.blocks = pl.fuse_blocks;
-                d.fuse.top_slots = (s.lvl_slots[p][(size_t)pl.fuse_lo] & kSlotsWrite) ? 1 : 0;
-                d.fuse.deep_read = pl.lvl_kind[T1] == 2 ? 0
-                                   : (s.lvl_slots[p][(size_t)T1] & kSlotsRead) ? 1 : 2;
-            }
+        }
+        // the game's own structures for when it iterates alone
+        s.top_levels[p] = lone ? pl.top_levels : 0;
+        s.fuse_lo[p] = 0;
+        s.fuse_hi[p] = -1;
+        s.fuse_blocks[p] = 0;
+        s.fuse_off[p].clear();
+        s.fuse_list[p].clear();
+        if (pl.fuse_hi > pl.fuse_lo && fuse_plan_ok(pl) &&
+            (int64_t)pl.fuse_off.size() <= cap.fuse_off[p] &&
+            (int64_t)pl.fuse_list.size() <= cap.fuse_list[p]) {
+            s.fuse_lo[p] = pl.fuse_lo;
+            s.fuse_hi[p] = pl.fuse_hi;
+            s.fuse_blocks[p] = pl.fuse_blocks;
+            s.fuse_off[p] = pl.fuse_off;
+            s.fuse_list[p] = pl.fuse_list;
         }
     }
     // payoff matrix: row pointers at the row player's sequences, indices
@@ -1516,6 +1507,8 @@ int Engine::add(const HostGame &hg, const GameImage &img, const GameParams &gp, 
         }
         CHECK(cp(sc + k, src, sizeof h));
     }
+    // a lone solver's game always iterates alone
+    if (lone) CHECK(single_plans(k, ups));
     if (async) {
         CHECK(hipEventCreateWithFlags(&s.up_ev, hipEventDisableTiming));
         CHECK(hipEventRecord(s.up_ev, ups));
@@ -1788,8 +1781,68 @@ int Engine::rebuild()
     hipError_t e = wait_uploads(act);
     if (e != hipSuccess) return device_error("admission copies", e);
     int rc = build_tables(it, tab_region[0], act);
-    if (rc) it.valid = false;
-    return rc;
+    if (rc) {
+        it.valid = false;
+        return rc;
+    }
+    // a batch whose only iterating game can use that game's own structures
+    if (!lone) {
+        e = single_plans(act.size() == 1 ? act[0] : -1, st);
+        if (e != hipSuccess) {
+            it.valid = false;
+            return device_error("fused-level lists", e);
+        }
+    }
+    return CFR_OK;
+}
+
+hipError_t Engine::single_plans(int k, hipStream_t s)
+{
+    single_slot = -1;
+    for (int p = 0; p < 2; ++p) {
+        dp[p].shallow = ShallowPlan();
+        dp[p].fuse = FusePlan();
+    }
+    if (k < 0 || up_pass != CFR_UP_DEFAULT) return hipSuccess;
+    const Slot &g = slots[(size_t)k];
+    single_slot = k;
+    for (int p = 0; p < 2; ++p) {
+        DevPlayer &d = dp[p];
+        if (g.top_levels[p] > 0) continue;  // k_top takes the shallow levels
+        const int32_t I = (int32_t)g.ib[p], L = g.n_levels[p];
+        const std::vector<int32_t> &li = g.lvl_inf[p];
+        const std::vector<uint8_t> &kind = g.lvl_kind[p];
+        // the shallow levels in one block: from the root down while they are
+        // small and on the fast path (two levels at least, or nothing is
+        // gained), the deepest of them reading value slots unless it is the
+        // game's last level
+        int32_t T = 0;
+        while (T < L && T < kShallowLevels && kind[(size_t)T] != 0 && li[(size_t)T + 1] <= kShallowMax)
+            ++T;
+        if (T >= 2 && T < L && !(g.lvl_slots[p][(size_t)T - 1] & kSlotsRead)) T = 0;
+        if (T >= 2) {
+            d.shallow.levels = T;
+            for (int32_t lv = 0; lv <= T; ++lv) d.shallow.lo[lv] = I + li[(size_t)lv];
+            for (int32_t lv = 0; lv < T; ++lv) d.shallow.kind[lv] = kind[(size_t)lv];
+        }
+        // the fused levels below them; the shallowest stores its values as
+        // the level above reads them, the deepest reads its children's
+        // values as the level below stores them
+        const int32_t T0 = g.fuse_lo[p], T1 = g.fuse_hi[p];
+        if (T1 > T0 && d.shallow.levels <= T0) {
+            hipError_t e = h2d(d.fuse_off, g.fuse_off[p].data(), g.fuse_off[p].size(), s);
+            if (e == hipSuccess) e = h2d(d.fuse_list, g.fuse_list[p].data(), g.fuse_list[p].size(), s);
+            if (e != hipSuccess) return e;
+            d.fuse.levels = T1 - T0 + 1;
+            d.fuse.lo = T0;
+            d.fuse.base = I;
+            d.fuse.blocks = g.fuse_blocks[p];
+            d.fuse.top_slots = (g.lvl_slots[p][(size_t)T0] & kSlotsWrite) ? 1 : 0;
+            d.fuse.deep_read = kind[(size_t)T1] == 2 ? 0
+                               : (g.lvl_slots[p][(size_t)T1] & kSlotsRead) ? 1 : 2;
+        }
+    }
+    return hipSuccess;
 }
 
 hipError_t Engine::spmv(const Tables &T, int which, const void *xin, void *yout, bool begin,
@@ -1832,18 +1885,22 @@ hipError_t Engine::sweeps(const Tables &T, int p, double usign, hipStream_t s, b
     const int maxL = (int)T.up_l[p].size();
     hipError_t e;
     const bool top = lone && d.top_levels > 0;
-    const int shallow = lone && !top ? d.shallow.levels : 0;
+    // the one-block shallow pass and the fused levels belong to the game
+    // iterating alone (set by single_plans), with its own scalars
+    const int one = single_slot;
+    const int shallow = !top && one >= 0 ? d.shallow.levels : 0;
     const int low = top ? d.top_levels : shallow;
     // ObserveUtility, deepest level first (level 0's launch also does its
     // top-down step); with CFR_UP_PAIRS a lone game runs pairs of adjacent
     // levels that fit the two-level launch as one launch each
     const bool pairs = lone && up_pass == CFR_UP_PAIRS && !slots.empty() && slots[0].live;
-    const bool fuse = lone && !top && up_pass == CFR_UP_DEFAULT && d.fuse.levels >= 2 &&
+    const bool fuse = !top && one >= 0 && up_pass == CFR_UP_DEFAULT && d.fuse.levels >= 2 &&
                       d.fuse.lo >= low;
     for (int L = maxL - 1; L >= low;) {
         if (fuse && L == d.fuse.lo + d.fuse.levels - 1) {
             // the fused levels, one launch
-            if ((e = launch_fuse(prec, slots[0].gp.variant, d, usign, sc, s)) != hipSuccess)
+            if ((e = launch_fuse(prec, slots[(size_t)one].gp.variant, d, usign, sc + one, s)) !=
+                hipSuccess)
                 return e;
             L = d.fuse.lo - 1;
             continue;
@@ -1874,12 +1931,13 @@ hipError_t Engine::sweeps(const Tables &T, int p, double usign, hipStream_t s, b
     } else if (shallow > 0) {
         // the shallow levels' bottom-up pass in one block (level 0 does its
         // top-down step there too)
-        if ((e = launch_shallow(prec, slots[0].gp.variant, d, usign, sc, s)) != hipSuccess)
+        if ((e = launch_shallow(prec, slots[(size_t)one].gp.variant, d, usign, sc + one, s)) !=
+            hipSuccess)
             return e;
     }
     if (!top && down_pass == CFR_DOWN_DEFAULT && T.dall_depth[p] <= kDownAllMaxDepth) {
         const RangeBlock &dr = T.dall_direct[p];
-        if (fold && lone && dr.hi > dr.lo) {
+        if (fold && dr.hi > dr.lo) {
             // from the game's empty sequence on, writing the permuted copy too
             *fold = true;
             const RangeBlock all{dr.aux, dr.hi, dr.slot, dr.aux};

@@ -62,7 +62,8 @@ struct SlotRef {
 };
 
 // Device arrays of one player, covering every slot (global indices).
-// The shallow levels 0 .. levels-1 of a lone game's bottom-up pass in one
+// The shallow levels 0 .. levels-1 of the bottom-up pass of a game
+// iterating alone (a lone solver's, or a batch's only active one) in one
 // block (k_shallow): each level's values stay in LDS for the level above,
 // and only the deepest of them reads its children's values from global
 // memory (their value slots).  Levels are taken from the root down while
@@ -78,8 +79,10 @@ struct ShallowPlan {
     uint8_t kind[kShallowLevels] = {};    // 1 fast, 2 fast without decision points below
 };
 
-// Levels lo .. lo+levels-1 below the shallow ones of a lone game in one
-// launch (k_fuse): each block takes whole subtrees below a group of level-lo
+// Levels lo .. lo+levels-1 below the shallow ones of a game iterating alone
+// (a lone solver's, or a batch's only active one) in one launch (k_fuse),
+// from lists of the game's local decision points (base added): each block
+// takes whole subtrees below a group of level-lo
 // decision points, at most kFuseThreads decision points in all (one per
 // thread), every level on the fast path.  Inside a block the levels pass
 // their values through vinf, separated by block barriers; the shallowest
@@ -111,10 +114,12 @@ struct ShallowPlan {
 #endif
 constexpr int kFuseThreads = CFR_FUSE_THREADS;
 constexpr int kFuseLevels = 4;
-constexpr int32_t kFuseDeepMax = CFR_FUSE_DEEP_MAX;
+constexpr int32_t kFuseDeepMax = CFR_FUSE_DEEP_MAX;  // decision points of any fused level at most
+constexpr int64_t kFuseListMax = (int64_t)kFuseLevels * kFuseDeepMax;
 struct FusePlan {
     int32_t levels = 0;     // 0: not used
     int32_t lo = 0;         // shallowest fused level
+    int32_t base = 0;       // the game's first decision point (the lists are local)
     int32_t blocks = 0;
     int32_t top_slots = 0;  // the shallowest level writes value slots
     int32_t deep_read = 0;  // deepest level: 0 no children, 1 reads slots, 2 reads vinf

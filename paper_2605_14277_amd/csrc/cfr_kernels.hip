@@ -18,8 +18,14 @@
 //   k_down      one treeplex level of NextStrategy's top-down pass, fused
 //               with the average-strategy accumulation of the strategy it
 //               overwrites: one thread per sequence.
+//   k_down_all  the whole top-down pass below level 0 in one launch: each
+//               sequence multiplies its parent chain from the root down.
 //   k_top       the shallow levels of a lone game, bottom-up then top-down,
 //               in one launch: one block per root decision point's subtree.
+//   k_shallow   the shallow levels of a game iterating alone, bottom-up, in
+//               one 1024-thread block, values passed between levels in LDS.
+//   k_fuse      the small levels below those in one launch, a block per
+//               group of whole subtrees from a host-built list.
 //   k_br        one level of the best-response max-sweep.
 //   k_normalize / k_root / k_dot   average normalisation and deterministic
 //               per-game scalar reductions.  The per-iteration scalars (t,
@@ -1244,7 +1250,7 @@ __global__ __launch_bounds__(kTopThreads) void k_top(
     }
 }
 
-// The shallow levels of a lone game in one block: the values of each level's
+// The shallow levels of a game iterating alone in one block: the values of each level's
 // decision points stay in LDS, where the level above reads them through its
 // child lists, so consecutive levels are separated by a block barrier
 // instead of a kernel boundary and a round trip through global memory.  The
@@ -1299,10 +1305,14 @@ __global__ __launch_bounds__(kShallowThreads) void k_shallow(
     for (int l = sp.levels - 1; l >= 0; --l) {
         if (own && lvl == l) {
             if (l < sp.levels - 1) {
+                // only the children that exist: the clamped ids of the
+                // others need not be in this block's LDS (the value of a
+                // missing child is never added)
 #pragma unroll
                 for (int k = 0; k < kFastActs; ++k)
 #pragma unroll
-                    for (int i = 0; i < kFastKids; ++i) L.cv[k][i] = lvb[L.cid[k][i]];
+                    for (int i = 0; i < kFastKids; ++i)
+                        L.cv[k][i] = i < L.cnt[k] ? lvb[L.cid[k][i]] : (C)0;
             }
             lvb[j] = fast_apply<P, VAR, kFastKids>(L, usign, b, r, m, dpos, dneg);
             if (l == 0) down_infoset<P>(j, inf_first, seq_par, b, x, s, w, 1, true);
@@ -1311,7 +1321,7 @@ __global__ __launch_bounds__(kShallowThreads) void k_shallow(
     }
 }
 
-// Levels lo .. lo+D-1 of a lone game (below its shallow levels) in one
+// Levels lo .. lo+D-1 of a game iterating alone (below its shallow levels) in one
 // launch.  Block b takes the decision points fuse_list[off[l] .. off[l+1])
 // of level lo+l (off = fuse_off + b*(D+1)): whole subtrees below some of
 // level lo's decision points, so every child a block's decision point reads
@@ -1353,7 +1363,7 @@ __global__ __launch_bounds__(kFuseThreads) void k_fuse(
     FastLoads<P, kFastKids> L;
     int32_t j = 0, cs = -1;
     if (own) {
-        j = fuse_list[pos];
+        j = fp.base + fuse_list[pos];
         if (deepest && fp.deep_read == 1)
             fast_load<P, VAR, kFastKids, kSlotsRead>(j, inf_first, child_ptr, child_idx, g, b, r,
                                                      m, kd, L);
