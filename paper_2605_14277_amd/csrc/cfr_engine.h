@@ -297,6 +297,9 @@ struct Engine {
     std::vector<int> ev_set;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    // runs launched directly since the graph was dropped: the first short
+    // run after the set of games changes is not captured
+    int direct_runs = 0;
     int64_t check_every = 0;  // 0: no checks (single-game solver)
     int64_t phase = 0;        // iterations since the last check
     int64_t checks = 0;       // checks done so far

@@ -1014,6 +1014,7 @@ void Engine::drop_graph()
     if (graph) (void)hipGraphDestroy(graph);
     gexec = nullptr;
     graph = nullptr;
+    direct_runs = 0;
 }
 
 void Engine::release()
@@ -2010,7 +2011,18 @@ int Engine::iterate(int64_t n)
         if (slots[(size_t)k].gp.variant < CFR_VANILLA)
             return fail(CFR_ESTATE, "a game has no regret minimiser set");
     hipError_t e = hipSuccess;
-    if (use_graph && !timing) {
+    // Capturing and instantiating the iteration's graph costs about as much
+    // host time as launching twenty iterations directly.  A batch's set of
+    // games often changes at every check, so the first short run after a
+    // change launches directly and the graph is built only when the same
+    // set runs again (or for a long run).  A lone solver's set never
+    // changes: it captures at once.
+    constexpr int64_t kGraphNow = 32;
+    if (use_graph && !timing && !gexec && !lone && n < kGraphNow && direct_runs == 0) {
+        ++direct_runs;
+        HostTimer timer(&host_s[kHostEnqueue], &host_n[kHostEnqueue]);
+        for (int64_t i = 0; i < n && e == hipSuccess; ++i) e = enqueue_iteration(st);
+    } else if (use_graph && !timing) {
         if (!gexec) {
             e = build_graph();
             if (e != hipSuccess) {
