@@ -423,3 +423,30 @@ def test_asynchronous_check_periods_equal_run(cfr, mix, precision):
     assert out[0][0] == out[1][0]
     for a, c in zip(out[0][1], out[1][1]):
         assert np.array_equal(a, c)
+
+
+@pytest.mark.parametrize("name", ["cfg2", "no-shallow-p2"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_acc64"])
+def test_game_left_alone_uses_its_own_sweep_structures(cfr, games, name, precision):
+    """A batch whose other games have finished iterates the game left alone
+    with that game's own one-block shallow levels and fused levels (from
+    its prepared plan, at a nonzero index base: a finished game sits before
+    it), after running a launch per level while both iterated; the result
+    equals the lone solver's bit for bit.  The second game's player 2 has
+    no shallow pass, so its fused launch starts at level 0."""
+    if name == "cfg2":
+        g = gg.cfg2()
+    else:
+        g = gg.public_game(11, S=96, max_depth=6, branch_lo=2, branch_hi=3, p_stop=0.1,
+                           payoff_kind="showdown", name="no-shallow-p2")
+    first = games["stops"]
+    b = make_batch(cfr, [first, g], max_games=2, precision=precision, check_every=10)
+    a = b.add(first, "cfr+", max_iterations=20)  # finishes after two checks
+    k = b.add(g, "dcfr", max_iterations=70)
+    while b.run(10):
+        pass
+    assert b.status(a)["iterations"] == 20 and b.status(k)["iterations"] == 70
+    solo = lone(cfr, g, "dcfr", "alternating", 70, precision)
+    assert_same(b, k, solo, f"{name} left alone ({precision})")
+    solo.close()
+    b.close()
