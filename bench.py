@@ -690,6 +690,12 @@ def bench_serving(args, torch):
     print(json.dumps(out), flush=True)
 
 
+# the size sweep: (terminals, depth, terminal range accepted) of the public
+# tree, and the signals per player
+SIZE_TREES = ((1e3, 6, 900, 1100), (1e4, 8, 9000, 11000), (1e5, 10, 96000, 106000))
+SIZE_SIGNALS = (8, 16, 32)
+
+
 def bench_sizes(args, torch):
     """Iterations/s against game size: the large game's generator at about
     1e3, 1e4 and 1e5 terminals with 8, 16 and 32 signals (5e4 to 1e8 payoff
