@@ -795,8 +795,8 @@ def main():
     ap.add_argument("--serve-lanes", type=int, default=2, choices=[1, 2],
                     help="serve: 2 = games of at most --small-nnz nonzeros in a batch of their "
                          "own on a stream of their own")
-    ap.add_argument("--small-nnz", type=float, default=5e6, help="serve: small-game lane limit")
-    ap.add_argument("--small-share", type=float, default=0.2,
+    ap.add_argument("--small-nnz", type=float, default=1e7, help="serve: small-game lane limit")
+    ap.add_argument("--small-share", type=float, default=0.25,
                     help="serve: share of the device budget for the small-game lane")
     ap.add_argument("--solo", type=int, default=1,
                     help="serve: games the main lane holds before admitting another beside "
