@@ -803,3 +803,48 @@ def test_shallow_block_large_game(cfr, large_game, precision):
         assert np.array_equal(a.regrets(p), b.regrets(p))
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_sweep_structures_on_irregular_games(cfr, seed):
+    """Random public games of irregular shape (early stops, uneven branching,
+    decision points with one action, from tiny to 1e6 nonzeros): the default
+    sweep of a lone game (one-block shallow levels, fused small levels, the
+    top-down pass writing the first-touch copy) equals the sweep one launch
+    per level bit for bit in FP64, and so does the same game left iterating
+    alone in a batch after a smaller game has finished."""
+    rng = np.random.default_rng(1000 + seed)
+    S = int(rng.choice([4, 12, 33, 70, 96]))
+    depth = int(rng.integers(3, 8))
+    lo = int(rng.integers(1, 3))
+    hi = int(rng.integers(lo, 5))
+    g = gg.public_game(2000 + seed, S=S, max_depth=depth, branch_lo=lo, branch_hi=hi,
+                       p_stop=float(rng.uniform(0.0, 0.4)), payoff_kind="showdown",
+                       name=f"irregular-{seed}")
+    say(f"case: irregular game {seed}: S={S} depth={depth} branching {lo}..{hi}, nnz={g.nnz}")
+    perm = {"items": [16, 16], "rows": [256, 256], "vec": [2, 2], "perm": [0, 1], "xcd": [1, 1]}
+    out = []
+    for kw in ({}, {"up_pass": "levels", "down_pass": "levels"}):
+        s = cfr.Solver(g, precision="fp64", **kw)
+        s.tiling = perm
+        s.step(15, "pcfr+", "alternating")
+        out.append([s.strategy(p, k) for p in range(2) for k in ("current", "average")] +
+                   [s.regrets(p) for p in range(2)])
+        s.close()
+    for a, c in zip(out[0], out[1]):
+        assert np.array_equal(a, c), seed
+    first = gg.public_game(3000 + seed, S=3, max_depth=3, branch_lo=2, branch_hi=2, p_stop=0.0,
+                           payoff_kind="showdown", name="first")
+    units = np.sum([cfr.Batch.game_size(x) for x in (first, g)], axis=0)
+    b = cfr.Batch([int(units[0]), int(units[1])], [int(units[2]), int(units[3])], int(units[4]),
+                  max_games=2, precision="fp64", check_every=5)
+    b.tiling = perm
+    b.add(first, "cfr+", max_iterations=5)
+    k = b.add(g, "pcfr+", max_iterations=15)
+    while b.run(5):
+        pass
+    assert b.status(k)["iterations"] == 15
+    got = [b.strategy(k, p, kind) for p in range(2) for kind in ("current", "average")]
+    for a, c in zip(got, out[1][:4]):
+        assert np.array_equal(a, c), seed
+    b.close()
