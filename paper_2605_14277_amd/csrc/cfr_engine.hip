@@ -1938,20 +1938,12 @@ hipError_t Engine::sweeps(const Tables &T, int p, double usign, hipStream_t s, b
     }
     if (!top && down_pass == CFR_DOWN_DEFAULT && T.dall_depth[p] <= kDownAllMaxDepth) {
         const RangeBlock &dr = T.dall_direct[p];
-        if (dr.hi > dr.lo) {
-            // one game: a thread per decision point of levels 1 and below
-            // (its actions share one parent chain); with the fold from level
-            // 0 on, writing the permuted copy of every sequence too
-            const Slot &g = slots[(size_t)dr.slot];
-            const int32_t I = (int32_t)g.ib[p];
-            const int32_t lv1 = I + g.lvl_inf[p][1], end = I + g.n_inf[p];
-            if (fold) {
-                *fold = true;
-                const RangeBlock all{I + g.lvl_inf[p][0], end, dr.slot, dr.aux};
-                return launch_down_dp(prec, T.dall_depth[p], all, d, 1, sc, s, 1, lv1);
-            }
-            const RangeBlock dps{lv1, end, dr.slot, dr.aux};
-            return launch_down_dp(prec, T.dall_depth[p], dps, d, 1, sc, s, 0, 0);
+        if (fold && dr.hi > dr.lo) {
+            // from the game's empty sequence on, writing the permuted copy too
+            *fold = true;
+            const RangeBlock all{dr.aux, dr.hi, dr.slot, dr.aux};
+            return launch_down_all(prec, T.dall_depth[p], T.dall[p], T.n_dall[p], &all, d, 1, sc,
+                                   s, 1, dr.lo);
         }
         return launch_down_all(prec, T.dall_depth[p], T.dall[p], T.n_dall[p], &dr, d, 1, sc, s);
     }

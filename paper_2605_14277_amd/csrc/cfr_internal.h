@@ -203,14 +203,6 @@ hipError_t launch_down(int prec, const RangeBlock *tab, int32_t n_tab, const Dev
 // Top-down pass over every level below level 0 in one launch: each sequence
 // of `tab` (aux = its game's empty sequence) multiplies the behavioural
 // strategies of its at most max_depth (<= kDownAllMaxDepth) ancestors.
-// The one-launch top-down pass of a game iterating alone over the decision
-// points of `dps` (aux: the game's empty sequence), one thread per decision
-// point; with `fold` (dps from level 0) it also writes the first-touch copy
-// p.xp[p.pos[σ]] = x[σ] of every sequence and averages only the decision
-// points from avg_lo on.
-hipError_t launch_down_dp(int prec, int max_depth, const RangeBlock &dps, const DevPlayer &p,
-                          int average, const Scalars *sc, hipStream_t st, int fold,
-                          int32_t avg_lo);
 // With `fold` (a direct range from one game's empty sequence on) it also
 // writes the first-touch copy p.xp[p.pos[i]] = x[i] and averages only the
 // sequences from avg_lo on.

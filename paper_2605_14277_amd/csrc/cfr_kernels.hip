@@ -1024,26 +1024,22 @@ __device__ __forceinline__ void down_infoset(int32_t j, const int32_t *__restric
 // direct range (hi > lo: one game's contiguous range, passed by value) the
 // block's share of it, which saves the dependent load of the entry.
 template <bool XCD>
-__device__ __forceinline__ RangeBlock direct_block(const RangeBlock &dr)
-{
-    int32_t bid = (int32_t)blockIdx.x;
-    if (XCD) {
-        // workgroups are dealt round-robin over the 8 XCDs: each XCD takes
-        // a contiguous eighth of the range (the grid is a multiple of 8;
-        // blocks past the end get an empty range)
-        const int32_t n = (dr.hi - dr.lo + kRangeBlock - 1) / kRangeBlock;
-        const int32_t per = (n + 7) / 8;
-        bid = (int32_t)(blockIdx.x % 8) * per + (int32_t)(blockIdx.x / 8);
-    }
-    const int32_t lo = dr.lo + bid * kRangeBlock;
-    return RangeBlock{lo, min(lo + kRangeBlock, dr.hi), dr.slot, dr.aux};
-}
-
-template <bool XCD>
 __device__ __forceinline__ RangeBlock block_range(const RangeBlock *__restrict__ tab,
                                                   const RangeBlock &dr)
 {
-    if (dr.hi > dr.lo) return direct_block<XCD>(dr);
+    if (dr.hi > dr.lo) {
+        int32_t bid = (int32_t)blockIdx.x;
+        if (XCD) {
+            // workgroups are dealt round-robin over the 8 XCDs: each XCD
+            // takes a contiguous eighth of the range (the grid is a multiple
+            // of 8; blocks past the end get an empty range)
+            const int32_t n = (dr.hi - dr.lo + kRangeBlock - 1) / kRangeBlock;
+            const int32_t per = (n + 7) / 8;
+            bid = (int32_t)(blockIdx.x % 8) * per + (int32_t)(blockIdx.x / 8);
+        }
+        const int32_t lo = dr.lo + bid * kRangeBlock;
+        return RangeBlock{lo, min(lo + kRangeBlock, dr.hi), dr.slot, dr.aux};
+    }
     return tab[blockIdx.x];
 }
 
@@ -1474,81 +1470,6 @@ __global__ __launch_bounds__(kThreads) void k_down_all(const RangeBlock *__restr
     }
     x[i] = xv;
     if (FOLD) xp[pos[i]] = xv;
-}
-
-// The one-launch top-down pass of a game iterating alone, one thread per
-// decision point of dr (levels 1 and below; with FOLD from level 0): the
-// parent chain is walked once for all of the decision point's sequences,
-// its realisation weight multiplied from the root down, and each action
-// takes x = x_parent * b, the same products in the same order as the
-// level-by-level pass.  With FOLD the launch also writes the first-touch
-// copy of every sequence (the range's first thread the empty sequence's),
-// and the decision points below avg_lo (whose x the bottom-up pass already
-// wrote) are not averaged again.
-template <int P, int MAXD, bool FOLD>
-__global__ __launch_bounds__(kThreads) void k_down_dp(
-    RangeBlock dr, const int32_t *__restrict__ inf_first, const int32_t *__restrict__ seq_par,
-    const typename Types<P>::V *__restrict__ b, typename Types<P>::V *__restrict__ x,
-    typename Types<P>::R *__restrict__ s, const Scalars *__restrict__ sc, int average,
-    const int32_t *__restrict__ pos, typename Types<P>::V *__restrict__ xp, int32_t avg_lo)
-{
-    using V = typename Types<P>::V;
-    using R = typename Types<P>::R;
-    const RangeBlock rb = direct_block<CFR_SWEEP_XCD_DOWN>(dr);
-    const int32_t root = dr.aux;
-    if (FOLD && rb.lo == dr.lo && threadIdx.x == 0) {
-        x[root] = (V)1;
-        xp[pos[root]] = (V)1;
-    }
-    const int32_t j = rb.lo + (int32_t)threadIdx.x;
-    if (j >= rb.hi) return;
-    const int32_t a0 = inf_first[j], a1 = inf_first[j + 1];
-    V chain[MAXD];
-    int d = 0;
-    int32_t q = seq_par[a0];
-#pragma unroll
-    for (int k = 0; k < MAXD; ++k) {
-        if (q != root) {
-            chain[k] = b[q];
-            q = seq_par[q];
-            d = k + 1;
-        }
-    }
-    V xpar = (V)1;
-#pragma unroll
-    for (int k = MAXD - 1; k >= 0; --k)
-        if (k < d) xpar = xpar * chain[k];
-    const R w = (R)sc[rb.slot].w;
-    const bool avg = average && (!FOLD || j >= avg_lo);
-    const int32_t n = a1 - a0;
-    if (n <= kFastActs) {
-        // all loads at once (clamped addresses), then the stores
-        V bv[kFastActs], xv[kFastActs];
-        R sv[kFastActs];
-#pragma unroll
-        for (int k = 0; k < kFastActs; ++k) {
-            const int32_t a = a0 + (k < n ? k : 0);
-            bv[k] = b[a];
-            xv[k] = x[a];
-            sv[k] = s[a];
-        }
-#pragma unroll
-        for (int k = 0; k < kFastActs; ++k) {
-            if (k < n) {
-                if (avg) s[a0 + k] = sv[k] + w * (R)xv[k];
-                const V xa = xpar * bv[k];
-                x[a0 + k] = xa;
-                if (FOLD) xp[pos[a0 + k]] = xa;
-            }
-        }
-        return;
-    }
-    for (int32_t a = a0; a < a1; ++a) {
-        if (avg) s[a] = s[a] + w * (R)x[a];
-        const V xa = xpar * b[a];
-        x[a] = xa;
-        if (FOLD) xp[pos[a]] = xa;
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -2227,41 +2148,6 @@ hipError_t launch_down_all(int prec, int max_depth, const RangeBlock *tab, int32
 {
     const RangeBlock dr = direct ? *direct : RangeBlock{0, 0, 0, 0};
     CFR_DISPATCH(prec, down_all_t<P>(max_depth, tab, n_tab, dr, p, average, sc, fold, avg_lo, st));
-}
-
-template <int P, int MAXD, bool FOLD>
-void down_dp_launch(const RangeBlock &dps, const DevPlayer &p, int average, const Scalars *sc,
-                    int32_t avg_lo, hipStream_t st)
-{
-    using T = Types<P>;
-    hipLaunchKernelGGL((k_down_dp<P, MAXD, FOLD>), dim3(sweep_grid(0, dps)), dim3(kThreads), 0, st,
-                       dps, p.inf_first, p.seq_par, (const typename T::V *)p.b,
-                       (typename T::V *)p.x, (typename T::R *)p.s, sc, average,
-                       FOLD ? p.pos : nullptr, FOLD ? (typename T::V *)p.xp : nullptr, avg_lo);
-}
-
-template <int P>
-hipError_t down_dp_t(int maxd, const RangeBlock &dps, const DevPlayer &p, int average,
-                     const Scalars *sc, int fold, int32_t avg_lo, hipStream_t st)
-{
-    if (dps.hi <= dps.lo) return hipSuccess;
-    if (fold && (avg_lo < dps.lo || avg_lo > dps.hi)) return hipErrorInvalidValue;
-    if (maxd <= 8) {
-        if (fold) down_dp_launch<P, 8, true>(dps, p, average, sc, avg_lo, st);
-        else down_dp_launch<P, 8, false>(dps, p, average, sc, avg_lo, st);
-    } else if (maxd <= kDownAllMaxDepth) {
-        if (fold) down_dp_launch<P, kDownAllMaxDepth, true>(dps, p, average, sc, avg_lo, st);
-        else down_dp_launch<P, kDownAllMaxDepth, false>(dps, p, average, sc, avg_lo, st);
-    } else {
-        return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_down_dp(int prec, int max_depth, const RangeBlock &dps, const DevPlayer &p,
-                          int average, const Scalars *sc, hipStream_t st, int fold, int32_t avg_lo)
-{
-    CFR_DISPATCH(prec, down_dp_t<P>(max_depth, dps, p, average, sc, fold, avg_lo, st));
 }
 
 hipError_t launch_normalize(int prec, const RangeBlock *tab, int32_t n_tab, const DevPlayer &p,
